@@ -1,0 +1,240 @@
+/*
+ * libfock: the Fock exchange operator V_X and the adaptively compressed
+ * exchange (ACE) operator on one AMD MI355X (gfx950).
+ *
+ * The operation (Jia, Wang & Lin, arXiv:1905.01348, Sec. 2, Eq. "applyVX",
+ * and the Fock-application algorithm of Sec. 3.2): for orbitals psi_j,
+ * j = 0..N-1, and targets phi_k,
+ *
+ *   (V_X phi_k)(r) = -(1/Omega) sum_j psi_j(r) IFFT_u[ K(G) FFT_u( conj(psi_j) phi_k ) ](r)
+ *
+ * with FFT_u / IFFT_u the unnormalised DFT pair on the cell's real-space grid,
+ * Omega the cell volume and K the Coulomb kernel 4 pi/|G|^2 (K(0) = 0) or the
+ * screened kernel 4 pi/|G|^2 (1 - exp(-|G|^2/(4 w^2))) (K(0) = pi/w^2), times
+ * the mixing fraction alpha (Sec. 2: V_X[P](r,r') = -alpha P(r,r') K(r-r')).
+ * Each (j, k) term is one Poisson-like solve; the paper counts N_e^2 of them
+ * per application (Sec. 2).
+ *
+ * ACE (cited in Sec. 1 as an alternative the paper does not use): from
+ * W = V_X Psi, M = Psi^H W (Hermitised), -M = L L^H (Cholesky, L lower with a
+ * real positive diagonal), xi = W L^{-H}; K_ACE phi = -xi (xi^H phi).  K_ACE
+ * equals V_X on span(Psi).  E_X = 1/2 Re tr(Psi^H V_X Psi) = 1/2 tr M.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * Layout: a block of orbitals is a device array of interleaved complex values
+ *   (re, im).  Column c (orbital c) starts at element base + c*ld, ld >= N_r,
+ *   and holds the grid vector with r = ix + n[0]*(iy + n[1]*iz), x fastest.
+ *   A contiguous torch tensor of shape (N, nz, ny, nx) has ld = N_r.
+ * Normalisation: orbitals are Euclidean-orthonormal grid vectors
+ *   (sum_r conj(psi_i) psi_j = delta_ij); the prefactor is -1/Omega.  The
+ *   library does not check orthonormality.
+ * Ownership: psi, phi and out are caller-owned device memory; the library
+ *   never frees them and keeps no reference past the stream-ordered end of
+ *   the call.  Outputs are overwritten, never accumulated into; out must not
+ *   alias psi or phi.  An fx_ace owns its factors until fx_ace_free.
+ * Streams: calls enqueue on `stream` (a hipStream_t; NULL means the default
+ *   (null) stream, as everywhere in HIP) and return without waiting, except fx_build_ace (one wait, to
+ *   read the Cholesky status) and fx_serve (runs to completion).  Workspace
+ *   is allocated on the first use of a shape, inside the context's HBM
+ *   budget; a later call with a shape already seen allocates nothing.
+ * Errors: every call returns an fx_status.  Argument errors are reported
+ *   synchronously before anything is enqueued; a text description of the
+ *   last error on the calling thread is available from fx_last_error().
+ *   HIP runtime failures map to FX_ERR_DEVICE.
+ * Threads: one fx_ctx per host thread, or external locking.
+ */
+#ifndef LIBFOCK_FOCK_H
+#define LIBFOCK_FOCK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum fx_status {
+  FX_OK = 0,
+  FX_ERR_INVALID = -1,     /* null pointer, bad size or leading dimension, aliasing */
+  FX_ERR_UNSUPPORTED = -2, /* grid edge not of the form 2^a 3^b in [2, 96], unknown enum */
+  FX_ERR_OOM = -3,         /* allocation failed or the HBM budget is exhausted */
+  FX_ERR_NOT_POSDEF = -4,  /* -M is not Hermitian positive definite (ACE build) */
+  FX_ERR_DEVICE = -5,      /* a HIP runtime call failed */
+  FX_ERR_BUSY = -6,        /* serving: request refused by admission control */
+  FX_ERR_CANCELLED = -7    /* serving: request cancelled before it ran */
+} fx_status;
+
+typedef enum fx_dtype {
+  FX_C128 = 0, /* complex double, interleaved */
+  FX_C64 = 1   /* complex float, interleaved */
+} fx_dtype;
+
+typedef enum fx_kernel_kind {
+  FX_COULOMB = 0, /* K = 4 pi/|G|^2, K(0) = 0 */
+  FX_HSE = 1      /* K = 4 pi/|G|^2 (1 - exp(-|G|^2/(4 w^2))), K(0) = pi/w^2 */
+} fx_kernel_kind;
+
+typedef enum fx_prec {
+  /* V_X pair path */
+  FX_PREC_FP64 = 0,       /* FP64 FFTs, FP64 accumulation */
+  FX_PREC_FP32 = 1,       /* FP32 FFTs, FP32 accumulation */
+  FX_PREC_FP32_ACC64 = 2, /* FP32 FFTs, FP64 accumulation over j */
+  /* ACE GEMMs */
+  FX_PREC_ACE_FP64 = 3,   /* FP64 matrix cores */
+  FX_PREC_ACE_FP32R = 4,  /* FP32 matrix cores + one FP64-combined residual step */
+  FX_PREC_ACE_BF16R = 5,  /* BF16 matrix cores + one FP64-combined residual step */
+  FX_PREC_ACE_FP32 = 6,   /* FP32 matrix cores, no residual step (ablation) */
+  FX_PREC_ACE_BF16 = 7    /* BF16 matrix cores, no residual step (ablation) */
+} fx_prec;
+
+/* Orthorhombic cell: grid n[0] x n[1] x n[2] (x, y, z), edges len[] in bohr. */
+typedef struct fx_cell {
+  int32_t n[3];
+  double len[3];
+} fx_cell;
+
+/* kind: fx_kernel_kind; omega: screening parameter (bohr^-1, FX_HSE only);
+ * scale: multiplies K (the mixing fraction alpha; 1 for the bare operator). */
+typedef struct fx_kernel {
+  int32_t kind;
+  double omega;
+  double scale;
+} fx_kernel;
+
+typedef struct fx_ctx fx_ctx;
+typedef struct fx_ace fx_ace;
+typedef struct fx_server fx_server;
+
+/* Open a context on HIP device `device`.  hbm_budget_bytes caps the memory the
+ * context may allocate (0 = 90% of the device's free memory).  *ctx receives
+ * the handle.  Errors: FX_ERR_INVALID (ctx NULL), FX_ERR_DEVICE. */
+fx_status fx_init(int device, size_t hbm_budget_bytes, fx_ctx** ctx);
+
+/* Wait for the context's work, free everything it owns, destroy it. */
+fx_status fx_finalize(fx_ctx* ctx);
+
+/* Text of the last error raised on the calling thread ("" if none). */
+const char* fx_last_error(void);
+
+/* Library version string. */
+const char* fx_version(void);
+
+/* Bytes currently allocated by the context, and the peak so far. */
+fx_status fx_memory(const fx_ctx* ctx, size_t* in_use, size_t* peak);
+
+/*
+ * out = V_X[psi] phi   (Eq. applyVX; one Poisson-like solve per pair (j,k)).
+ *
+ * psi:  device, n_psi orbitals, column stride ld_psi (elements), dtype in_dtype.
+ * phi:  device, n_phi targets, column stride ld_phi, dtype in_dtype; may be
+ *       the same pointer as psi (then phi_k = psi_k for k < n_phi).
+ * out:  device, n_phi columns, stride ld_out, dtype out_dtype; overwritten.
+ * prec: FX_PREC_FP64, FX_PREC_FP32 or FX_PREC_FP32_ACC64.  The j-sum runs in
+ *       ascending j in the accumulation precision, so results are bitwise
+ *       repeatable and independent of how the pairs are batched.
+ * ex_energy_dev: optional device double receiving E_X = 1/2 Re sum_k
+ *       <psi_k, out_k>; only allowed when phi == psi and ld_phi == ld_psi.
+ * Errors: FX_ERR_INVALID, FX_ERR_UNSUPPORTED, FX_ERR_OOM, FX_ERR_DEVICE.
+ */
+fx_status fx_apply_vx(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* kernel,
+                      const void* psi, int32_t n_psi, int64_t ld_psi,
+                      const void* phi, int32_t n_phi, int64_t ld_phi,
+                      void* out, int64_t ld_out,
+                      fx_dtype in_dtype, fx_dtype out_dtype, fx_prec prec,
+                      void* stream, double* ex_energy_dev);
+
+/*
+ * Build the ACE factors of V_X[psi]: W = V_X psi (with vx_prec), M = psi^H W in
+ * FP64, Hermitised, FP64 Cholesky -M = L L^H, L^{-1} in FP64, xi = W L^{-H}.
+ * The handle keeps xi (FP64) and, on first use, the split forms needed by
+ * ace_prec.  *ex_energy (host, nullable) receives 1/2 tr M.
+ * Waits on `stream` once (Cholesky status).  Errors: FX_ERR_INVALID,
+ * FX_ERR_UNSUPPORTED, FX_ERR_OOM, FX_ERR_NOT_POSDEF (-M not positive
+ * definite: e.g. a single constant orbital with the Coulomb kernel),
+ * FX_ERR_DEVICE.
+ */
+fx_status fx_build_ace(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* kernel,
+                       const void* psi, int32_t n_psi, int64_t ld_psi, fx_dtype in_dtype,
+                       fx_prec vx_prec, fx_prec ace_prec, void* stream,
+                       fx_ace** ace, double* ex_energy);
+
+/*
+ * out = K_ACE phi = -xi (xi^H phi).  prec: one of the FX_PREC_ACE_* values.
+ * phi: device, n_phi columns of N_r, stride ld_phi, dtype in_dtype.
+ * out: device, n_phi columns, stride ld_out, dtype out_dtype; overwritten.
+ * The first call with a new precision or a larger n_phi allocates; later
+ * calls do not.  Errors: FX_ERR_INVALID, FX_ERR_UNSUPPORTED, FX_ERR_OOM,
+ * FX_ERR_DEVICE.
+ */
+fx_status fx_apply_ace(fx_ctx* ctx, const fx_ace* ace,
+                       const void* phi, int32_t n_phi, int64_t ld_phi,
+                       void* out, int64_t ld_out,
+                       fx_dtype in_dtype, fx_dtype out_dtype, fx_prec prec, void* stream);
+
+/* Copy the FP64 factors out of a handle (device pointers, caller-owned):
+ * xi (N_r x N, ld = N_r, c128), L (N x N column-major, c128), M likewise.
+ * Any pointer may be NULL.  Synchronous. */
+fx_status fx_ace_export(const fx_ace* ace, void* xi, void* L, void* M);
+
+/* Number of orbitals and grid points of a handle. */
+fx_status fx_ace_shape(const fx_ace* ace, int32_t* n, int64_t* n_r);
+
+/* Free an ACE handle (waits for its work first). */
+fx_status fx_ace_free(fx_ace* ace);
+
+/*
+ * Serving: continuous batching of V_X / ACE requests over resident orbitals.
+ *
+ * fx_serve_create: max_slots requests may be in flight on the device at once,
+ *   spread over n_streams streams; same-grid requests that are waiting are
+ *   merged into one launch of up to max_batch_pairs pairs; admission keeps the
+ *   memory of resident trajectories plus in-flight requests within
+ *   hbm_budget_bytes (0 = the context budget).
+ * fx_serve_register: copy psi (N_r x n, dtype) into library-owned resident
+ *   memory as trajectory `traj`, and build its ACE factors (ace_prec).
+ * fx_serve: replay `n_reqs` requests whose arrival times (seconds from the
+ *   start) are t_arrival_s; request i computes V_X (op 0) or K_ACE (op 1)
+ *   applied to orbitals first..first+count-1 of its trajectory, written to
+ *   its `out` (device, ld_out, dtype of the trajectory).  Returns when every
+ *   request has finished; per_req_status/per_req_latency_ms (nullable host
+ *   arrays of n_reqs) receive each request's status and latency (completion
+ *   time minus arrival time), and report the aggregate.
+ */
+typedef struct fx_serve_cfg {
+  int32_t max_slots;
+  int32_t n_streams;
+  int32_t max_batch_pairs;
+  size_t hbm_budget_bytes;
+} fx_serve_cfg;
+
+typedef struct fx_request {
+  int32_t traj;
+  int32_t op; /* 0 = V_X, 1 = ACE */
+  int32_t first;
+  int32_t count;
+  double t_arrival_s;
+  void* out;
+  int64_t ld_out;
+} fx_request;
+
+typedef struct fx_serve_report {
+  double p50_ms, p99_ms, mean_ms, max_ms;
+  double req_per_s, pairs_per_s, busy_frac, wall_s;
+  int64_t n_done, n_rejected, n_batches;
+  size_t hbm_peak_bytes;
+} fx_serve_report;
+
+fx_status fx_serve_create(fx_ctx* ctx, const fx_serve_cfg* cfg, fx_server** srv);
+fx_status fx_serve_register(fx_server* srv, int32_t traj, const fx_cell* cell, const fx_kernel* kernel,
+                            const void* psi, int32_t n, int64_t ld, fx_dtype dtype,
+                            fx_prec vx_prec, fx_prec ace_prec);
+fx_status fx_serve(fx_server* srv, const fx_request* reqs, int32_t n_reqs,
+                   fx_status* per_req_status, double* per_req_latency_ms, fx_serve_report* report);
+fx_status fx_serve_destroy(fx_server* srv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LIBFOCK_FOCK_H */

@@ -1,0 +1,164 @@
+// Shared internals of libfock: status/error plumbing, the device context,
+// its HBM-budgeted allocator and per-stream workspaces.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/fock.h"
+#include "../../include/fock_prof.h"
+#include "../../include/fock_debug.h"
+
+namespace fx {
+
+// ---- error reporting (thread-local text, returned status) -----------------
+void set_error(const char* fmt, ...);
+void clear_error();
+
+#define FX_FAIL(code, ...)          \
+  do {                              \
+    ::fx::set_error(__VA_ARGS__);   \
+    return (code);                  \
+  } while (0)
+
+#define FX_HIP(call)                                                                 \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess) {                                                          \
+      ::fx::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), __FILE__, \
+                      __LINE__);                                                     \
+      return FX_ERR_DEVICE;                                                          \
+    }                                                                                \
+  } while (0)
+
+#define FX_TRY(expr)              \
+  do {                            \
+    fx_status s_ = (expr);        \
+    if (s_ != FX_OK) return s_;   \
+  } while (0)
+
+// Launch-error check after a kernel launch.
+#define FX_LAUNCH_CHECK() FX_HIP(hipGetLastError())
+
+// ---- complex scalars --------------------------------------------------------
+template <typename T>
+struct alignas(2 * sizeof(T)) cpx {
+  T x, y;
+};
+
+// ---- device buffers owned by a context --------------------------------------
+struct Ctx;
+
+// A growable device buffer charged to the context budget.
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+
+// Named scratch buffers for one stream of work (the context has one set, a
+// server has one set per in-flight slot).
+struct Workspace {
+  std::map<std::string, DevBuf> bufs;
+};
+
+// Cached per-grid constant tables (twiddles, fold maps, kernel tables).
+struct TableKey {
+  int n[3];
+  double len[3];
+  int kind;
+  double omega, scale;
+  int prec;  // 0 = fp64 tables, 1 = fp32 tables
+  bool operator<(const TableKey& o) const;
+};
+
+struct GridTables {
+  // per axis: twiddles w_n^t = exp(-2 pi i t/n), t < n, in the table precision
+  void* tw[3] = {nullptr, nullptr, nullptr};
+  // per axis: for each position of the digit-reversed spectrum, the folded
+  // frequency index |m| in [0, n/2]
+  int* fold[3] = {nullptr, nullptr, nullptr};
+  // K(G) * (-scale/Omega) on the folded grid (nx/2+1)*(ny/2+1)*(nz/2+1)
+  void* kfold = nullptr;
+  size_t bytes = 0;
+};
+
+// One timed launch: events recorded before and after it on its stream.
+struct ProfRec {
+  int id;
+  hipEvent_t a, b;
+};
+
+}  // namespace fx
+
+struct fx_ctx {
+  int device = 0;
+  size_t budget = 0;
+  size_t in_use = 0;
+  size_t peak = 0;
+  hipStream_t stream = nullptr;
+  int n_cu = 0;
+  std::recursive_mutex mu;
+  fx::Workspace ws;  // workspace of the context's own calls
+  std::map<fx::TableKey, fx::GridTables> tables;
+  // per-kernel timing (fx_prof_enable)
+  bool prof = false;
+  std::vector<fx::ProfRec> prof_recs;
+  std::vector<hipEvent_t> ev_pool;
+  int64_t prof_launches[FX_K_COUNT] = {0};
+  double prof_ms[FX_K_COUNT] = {0};
+};
+
+namespace fx {
+
+// Allocation charged to the context budget.  Returns FX_ERR_OOM when the
+// budget would be exceeded or hipMalloc fails.
+fx_status ctx_alloc(fx_ctx* ctx, size_t bytes, void** out);
+void ctx_free(fx_ctx* ctx, void* p, size_t bytes);
+
+// Return workspace buffer `name` with at least `bytes`, growing it if needed
+// (growth waits for the device before freeing the old buffer).
+fx_status ws_get(fx_ctx* ctx, Workspace* ws, const char* name, size_t bytes, void** out);
+void ws_release(fx_ctx* ctx, Workspace* ws);
+
+// Device tables for one grid/kernel/precision (built on the host in FP64).
+fx_status grid_tables(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* kern, int prec,
+                      const GridTables** out);
+
+// Plan of an FFT axis: n = R[0] * R[1] * ... (at most 4 radices from
+// {2,3,4,6,8,9,12,16}); DIF stages run in this order.
+struct AxisPlan {
+  int n;
+  int nst;
+  int R[4];
+};
+bool make_axis_plan(int n, AxisPlan* p);
+// Frequency index held at each position after the forward DIF stages.
+void plan_positions(const AxisPlan& p, std::vector<int>* freq_of_pos);
+
+// Host copies of the tables (FP64), used to upload and by the host check.
+struct HostTables {
+  AxisPlan plan[3];
+  std::vector<cpx<double>> tw[3];
+  std::vector<int> fold[3];
+  std::vector<double> kfold;
+};
+void host_tables(const fx_cell* cell, const fx_kernel* kern, HostTables* h);
+
+bool supported_edge(int n);
+fx_status check_cell(const fx_cell* cell);
+fx_status check_kernel(const fx_kernel* k);
+
+// Bracket a launch with events when timing is on (no-ops otherwise).
+fx_status prof_begin(fx_ctx* ctx, hipStream_t st, int id, int* slot);
+fx_status prof_end(fx_ctx* ctx, hipStream_t st, int slot);
+
+inline size_t dtype_size(fx_dtype d) { return d == FX_C128 ? 16 : 8; }
+
+}  // namespace fx

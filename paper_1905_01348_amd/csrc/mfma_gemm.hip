@@ -1,0 +1,483 @@
+// K_ACE phi = -xi (xi^H phi) on the matrix cores.
+//
+// Both projections are written as real GEMMs whose two operands are
+// contiguous along the reduction dimension ("TN"), on the interleaved
+// (re, im) real view of the complex arrays:
+//
+//   C = xi^H phi  : D (N x 2R) = A B^T, A row m = column m of xi (2 N_r reals),
+//                   B row 2n = phi_n, B row 2n+1 = (-i phi_n) = (im, -re) pairs;
+//                   Re C(m,n) = D(m, 2n), Im C(m,n) = D(m, 2n+1).  The reduction
+//                   (2 N_r long) is split across workgroups; split partial sums
+//                   are added in FP64 in a fixed order.
+//   y = -xi C     : D (N_r x 2R) = A B^T, A row r = row r of xi (2 N reals),
+//                   B row 2n = (Re C, -Im C) pairs, B row 2n+1 = (Im C, Re C);
+//                   y(r,n) = -(D(r,2n), D(r,2n+1)).
+//
+// Precision forms: every operand X is split as X_p = round(X) and
+// r_X = round(X - X_p) (FP32 or BF16), and with the residual step the GEMM
+// computes A_p B_p (main accumulator) and A_p r_B + r_A B_p (correction
+// accumulator), both in FP32 on the matrix cores, added in FP64 at the end.
+#include <algorithm>
+#include <cstdint>
+
+#include "fft.hpp"
+#include "mfma_gemm.hpp"
+#include "vx.hpp"
+
+namespace fx {
+
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// ---- rounding ---------------------------------------------------------------
+// float -> bfloat16, round to nearest even (NaN kept quiet)
+__device__ inline uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__device__ inline float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+template <typename S>
+struct Prec;
+template <>
+struct Prec<float> {
+  static constexpr int BK = 32;   // K elements per tile step (128 bytes per row)
+  static constexpr int PAD = 4;   // LDS row padding (elements)
+  __device__ static float round(double x) { return (float)x; }
+  __device__ static double widen(float s) { return (double)s; }
+};
+template <>
+struct Prec<uint16_t> {
+  static constexpr int BK = 64;
+  static constexpr int PAD = 8;
+  __device__ static uint16_t round(double x) { return f2bf((float)x); }
+  __device__ static double widen(uint16_t s) { return (double)bf2f(s); }
+};
+
+constexpr int KPAD = 64;  // reduction dims of split arrays are padded to this
+static int64_t roundk(int64_t k) { return (k + KPAD - 1) / KPAD * KPAD; }
+
+// (a, b) pairs -> (b, -a) on a 16-byte vector: multiplication by -i of the
+// complex values it holds.
+__device__ inline uint4 times_minus_i(uint4 v, int elem_bytes) {
+  if (elem_bytes == 4) {
+    return uint4{v.y, v.x ^ 0x80000000u, v.w, v.z ^ 0x80000000u};
+  }
+  // bf16: 4 pairs, each 32-bit word holds (lo = a, hi = b)
+  uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const uint32_t a = w[i] & 0xffffu, b = w[i] >> 16;
+    w[i] = b | ((a ^ 0x8000u) << 16);
+  }
+  return uint4{w[0], w[1], w[2], w[3]};
+}
+
+// ---------------------------------------------------------------------------
+// TN GEMM on matrix cores.  256 threads = 4 waves in a 2x2 arrangement, each
+// wave a 64x64 block of D made of 2x2 MFMA 32x32 tiles.  Workgroup tile
+// 128 x 128, K step BK.
+//   A: rows m (M of them), A[m*lda + k];  B: rows n (N of them), B[n*ldb + k].
+//   BDOUBLE: B holds N/2 source rows; LDS row 2c is source row c and row
+//            2c+1 is source row c times -i (see header comment).
+//   MODE 0: write FP64 partial sums, partial[(split*M + m)*N + n].
+//   MODE 1: write y(r=m, n/2) component n&1 = -alpha * D to a complex output.
+// ---------------------------------------------------------------------------
+constexpr int TBM = 128, TBN = 128;
+
+template <typename S, bool REFINE, bool BDOUBLE, int MODE>
+__global__ void __launch_bounds__(256) k_tn_mfma(int M, int N, int K, int kchunk, const S* __restrict__ Ap,
+                                                 const S* __restrict__ Ar, int64_t lda, const S* __restrict__ Bp,
+                                                 const S* __restrict__ Br, int64_t ldb, double* __restrict__ partial,
+                                                 void* __restrict__ out, int64_t ldo, int out_c64, double alpha,
+                                                 int tiles_m, int tiles_n) {
+  constexpr int BK = Prec<S>::BK;
+  constexpr int LDK = BK + Prec<S>::PAD;
+  constexpr int EPV = 16 / sizeof(S);  // elements per 16-byte vector
+  constexpr int VPR = BK / EPV;        // vectors per tile row (8)
+  constexpr int NT = REFINE ? 4 : 2;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  S* sm = reinterpret_cast<S*>(smem_raw);
+  S* sAp = sm;
+  S* sBp = sm + TBM * LDK;
+  S* sAr = sm + 2 * TBM * LDK;
+  S* sBr = sm + 3 * TBM * LDK;
+
+  // block -> (tile_m, tile_n, split); consecutive blocks on one XCD share
+  // the A row-tile: the hardware deals blocks to the 8 XCDs round-robin.
+  const int nblk = gridDim.x;
+  const int bid = blockIdx.x;
+  const int per_xcd = (nblk + 7) / 8;
+  int lid = (bid % 8) * per_xcd + bid / 8;
+  if (nblk % 8 != 0) lid = bid;  // keep the mapping a bijection
+  const int tn = lid % tiles_n;
+  const int rest = lid / tiles_n;
+  const int tm = rest % tiles_m;
+  const int split = rest / tiles_m;
+  const int m0 = tm * TBM, n0 = tn * TBN;
+  const int kbeg = split * kchunk;
+  const int kend = min(K, kbeg + kchunk);
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+
+  floatx16 acc[2][2], cor[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        acc[i][j][e] = 0.f;
+        cor[i][j][e] = 0.f;
+      }
+    }
+
+  // register staging of one K step: 4 vectors per thread per A tile; B tile
+  // rows: 128 (plain) or 64 source rows (BDOUBLE, 2 vectors per thread)
+  constexpr int BV = BDOUBLE ? 2 : 4;
+  uint4 ra[2][4], rb[2][BV];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int v = tid + 256 * u, row = v / VPR, c = v % VPR;
+      const int m = m0 + row;
+      uint4 z = {0, 0, 0, 0};
+      ra[0][u] = m < M ? *reinterpret_cast<const uint4*>(Ap + (int64_t)m * lda + k0 + c * EPV) : z;
+      if (REFINE) ra[1][u] = m < M ? *reinterpret_cast<const uint4*>(Ar + (int64_t)m * lda + k0 + c * EPV) : z;
+    }
+#pragma unroll
+    for (int u = 0; u < BV; ++u) {
+      const int v = tid + 256 * u, row = v / VPR, c = v % VPR;
+      const int n = BDOUBLE ? n0 / 2 + row : n0 + row;
+      const int nlim = BDOUBLE ? N / 2 : N;
+      uint4 z = {0, 0, 0, 0};
+      rb[0][u] = n < nlim ? *reinterpret_cast<const uint4*>(Bp + (int64_t)n * ldb + k0 + c * EPV) : z;
+      if (REFINE) rb[1][u] = n < nlim ? *reinterpret_cast<const uint4*>(Br + (int64_t)n * ldb + k0 + c * EPV) : z;
+    }
+  };
+  auto sstore = [&]() {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int v = tid + 256 * u, row = v / VPR, c = v % VPR;
+      *reinterpret_cast<uint4*>(sAp + row * LDK + c * EPV) = ra[0][u];
+      if (REFINE) *reinterpret_cast<uint4*>(sAr + row * LDK + c * EPV) = ra[1][u];
+    }
+#pragma unroll
+    for (int u = 0; u < BV; ++u) {
+      const int v = tid + 256 * u, row = v / VPR, c = v % VPR;
+      if (BDOUBLE) {
+        *reinterpret_cast<uint4*>(sBp + (2 * row) * LDK + c * EPV) = rb[0][u];
+        *reinterpret_cast<uint4*>(sBp + (2 * row + 1) * LDK + c * EPV) = times_minus_i(rb[0][u], sizeof(S));
+        if (REFINE) {
+          *reinterpret_cast<uint4*>(sBr + (2 * row) * LDK + c * EPV) = rb[1][u];
+          *reinterpret_cast<uint4*>(sBr + (2 * row + 1) * LDK + c * EPV) = times_minus_i(rb[1][u], sizeof(S));
+        }
+      } else {
+        *reinterpret_cast<uint4*>(sBp + row * LDK + c * EPV) = rb[0][u];
+        if (REFINE) *reinterpret_cast<uint4*>(sBr + row * LDK + c * EPV) = rb[1][u];
+      }
+    }
+  };
+
+  if (kbeg < kend) gload(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+    sstore();
+    __syncthreads();
+    if (k0 + BK < kend) gload(k0 + BK);
+    const int ar = wm * 64 + (lane & 31);
+    const int br = wn * 64 + (lane & 31);
+    if constexpr (sizeof(S) == 4) {
+#pragma unroll
+      for (int kk = 0; kk < BK / 2; ++kk) {
+        const int kc = kk * 2 + (lane >> 5);
+        float a[2], b[2], a2[2], b2[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          a[t] = reinterpret_cast<const float*>(sAp)[(ar + 32 * t) * LDK + kc];
+          b[t] = reinterpret_cast<const float*>(sBp)[(br + 32 * t) * LDK + kc];
+          if (REFINE) {
+            a2[t] = reinterpret_cast<const float*>(sAr)[(ar + 32 * t) * LDK + kc];
+            b2[t] = reinterpret_cast<const float*>(sBr)[(br + 32 * t) * LDK + kc];
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b[j], acc[i][j], 0, 0, 0);
+            if (REFINE) {
+              cor[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b2[j], cor[i][j], 0, 0, 0);
+              cor[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a2[i], b[j], cor[i][j], 0, 0, 0);
+            }
+          }
+      }
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < BK / 16; ++kk) {
+        const int kc = kk * 16 + (lane >> 5) * 8;
+        bf16x8 a[2], b[2], a2[2], b2[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          a[t] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(sAp + (ar + 32 * t) * LDK + kc));
+          b[t] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(sBp + (br + 32 * t) * LDK + kc));
+          if (REFINE) {
+            a2[t] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(sAr + (ar + 32 * t) * LDK + kc));
+            b2[t] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(sBr + (br + 32 * t) * LDK + kc));
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+            if (REFINE) {
+              cor[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b2[j], cor[i][j], 0, 0, 0);
+              cor[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2[i], b[j], cor[i][j], 0, 0, 0);
+            }
+          }
+      }
+    }
+    __syncthreads();
+  }
+
+  // epilogue: D tile element e of (i, j): row = i*32 + 8*(e/4) + 4*(lane/32) + e%4, col = j*32 + lane%32
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int n = n0 + wn * 64 + j * 32 + (lane & 31);
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int m = m0 + wm * 64 + i * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+        if (m >= M || n >= N) continue;
+        const double v = (double)acc[i][j][e] + (REFINE ? (double)cor[i][j][e] : 0.0);
+        if (MODE == 0) {
+          partial[((int64_t)split * M + m) * N + n] = v;
+        } else {
+          const int64_t idx = ((int64_t)(n >> 1) * ldo + m) * 2 + (n & 1);
+          if (out_c64)
+            reinterpret_cast<float*>(out)[idx] = (float)(-alpha * v);
+          else
+            reinterpret_cast<double*>(out)[idx] = -alpha * v;
+        }
+      }
+    }
+}
+
+// ---- split kernels ----------------------------------------------------------
+// xi (complex double, N_r x N, ld N_r) -> col form: row m = interleaved column m.
+template <typename S>
+__global__ void k_split_col(const double* __restrict__ xi, int64_t nr, int n, int64_t kc, S* __restrict__ p,
+                            S* __restrict__ r) {
+  const int64_t total = (int64_t)n * kc;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t m = i / kc, k = i - m * kc;
+    const double v = k < 2 * nr ? xi[m * 2 * nr + k] : 0.0;
+    const S hp = Prec<S>::round(v);
+    p[i] = hp;
+    r[i] = Prec<S>::round(v - Prec<S>::widen(hp));
+  }
+}
+
+// xi -> row form: row r = interleaved row r of xi (N complex values), padded
+// to kn.  64 grid points x 32 orbitals per block through LDS.
+template <typename S>
+__global__ void __launch_bounds__(256) k_split_row(const double* __restrict__ xi, int64_t nr, int n, int64_t kn,
+                                                   S* __restrict__ p, S* __restrict__ r) {
+  __shared__ double2 t[32][65];
+  const int64_t r0 = (int64_t)blockIdx.x * 64;
+  const int m0 = blockIdx.y * 32;
+  for (int e = threadIdx.x; e < 32 * 64; e += 256) {
+    const int mi = e / 64, ri = e % 64;
+    const int64_t rr = r0 + ri;
+    const int m = m0 + mi;
+    double2 v = {0.0, 0.0};
+    if (m < n && rr < nr) v = reinterpret_cast<const double2*>(xi)[(int64_t)m * nr + rr];
+    t[mi][ri] = v;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int ri = e / 64, kk = e % 64;  // kk: position in the 64-wide k window
+    const int64_t rr = r0 + ri;
+    if (rr >= nr) continue;
+    const double2 v = t[kk >> 1][ri];
+    const double x = (kk & 1) ? v.y : v.x;
+    const int64_t idx = rr * kn + 2 * (int64_t)m0 + kk;
+    const S hp = Prec<S>::round(x);
+    p[idx] = hp;
+    r[idx] = Prec<S>::round(x - Prec<S>::widen(hp));
+  }
+}
+
+// phi (complex, ld) -> B source rows: row n = interleaved phi_n, padded to kc.
+template <typename S, typename TI>
+__global__ void k_split_phi(const TI* __restrict__ phi, int64_t ld, int64_t nr, int R, int64_t kc,
+                            S* __restrict__ p, S* __restrict__ r) {
+  const int64_t total = (int64_t)R * kc;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t n = i / kc, k = i - n * kc;
+    const double v = k < 2 * nr ? (double)phi[n * 2 * ld + k] : 0.0;
+    const S hp = Prec<S>::round(v);
+    p[i] = hp;
+    r[i] = Prec<S>::round(v - Prec<S>::widen(hp));
+  }
+}
+
+// Fixed-order FP64 sum of the C = xi^H phi split partials, written as the B
+// operand of y = -xi C: row 2n = (Re C(k,n), -Im C(k,n)) pairs, row 2n+1 =
+// (Im C(k,n), Re C(k,n)) pairs, padded to kn; split p / r.
+template <typename S>
+__global__ void k_reduce_cn(const double* __restrict__ partial, int nsplit, int n, int R, int64_t kn,
+                            S* __restrict__ p, S* __restrict__ r) {
+  const int64_t M = n, NN = 2 * (int64_t)R;
+  const int64_t total = (int64_t)R * (kn / 2);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t nc = i / (kn / 2), k = i - nc * (kn / 2);
+    double cr = 0.0, ci = 0.0;
+    if (k < n) {
+      for (int s = 0; s < nsplit; ++s) {
+        cr += partial[((int64_t)s * M + k) * NN + 2 * nc];
+        ci += partial[((int64_t)s * M + k) * NN + 2 * nc + 1];
+      }
+    }
+    const double v[4] = {cr, -ci, ci, cr};
+    const int64_t base0 = (2 * nc) * kn + 2 * k, base1 = (2 * nc + 1) * kn + 2 * k;
+    const int64_t idx[4] = {base0, base0 + 1, base1, base1 + 1};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const S hp = Prec<S>::round(v[q]);
+      p[idx[q]] = hp;
+      r[idx[q]] = Prec<S>::round(v[q] - Prec<S>::widen(hp));
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+template <typename K>
+static fx_status allow_lds_mfma(K kernel, size_t bytes) {
+  if (bytes > 65536) FX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  return FX_OK;
+}
+
+template <typename S>
+static fx_status prepare_split_t(fx_ace* a, AceSplit* sp, hipStream_t st) {
+  if (sp->ready) return FX_OK;
+  const int64_t nr = a->nr;
+  const int n = a->n;
+  sp->kc = roundk(2 * nr);
+  sp->kn = roundk(2 * (int64_t)n);
+  const size_t cb = sizeof(S) * (size_t)n * sp->kc, rb = sizeof(S) * (size_t)nr * sp->kn;
+  FX_TRY(ace_alloc(a, cb, &sp->col_p));
+  FX_TRY(ace_alloc(a, cb, &sp->col_r));
+  FX_TRY(ace_alloc(a, rb, &sp->row_p));
+  FX_TRY(ace_alloc(a, rb, &sp->row_r));
+  const int64_t tc = (int64_t)n * sp->kc;
+  hipLaunchKernelGGL((k_split_col<S>), dim3((unsigned)std::min<int64_t>((tc + 255) / 256, 16384)), dim3(256), 0, st,
+                     (const double*)a->xi, nr, n, sp->kc, (S*)sp->col_p, (S*)sp->col_r);
+  FX_LAUNCH_CHECK();
+  hipLaunchKernelGGL((k_split_row<S>), dim3((unsigned)((nr + 63) / 64), (unsigned)(sp->kn / 64)), dim3(256), 0, st,
+                     (const double*)a->xi, nr, n, sp->kn, (S*)sp->row_p, (S*)sp->row_r);
+  FX_LAUNCH_CHECK();
+  sp->ready = true;
+  return FX_OK;
+}
+
+fx_status ace_prepare_split(fx_ace* a, fx_prec prec, hipStream_t st) {
+  if (prec == FX_PREC_ACE_FP32R || prec == FX_PREC_ACE_FP32) return prepare_split_t<float>(a, &a->f32, st);
+  if (prec == FX_PREC_ACE_BF16R || prec == FX_PREC_ACE_BF16) return prepare_split_t<uint16_t>(a, &a->b16, st);
+  return FX_OK;
+}
+
+template <typename S, bool REFINE>
+static fx_status apply_t(fx_ctx* ctx, Workspace* ws, fx_ace* a, AceSplit* sp, const void* phi, int R, int64_t ld_phi,
+                         void* out, int64_t ld_out, fx_dtype in_dtype, fx_dtype out_dtype, hipStream_t st) {
+  constexpr int BK = Prec<S>::BK;
+  constexpr int LDK = BK + Prec<S>::PAD;
+  const int64_t nr = a->nr;
+  const int n = a->n;
+  FX_TRY(prepare_split_t<S>(a, sp, st));
+  // phi split
+  void *php = nullptr, *phr = nullptr;
+  const size_t pb = sizeof(S) * (size_t)R * sp->kc;
+  FX_TRY(ws_get(ctx, ws, sizeof(S) == 4 ? "mf_phi_p32" : "mf_phi_p16", pb, &php));
+  FX_TRY(ws_get(ctx, ws, sizeof(S) == 4 ? "mf_phi_r32" : "mf_phi_r16", pb, &phr));
+  const int64_t tp = (int64_t)R * sp->kc;
+  int slot;
+  FX_TRY(prof_begin(ctx, st, FX_K_SPLIT, &slot));
+  if (in_dtype == FX_C128)
+    hipLaunchKernelGGL((k_split_phi<S, double>), dim3((unsigned)std::min<int64_t>((tp + 255) / 256, 16384)),
+                       dim3(256), 0, st, (const double*)phi, ld_phi, nr, R, sp->kc, (S*)php, (S*)phr);
+  else
+    hipLaunchKernelGGL((k_split_phi<S, float>), dim3((unsigned)std::min<int64_t>((tp + 255) / 256, 16384)),
+                       dim3(256), 0, st, (const float*)phi, ld_phi, nr, R, sp->kc, (S*)php, (S*)phr);
+  FX_LAUNCH_CHECK();
+  FX_TRY(prof_end(ctx, st, slot));
+
+  const size_t lds = (size_t)(REFINE ? 4 : 2) * TBM * LDK * sizeof(S);
+  // C = xi^H phi: M = n, N = 2R, K = kc, split over K
+  {
+    const int tiles_m = (n + TBM - 1) / TBM, tiles_n = (2 * R + TBN - 1) / TBN;
+    const int tiles = tiles_m * tiles_n;
+    const int64_t ksteps = sp->kc / BK;
+    int nsplit = (int)std::max<int64_t>(1, std::min<int64_t>((8 * ctx->n_cu + tiles - 1) / tiles, ksteps / 16));
+    if (const char* e = getenv("FX_ACE_NSPLIT")) nsplit = std::max(1, atoi(e));
+    int64_t kchunk = (ksteps + nsplit - 1) / nsplit * BK;
+    nsplit = (int)((sp->kc + kchunk - 1) / kchunk);
+    void* part = nullptr;
+    FX_TRY(ws_get(ctx, ws, "mf_partial", sizeof(double) * (size_t)nsplit * n * 2 * R, &part));
+    auto kern = k_tn_mfma<S, REFINE, true, 0>;
+    FX_TRY(allow_lds_mfma(kern, lds));
+    FX_TRY(prof_begin(ctx, st, FX_K_GEMM_CN, &slot));
+    hipLaunchKernelGGL(kern, dim3((unsigned)(tiles * nsplit)), dim3(256), lds, st, n, 2 * R, (int)sp->kc,
+                       (int)kchunk, (const S*)sp->col_p, (const S*)sp->col_r, sp->kc, (const S*)php, (const S*)phr,
+                       sp->kc, (double*)part, (void*)nullptr, (int64_t)0, 0, 0.0, tiles_m, tiles_n);
+    FX_LAUNCH_CHECK();
+    FX_TRY(prof_end(ctx, st, slot));
+    // reduce -> B operand of the second product
+    void *bp = nullptr, *br = nullptr;
+    const size_t bb = sizeof(S) * (size_t)2 * R * sp->kn;
+    FX_TRY(ws_get(ctx, ws, sizeof(S) == 4 ? "mf_bnn_p32" : "mf_bnn_p16", bb, &bp));
+    FX_TRY(ws_get(ctx, ws, sizeof(S) == 4 ? "mf_bnn_r32" : "mf_bnn_r16", bb, &br));
+    const int64_t tr = (int64_t)R * (sp->kn / 2);
+    FX_TRY(prof_begin(ctx, st, FX_K_REDUCE, &slot));
+    hipLaunchKernelGGL((k_reduce_cn<S>), dim3((unsigned)std::min<int64_t>((tr + 255) / 256, 16384)), dim3(256), 0, st,
+                       (const double*)part, nsplit, n, R, sp->kn, (S*)bp, (S*)br);
+    FX_LAUNCH_CHECK();
+    FX_TRY(prof_end(ctx, st, slot));
+    // y = -xi C: M = nr, N = 2R, K = kn
+    const int tm2 = (int)((nr + TBM - 1) / TBM), tn2 = (2 * R + TBN - 1) / TBN;
+    auto kern2 = k_tn_mfma<S, REFINE, false, 1>;
+    FX_TRY(allow_lds_mfma(kern2, lds));
+    FX_TRY(prof_begin(ctx, st, FX_K_GEMM_NN, &slot));
+    hipLaunchKernelGGL(kern2, dim3((unsigned)(tm2 * tn2)), dim3(256), lds, st, (int)nr, 2 * R, (int)sp->kn,
+                       (int)sp->kn, (const S*)sp->row_p, (const S*)sp->row_r, sp->kn, (const S*)bp, (const S*)br,
+                       sp->kn, (double*)nullptr, out, ld_out, out_dtype == FX_C64 ? 1 : 0, 1.0, tm2, tn2);
+    FX_LAUNCH_CHECK();
+    FX_TRY(prof_end(ctx, st, slot));
+  }
+  return FX_OK;
+}
+
+fx_status ace_apply_mfma(fx_ctx* ctx, Workspace* ws, fx_ace* a, const void* phi, int nphi, int64_t ld_phi, void* out,
+                         int64_t ld_out, fx_dtype in_dtype, fx_dtype out_dtype, fx_prec prec, hipStream_t st) {
+  switch (prec) {
+    case FX_PREC_ACE_FP32R:
+      return apply_t<float, true>(ctx, ws, a, &a->f32, phi, nphi, ld_phi, out, ld_out, in_dtype, out_dtype, st);
+    case FX_PREC_ACE_FP32:
+      return apply_t<float, false>(ctx, ws, a, &a->f32, phi, nphi, ld_phi, out, ld_out, in_dtype, out_dtype, st);
+    case FX_PREC_ACE_BF16R:
+      return apply_t<uint16_t, true>(ctx, ws, a, &a->b16, phi, nphi, ld_phi, out, ld_out, in_dtype, out_dtype, st);
+    case FX_PREC_ACE_BF16:
+      return apply_t<uint16_t, false>(ctx, ws, a, &a->b16, phi, nphi, ld_phi, out, ld_out, in_dtype, out_dtype, st);
+    default:
+      FX_FAIL(FX_ERR_UNSUPPORTED, "precision %d is not a matrix-core ACE precision", prec);
+  }
+}
+
+}  // namespace fx

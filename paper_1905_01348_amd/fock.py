@@ -1,0 +1,307 @@
+"""ctypes binding of libfock's C ABI (include/fock.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+library.  torch tensors supply device memory and streams.  If libfock.so has
+not been built the binding raises; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfock.so")
+
+# ---- enums (mirror include/fock.h) -----------------------------------------
+FX_OK = 0
+FX_ERR_INVALID = -1
+FX_ERR_UNSUPPORTED = -2
+FX_ERR_OOM = -3
+FX_ERR_NOT_POSDEF = -4
+FX_ERR_DEVICE = -5
+FX_ERR_BUSY = -6
+FX_ERR_CANCELLED = -7
+STATUS_NAMES = {0: "FX_OK", -1: "FX_ERR_INVALID", -2: "FX_ERR_UNSUPPORTED", -3: "FX_ERR_OOM",
+                -4: "FX_ERR_NOT_POSDEF", -5: "FX_ERR_DEVICE", -6: "FX_ERR_BUSY", -7: "FX_ERR_CANCELLED"}
+
+FX_C128, FX_C64 = 0, 1
+FX_COULOMB, FX_HSE = 0, 1
+PREC = {
+    "fp64": 0, "fp32": 1, "fp32acc64": 2,
+    "ace_fp64": 3, "ace_fp32r": 4, "ace_bf16r": 5, "ace_fp32": 6, "ace_bf16": 7,
+}
+KIND = {"coulomb": FX_COULOMB, "hse": FX_HSE}
+KERNEL_IDS = {"vx_plane_fwd": 0, "vx_pencil_z": 1, "vx_plane_inv": 2, "convert": 3, "gemm_cn": 4, "gemm_nn": 5,
+              "reduce": 6, "split": 7, "linalg": 8}
+
+
+class FxCell(C.Structure):
+    _fields_ = [("n", C.c_int32 * 3), ("len", C.c_double * 3)]
+
+
+class FxKernel(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("omega", C.c_double), ("scale", C.c_double)]
+
+
+class FxServeCfg(C.Structure):
+    _fields_ = [("max_slots", C.c_int32), ("n_streams", C.c_int32), ("max_batch_pairs", C.c_int32),
+                ("hbm_budget_bytes", C.c_size_t)]
+
+
+class FxRequest(C.Structure):
+    _fields_ = [("traj", C.c_int32), ("op", C.c_int32), ("first", C.c_int32), ("count", C.c_int32),
+                ("t_arrival_s", C.c_double), ("out", C.c_void_p), ("ld_out", C.c_int64)]
+
+
+class FxServeReport(C.Structure):
+    _fields_ = [("p50_ms", C.c_double), ("p99_ms", C.c_double), ("mean_ms", C.c_double), ("max_ms", C.c_double),
+                ("req_per_s", C.c_double), ("pairs_per_s", C.c_double), ("busy_frac", C.c_double),
+                ("wall_s", C.c_double), ("n_done", C.c_int64), ("n_rejected", C.c_int64),
+                ("n_batches", C.c_int64), ("hbm_peak_bytes", C.c_size_t)]
+
+
+# exported names and their signatures
+_SIGS = {
+    "fx_init": (C.c_int, [C.c_int, C.c_size_t, C.POINTER(C.c_void_p)]),
+    "fx_finalize": (C.c_int, [C.c_void_p]),
+    "fx_last_error": (C.c_char_p, []),
+    "fx_version": (C.c_char_p, []),
+    "fx_memory": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
+    "fx_apply_vx": (C.c_int, [C.c_void_p, C.POINTER(FxCell), C.POINTER(FxKernel),
+                              C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_int32, C.c_int64,
+                              C.c_void_p, C.c_int64, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p]),
+    "fx_build_ace": (C.c_int, [C.c_void_p, C.POINTER(FxCell), C.POINTER(FxKernel),
+                               C.c_void_p, C.c_int32, C.c_int64, C.c_int, C.c_int, C.c_int, C.c_void_p,
+                               C.POINTER(C.c_void_p), C.POINTER(C.c_double)]),
+    "fx_apply_ace": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_int64,
+                               C.c_int, C.c_int, C.c_int, C.c_void_p]),
+    "fx_ace_export": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "fx_ace_shape": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32), C.POINTER(C.c_int64)]),
+    "fx_ace_free": (C.c_int, [C.c_void_p]),
+    "fx_serve_create": (C.c_int, [C.c_void_p, C.POINTER(FxServeCfg), C.POINTER(C.c_void_p)]),
+    "fx_serve_register": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(FxCell), C.POINTER(FxKernel),
+                                    C.c_void_p, C.c_int32, C.c_int64, C.c_int, C.c_int, C.c_int]),
+    "fx_serve": (C.c_int, [C.c_void_p, C.POINTER(FxRequest), C.c_int32, C.POINTER(C.c_int),
+                           C.POINTER(C.c_double), C.POINTER(FxServeReport)]),
+    "fx_serve_destroy": (C.c_int, [C.c_void_p]),
+    "fx_prof_enable": (C.c_int, [C.c_void_p, C.c_int]),
+    "fx_prof_read": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
+    "fx_debug_host_pair": (C.c_int, [C.POINTER(FxCell), C.POINTER(FxKernel), C.c_int, C.c_void_p, C.c_void_p,
+                                      C.c_void_p]),
+}
+
+_lib = None
+
+
+def load():
+    """Load libfock.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libfock.so not built ({LIB_PATH}); run __graft_entry__.build()")
+    lib = C.CDLL(LIB_PATH)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class FockError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _check(status):
+    if status != FX_OK:
+        raise FockError(status, load().fx_last_error().decode(errors="replace"))
+
+
+def make_cell(n, L):
+    n3 = tuple(int(v) for v in (n if hasattr(n, "__len__") else (n, n, n)))
+    l3 = tuple(float(v) for v in (L if hasattr(L, "__len__") else (L, L, L)))
+    c = FxCell()
+    c.n[:] = n3
+    c.len[:] = l3
+    return c
+
+
+def make_kernel(kind="hse", omega=0.106, scale=1.0):
+    k = FxKernel()
+    k.kind = KIND[kind] if isinstance(kind, str) else int(kind)
+    k.omega = float(omega)
+    k.scale = float(scale)
+    return k
+
+
+def _dtype_code(t):
+    import torch
+
+    if t.dtype == torch.complex128:
+        return FX_C128
+    if t.dtype == torch.complex64:
+        return FX_C64
+    raise TypeError(f"orbitals must be complex64 or complex128, got {t.dtype}")
+
+
+def _cols(t, nr):
+    """(pointer, ncols, ld) of a device tensor holding columns of nr points."""
+    if not t.is_cuda:
+        raise TypeError("device (cuda/hip) tensor expected")
+    if t.dim() == 1:
+        if t.numel() != nr:
+            raise ValueError("1-D tensor must hold one orbital")
+        return t.data_ptr(), 1, nr
+    if t.stride(-1) != 1:
+        raise ValueError("innermost dimension must be contiguous")
+    flat_inner = 1
+    for s in t.shape[1:]:
+        flat_inner *= s
+    if flat_inner != nr:
+        raise ValueError(f"each column must hold N_r = {nr} points, got {flat_inner}")
+    # every dim but the first must be contiguous within a column
+    expect = 1
+    for d in range(t.dim() - 1, 0, -1):
+        if t.stride(d) != expect and t.shape[d] != 1:
+            raise ValueError("columns must be contiguous")
+        expect *= t.shape[d]
+    return t.data_ptr(), t.shape[0], t.stride(0)
+
+
+def _stream_ptr(stream):
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+class Context:
+    """One libfock context on one device (owns tables, workspaces, budget)."""
+
+    def __init__(self, device=0, hbm_budget_bytes=0):
+        lib = load()
+        h = C.c_void_p()
+        _check(lib.fx_init(int(device), int(hbm_budget_bytes), C.byref(h)))
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if self.h:
+            _check(load().fx_finalize(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def memory(self):
+        a, b = C.c_size_t(), C.c_size_t()
+        _check(load().fx_memory(self.h, C.byref(a), C.byref(b)))
+        return a.value, b.value
+
+    # -- per-kernel timing (include/fock_prof.h) --------------------------------
+    def prof_enable(self, on=True):
+        _check(load().fx_prof_enable(self.h, 1 if on else 0))
+
+    def prof_read(self, kid):
+        n, ms = C.c_int64(), C.c_double()
+        _check(load().fx_prof_read(self.h, int(kid), C.byref(n), C.byref(ms)))
+        return n.value, ms.value
+
+    # -- V_X ------------------------------------------------------------------
+    def apply_vx(self, psi, phi=None, *, n, L, kernel="hse", omega=0.106, scale=1.0, prec="fp32acc64",
+                 out=None, out_dtype=None, stream=None, energy=False):
+        """out = V_X[psi] phi; returns out (and E_X as a 0-d float64 tensor if energy)."""
+        import torch
+
+        cell = make_cell(n, L)
+        nr = cell.n[0] * cell.n[1] * cell.n[2]
+        kern = make_kernel(kernel, omega, scale)
+        if phi is None:
+            phi = psi
+        pp, npsi, ldp = _cols(psi, nr)
+        fp, nphi, ldf = _cols(phi, nr)
+        if out is None:
+            od = out_dtype or (torch.complex128 if prec in ("fp64", "fp32acc64") else torch.complex64)
+            out = torch.empty((nphi,) + tuple(phi.shape[1:]), dtype=od, device=phi.device)
+        op, nout, ldo = _cols(out, nr)
+        if nout != nphi:
+            raise ValueError("out must have as many columns as phi")
+        if psi.dtype != phi.dtype:
+            raise TypeError("psi and phi must have the same dtype")
+        ex = torch.zeros((), dtype=torch.float64, device=psi.device) if energy else None
+        _check(load().fx_apply_vx(self.h, C.byref(cell), C.byref(kern), pp, npsi, ldp, fp, nphi, ldf, op, ldo,
+                                  _dtype_code(psi), _dtype_code(out), PREC[prec], _stream_ptr(stream),
+                                  C.c_void_p(ex.data_ptr()) if ex is not None else None))
+        return (out, ex) if energy else out
+
+    # -- ACE ------------------------------------------------------------------
+    def build_ace(self, psi, *, n, L, kernel="hse", omega=0.106, scale=1.0, vx_prec="fp64",
+                  ace_prec="ace_fp64", stream=None):
+        cell = make_cell(n, L)
+        nr = cell.n[0] * cell.n[1] * cell.n[2]
+        kern = make_kernel(kernel, omega, scale)
+        pp, npsi, ldp = _cols(psi, nr)
+        h = C.c_void_p()
+        ex = C.c_double()
+        _check(load().fx_build_ace(self.h, C.byref(cell), C.byref(kern), pp, npsi, ldp, _dtype_code(psi),
+                                   PREC[vx_prec], PREC[ace_prec], _stream_ptr(stream), C.byref(h), C.byref(ex)))
+        return Ace(self, h, nr, npsi, tuple(psi.shape[1:]), ex.value, psi.device)
+
+
+class Ace:
+    """Handle of ACE factors built by Context.build_ace."""
+
+    def __init__(self, ctx, h, nr, n, grid_shape, ex, device):
+        self.ctx, self.h, self.nr, self.n, self.grid_shape, self.ex, self.device = ctx, h, nr, n, grid_shape, ex, device
+
+    def apply(self, phi, *, prec="ace_fp64", out=None, out_dtype=None, stream=None):
+        import torch
+
+        fp, nphi, ldf = _cols(phi, self.nr)
+        if out is None:
+            out = torch.empty((nphi,) + tuple(phi.shape[1:]), dtype=out_dtype or phi.dtype, device=phi.device)
+        op, nout, ldo = _cols(out, self.nr)
+        _check(load().fx_apply_ace(self.ctx.h, self.h, fp, nphi, ldf, op, ldo, _dtype_code(phi), _dtype_code(out),
+                                   PREC[prec], _stream_ptr(stream)))
+        return out
+
+    def export(self):
+        import torch
+
+        xi = torch.empty((self.n, self.nr), dtype=torch.complex128, device=self.device)
+        L = torch.empty((self.n, self.n), dtype=torch.complex128, device=self.device)
+        M = torch.empty((self.n, self.n), dtype=torch.complex128, device=self.device)
+        _check(load().fx_ace_export(self.h, xi.data_ptr(), L.data_ptr(), M.data_ptr()))
+        # L and M are column-major N x N: the torch view (col, row) -> transpose
+        return xi, L.T.contiguous(), M.T.contiguous()
+
+    def free(self):
+        if self.h:
+            _check(load().fx_ace_free(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def debug_host_pair(psi_j, phi_k, *, n, L, kernel="hse", omega=0.106, scale=1.0, prec=0):
+    """Run the library's pass code on the host for one pair (prec 0: FP64, 1: FP32)."""
+    import numpy as np
+
+    cell = make_cell(n, L)
+    kern = make_kernel(kernel, omega, scale)
+    a = np.ascontiguousarray(psi_j, dtype=np.complex128)
+    b = np.ascontiguousarray(phi_k, dtype=np.complex128)
+    v = np.empty_like(a)
+    _check(load().fx_debug_host_pair(C.byref(cell), C.byref(kern), int(prec), a.ctypes.data, b.ctypes.data, v.ctypes.data))
+    return v

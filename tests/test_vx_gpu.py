@@ -1,0 +1,202 @@
+"""V_X on the GPU through the C ABI against the FP64 oracle.
+
+Tolerances (relative, per column, max over columns): FP64 path 1e-10;
+FP32 and FP32_ACC64 paths 1e-5 (the workload-stated bars).
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_util import col_err, dev, host, say, workers
+
+pytestmark = pytest.mark.gpu
+
+TOL64, TOL32 = 1e-10, 1e-5
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1905_01348_amd import Context
+
+    c = Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def cfg0():
+    w = synth.workload("cfg0")
+    psi = synth.make_orbitals(w["seed"], w["n"], w["L"], w["N"])
+    ref = oracle.apply_vx(psi, psi, w["n"], w["L"], "coulomb")
+    return w, psi, ref
+
+
+def test_cfg0_fp64_parity_and_energy(ctx, cfg0):
+    import torch
+
+    w, psi, ref = cfg0
+    say("cfg0 fp64", psi.shape)
+    out, ex = ctx.apply_vx(dev(psi), n=w["n"], L=w["L"], kernel="coulomb", prec="fp64", energy=True)
+    torch.cuda.synchronize()
+    assert col_err(host(out), ref) <= TOL64
+    ex_ref = oracle.exchange_energy(psi, ref)
+    assert abs(ex.item() - ex_ref) <= 1e-12 * abs(ex_ref)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp32acc64"])
+def test_cfg0_fp32_paths(ctx, cfg0, prec):
+    import torch
+
+    w, psi, ref = cfg0
+    say("cfg0", prec)
+    for in_dtype in (torch.complex128, torch.complex64):
+        out = ctx.apply_vx(dev(psi, in_dtype), n=w["n"], L=w["L"], kernel="coulomb", prec=prec)
+        err = col_err(host(out), ref)
+        say("  in", in_dtype, "err", err)
+        assert err <= TOL32
+
+
+GRIDS = [
+    ((2, 2, 2), (1.5, 1.5, 1.5), 3, 2),
+    ((3, 4, 6), (2.0, 2.5, 3.0), 4, 3),
+    ((8, 6, 9), (4.0, 3.0, 4.5), 5, 7),
+    ((16, 12, 18), (6.0, 5.0, 6.5), 7, 3),
+    ((27, 16, 8), (7.0, 5.0, 3.0), 3, 5),
+    ((32, 36, 24), (9.0, 9.5, 7.0), 6, 4),
+    ((81, 4, 6), (20.0, 2.0, 2.5), 2, 3),
+    ((96, 2, 3), (25.0, 1.0, 1.2), 3, 2),
+    ((9, 96, 12), (3.0, 25.0, 4.0), 2, 2),
+    ((6, 9, 96), (2.0, 3.0, 25.0), 2, 2),
+]
+
+
+@pytest.mark.parametrize("kind", ["hse", "coulomb"])
+@pytest.mark.parametrize("grid", GRIDS, ids=[str(g[0]) for g in GRIDS])
+def test_grids_fp64_and_fp32(ctx, grid, kind):
+    """Odd, even, orthorhombic and extreme-aspect grids; phi != psi; padded leading dimensions."""
+    import torch
+
+    n3, L3, N, Nt = grid
+    say("grid", n3, kind)
+    nr = int(np.prod(n3))
+    psi = synth.make_orbitals(11, n3, L3, N, ecut=1e4)
+    phi = synth.random_grid_vectors(12, n3, Nt)
+    ref = oracle.apply_vx(psi, phi, n3, L3, kind, 0.4)
+    # padded columns: ld = nr + 5
+    P = torch.zeros((N, nr + 5), dtype=torch.complex128, device="cuda")
+    P[:, :nr] = dev(psi.reshape(N, nr))
+    Q = torch.zeros((Nt, nr + 3), dtype=torch.complex128, device="cuda")
+    Q[:, :nr] = dev(phi.reshape(Nt, nr))
+    from paper_1905_01348_amd import fock as F
+    import ctypes as C
+
+    cell = F.make_cell(n3, L3)
+    kern = F.make_kernel(kind, 0.4)
+    for prec, tol in (("fp64", TOL64), ("fp32acc64", TOL32), ("fp32", TOL32)):
+        O = torch.full((Nt, nr + 7), complex(7.0, -7.0), dtype=torch.complex128, device="cuda")
+        st = F.load().fx_apply_vx(ctx.h, C.byref(cell), C.byref(kern), P.data_ptr(), N, nr + 5, Q.data_ptr(), Nt,
+                                  nr + 3, O.data_ptr(), nr + 7, F.FX_C128, F.FX_C128, F.PREC[prec],
+                                  C.c_void_p(torch.cuda.current_stream().cuda_stream), None)
+        assert st == 0, F.load().fx_last_error()
+        torch.cuda.synchronize()
+        got = host(O[:, :nr])
+        assert col_err(got, ref.reshape(Nt, nr)) <= tol, prec
+        # padding untouched
+        assert np.all(host(O[:, nr:]) == complex(7.0, -7.0))
+
+
+def test_planewave_closed_form_on_gpu(ctx):
+    from tests import pins
+
+    n3, L3 = (6, 6, 6), (5.0, 5.0, 5.0)
+    mvecs = [(0, 0, 0), (1, 0, 0), (0, -1, 2), (3, 1, -1), (-2, 2, 1)]
+    psi = synth.planewave_orbitals(n3, L3, mvecs)
+    out = host(ctx.apply_vx(dev(psi), n=n3, L=L3, kernel="hse", omega=0.3, prec="fp64"))
+    for k, mk in enumerate(mvecs):
+        lam = 0.0
+        for mj in mvecs:
+            d = [pins._wrap(mk[a] - mj[a], n3[a]) for a in range(3)]
+            g2 = sum((2 * np.pi * d[a] / L3[a]) ** 2 for a in range(3))
+            lam += pins._kernel_formula("hse", np.array([g2]), 0.3)[0]
+        exp = -lam / np.prod(L3) * psi[k]
+        assert np.abs(out[k] - exp).max() <= 1e-12 * np.abs(exp).max()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32acc64", "fp32"])
+def test_batching_invariance_and_repeatability_bitwise(ctx, cfg0, prec):
+    """The j-sum order is fixed: results are bitwise identical for any batch size and across runs."""
+    w, psi, _ = cfg0
+    P = dev(psi)
+    outs = []
+    for nj in ("", "1", "3", "16"):
+        if nj:
+            os.environ["FX_VX_NJ"] = nj
+        else:
+            os.environ.pop("FX_VX_NJ", None)
+        try:
+            outs.append(host(ctx.apply_vx(P, n=w["n"], L=w["L"], kernel="coulomb", prec=prec)))
+        finally:
+            os.environ.pop("FX_VX_NJ", None)
+    outs.append(host(ctx.apply_vx(P, n=w["n"], L=w["L"], kernel="coulomb", prec=prec)))
+    for o in outs[1:]:
+        assert np.array_equal(o.view(np.float64 if o.dtype == np.complex128 else np.float32),
+                              outs[0].view(np.float64 if o.dtype == np.complex128 else np.float32))
+
+
+def test_cfg1_sampled_columns(ctx):
+    """48^3, 128 orbitals, HSE: every precision on all 128 targets, oracle on 3 sampled targets."""
+    import torch
+
+    w = synth.workload("cfg1")
+    say("cfg1 generating")
+    psi = synth.make_orbitals(w["seed"], w["n"], w["L"], w["N"])
+    P = dev(psi)
+    ks = [0, 77, 127]
+    say("cfg1 oracle on", ks)
+    ref = oracle.apply_vx(psi, psi, w["n"], w["L"], "hse", targets=ks, workers=workers())
+    outs = {}
+    for prec, tol in (("fp64", TOL64), ("fp32acc64", TOL32), ("fp32", TOL32)):
+        out = ctx.apply_vx(P, n=w["n"], L=w["L"], kernel="hse", prec=prec)
+        torch.cuda.synchronize()
+        outs[prec] = out
+        err = col_err(host(out[ks]), ref)
+        say("cfg1", prec, err)
+        assert err <= tol
+    # FP32 forms against the GPU FP64 form on every column
+    r64 = host(outs["fp64"])
+    assert col_err(host(outs["fp32acc64"]), r64) <= TOL32
+    assert col_err(host(outs["fp32"]), r64) <= TOL32
+
+
+def test_error_paths(ctx, cfg0):
+    import torch
+    from paper_1905_01348_amd import FockError
+
+    w, psi, _ = cfg0
+    P = dev(psi)
+    with pytest.raises(FockError) as ei:  # out aliases psi
+        ctx.apply_vx(P, n=w["n"], L=w["L"], out=P, prec="fp64")
+    assert ei.value.status == -1
+    with pytest.raises(FockError) as ei:  # energy needs phi == psi
+        ctx.apply_vx(P, P[:3].clone(), n=w["n"], L=w["L"], prec="fp64", energy=True)
+    assert ei.value.status == -1
+    with pytest.raises(FockError) as ei:
+        ctx.apply_vx(P, n=(144, 96, 1), L=w["L"], prec="fp64")  # same N_r, unsupported edges
+    assert ei.value.status == -2
+    with pytest.raises(FockError) as ei:
+        ctx.apply_vx(P, n=w["n"], L=w["L"], prec="ace_fp64")
+    assert ei.value.status == -2
+    # budget too small -> OOM, reported, context still usable afterwards
+    from paper_1905_01348_amd import Context
+
+    small = Context(0, hbm_budget_bytes=1 << 20)
+    with pytest.raises(FockError) as ei:
+        small.apply_vx(P, n=w["n"], L=w["L"], prec="fp64")
+    assert ei.value.status == -3
+    small.close()
+    out = ctx.apply_vx(P, n=w["n"], L=w["L"], prec="fp64", kernel="coulomb")
+    torch.cuda.synchronize()
+    assert torch.isfinite(torch.view_as_real(out)).all()
