@@ -41,22 +41,6 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# Algorithmic HBM bytes per grid point per pair for each V_X kernel, storage
-# of s bytes per complex value (8 for the FP32 path, 16 for FP64):
-#   plane_fwd : read psi_j and phi_k, write the pair volume T   -> 3 s
-#   pencil_z  : read and write T                                -> 2 s
-#   plane_inv : read T and psi_j                                -> 2 s
-#               + read and write the FP64 partial sum of phi_k once per
-#                 batch of nj orbitals (16 B each way)          -> 32/nj
-def algorithmic_bytes_per_pt(kernel, s, nj, multi_batch):
-    if kernel == "vx_plane_fwd":
-        return 3 * s
-    if kernel == "vx_pencil_z":
-        return 2 * s
-    extra = (32.0 / nj) if multi_batch else (16.0 / nj)
-    return 2 * s + extra
-
-
 def cpu_baseline(psi_h, w, seconds):
     """The FP64 oracle as it stands, timed on a growing prefix of orbitals for target 0."""
     import numpy as np
@@ -87,11 +71,21 @@ def main():
     ap.add_argument("--prec", default="fp32acc64", choices=["fp32acc64", "fp32", "fp64"])
     ap.add_argument("--fp64-steps", type=int, default=2, help="timed FP64 steps for the comparison (0 = skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU oracle budget (0 = skip)")
+    ap.add_argument("--leg", default="vx", choices=["vx", "ace", "serve", "copy"],
+                    help="vx: V_X apply (default); ace: ACE build + apply at 96^3, N = R = 1024; serve: serving replay")
+    ap.add_argument("--requests", type=int, default=12000, help="serve leg: measured requests")
+    ap.add_argument("--warm-requests", type=int, default=1000, help="serve leg: warm-up requests")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU ring pass is a design, not built)", file=sys.stderr)
         sys.exit(2)
+    if args.leg == "copy":
+        return bench_copy(args)
+    if args.leg == "ace":
+        return bench_ace(args)
+    if args.leg == "serve":
+        return bench_serve(args)
 
     import numpy as np
     import torch
@@ -130,36 +124,25 @@ def main():
     value = pairs * args.steps / el
     ms_per_step = 1e3 * el / args.steps
 
-    # per-kernel durations over the timed region
-    s_bytes = 16 if args.prec == "fp64" else 8
-    pair_bytes = nr * s_bytes
-    cap = int(os.environ.get("FX_WORK_MB", "2048")) << 20
-    nk = min(Nt, max(1, cap // pair_bytes))
-    nj = min(N, max(1, (cap // pair_bytes) // nk))
-    if os.environ.get("FX_VX_NJ"):
-        nj = min(nj, int(os.environ["FX_VX_NJ"]))
-    multi = nj < N
+    # per-kernel durations (HIP events on the launch stream) and the
+    # algorithmic bytes each launch moves, both recorded by the library
     kern = {}
     for name in ("vx_plane_fwd", "vx_pencil_z", "vx_plane_inv", "convert"):
-        cnt, ms = ctx.prof_read(fock.KERNEL_IDS[name])
+        cnt, ms, work = ctx.prof_read(fock.KERNEL_IDS[name])
         if cnt:
-            kern[name] = {"launches": cnt, "avg_ms": ms / cnt, "total_ms": ms}
+            kern[name] = {"launches": cnt, "avg_ms": ms / cnt, "total_ms": ms,
+                          "bytes_per_launch": work / cnt, "algorithmic_GBps": work / (ms * 1e-3) / 1e9}
     ctx.prof_enable(False)
     dom = max((k for k in kern if k.startswith("vx_")), key=lambda k: kern[k]["total_ms"])
-    pairs_per_launch = (nk * nj) if dom != "vx_plane_inv" else nk * nj
-    bpp = algorithmic_bytes_per_pt(dom, s_bytes, nj, multi)
-    bytes_per_launch = bpp * nr * pairs_per_launch
-    achieved = bytes_per_launch / (kern[dom]["avg_ms"] * 1e-3) / 1e9
+    achieved = kern[dom]["algorithmic_GBps"]
+    bytes_per_launch = kern[dom]["bytes_per_launch"]
     traffic = None
     cpath = os.path.join(ROOT, "profiles", "vx_counters.json")
     if os.path.exists(cpath):
         c = json.load(open(cpath))
         if c.get("source_hash") == kernel_source_hash() and c.get("kernel") == dom and c.get("prec") == args.prec:
             traffic = c.get("bytes_per_launch")
-    for k in kern:
-        if k.startswith("vx_"):
-            b = algorithmic_bytes_per_pt(k, s_bytes, nj, multi) * nr * nk * nj
-            kern[k]["algorithmic_GBps"] = b / (kern[k]["avg_ms"] * 1e-3) / 1e9
+    path_bytes = sum(kern[k]["bytes_per_launch"] * kern[k]["launches"] for k in kern) / args.steps
 
     result = {
         "metric": "Fock-exchange orbital pairs/s",
@@ -180,7 +163,6 @@ def main():
             "prec": args.prec,
             "accumulation": "f64" if args.prec in ("fp64", "fp32acc64") else "f32",
             "pairs_per_step": pairs,
-            "batch": {"targets": nk, "orbitals": nj},
         },
         "roofline": {
             "bound": "hbm",
@@ -190,15 +172,13 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "algorithmic_bytes_per_pair_pt": bpp,
-            "pairs_per_launch": pairs_per_launch,
+            "algorithmic_bytes_per_launch": bytes_per_launch,
         },
         "kernels": kern,
     }
-    # model: whole-path algorithmic bytes / step time
-    total_bpp = sum(algorithmic_bytes_per_pt(k, s_bytes, nj, multi)
-                    for k in ("vx_plane_fwd", "vx_pencil_z", "vx_plane_inv"))
-    result["path_model_GBps"] = total_bpp * nr * pairs / (ms_per_step * 1e-3) / 1e9
+    # whole path: algorithmic bytes of every kernel per step / step time
+    result["path_algorithmic_GBps"] = path_bytes / (ms_per_step * 1e-3) / 1e9
+    result["path_bytes_per_pair_pt"] = path_bytes / (pairs * nr)
 
     if args.fp64_steps > 0 and args.prec != "fp64":
         del out
@@ -221,6 +201,166 @@ def main():
     if args.cpu_seconds > 0:
         log("[bench] CPU oracle baseline ...")
         result["cpu_baseline"] = cpu_baseline(psi_h, w, args.cpu_seconds)
+    ctx.close()
+    print(json.dumps(result))
+
+
+def bench_copy(args):
+    """Plain device-to-device copy of 1 GiB (torch's copy kernel): calibrates the
+    FETCH_SIZE / WRITE_SIZE counters against a known byte count."""
+    import torch
+
+    nbytes = 1 << 30
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(max(1, args.steps)):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    print(json.dumps({"metric": "device copy bandwidth", "value": 2 * nbytes / el / 1e9, "unit": "GB/s",
+                      "bytes_read_per_copy": nbytes, "bytes_written_per_copy": nbytes,
+                      "copies": max(1, args.steps) + 1}))
+
+
+MFMA_PEAK_TFLOPS = {"ace_fp32r": 157.3, "ace_fp32": 157.3, "ace_bf16r": 2500.0, "ace_bf16": 2500.0,
+                    "ace_fp64": 78.6}
+
+
+def bench_ace(args):
+    """ACE at one GPU's share of the 512-atom cell: 96^3 grid, N = 1024 orbitals, R = 1024 right-hand sides."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1905_01348_amd import Context, fock
+
+    w = synth.workload("cfg2")
+    n, L, N = w["n"], w["L"], w["N"]
+    nr = n ** 3
+    R = N
+    log("[bench-ace] generating orbitals (seed 2) and right-hand sides (seed 3) ...")
+    psi = torch.from_numpy(synth.make_orbitals(w["seed"], n, L, N, dtype=np.complex64)).to("cuda:0")
+    phi = torch.from_numpy(synth.make_orbitals(3, n, L, R, dtype=np.complex64)).to("cuda:0")
+    ctx = Context(0)
+    t0 = time.perf_counter()
+    ace = ctx.build_ace(psi, n=n, L=L, kernel="hse", omega=0.106, vx_prec="fp32acc64", ace_prec="ace_fp64")
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    log(f"[bench-ace] build {t_build:.2f} s ({N * N} pairs)")
+    out = torch.empty_like(phi)
+    res = {}
+    ref = None
+    for prec in ("ace_fp64", "ace_fp32r", "ace_bf16r", "ace_fp32", "ace_bf16"):
+        ace.apply(phi, prec=prec, out=out)  # first use builds the split copies of xi
+        torch.cuda.synchronize()
+        ctx.prof_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ace.apply(phi, prec=prec, out=out)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / args.steps
+        kern = {}
+        for name in ("gemm_cn", "gemm_nn", "reduce", "split"):
+            cnt, ms, work = ctx.prof_read(fock.KERNEL_IDS[name])
+            if cnt:
+                kern[name] = {"launches": cnt, "avg_ms": ms / cnt, "work_per_launch": work / cnt,
+                              "rate": work / (ms * 1e-3)}
+        ctx.prof_enable(False)
+        mult = 3 if prec.endswith("r") else 1
+        eff = 16.0 * nr * N * R  # two complex GEMMs, 8 real flops per complex MAC
+        per_gemm_exec = 8.0 * nr * N * R * mult
+        y = out.to(torch.complex128)
+        if ref is None:
+            ref = y.clone()
+        err = (torch.linalg.vector_norm(y - ref, dim=(1, 2, 3)) / torch.linalg.vector_norm(ref, dim=(1, 2, 3))).max()
+        entry = {"ms_per_apply": 1e3 * el, "effective_TFLOPs": eff / el / 1e12,
+                 "executed_TFLOPs": 2 * per_gemm_exec / el / 1e12, "max_col_rel_err_vs_fp64": float(err),
+                 "kernels": kern}
+        for g in ("gemm_cn", "gemm_nn"):
+            if g in kern:
+                ach = kern[g]["rate"] / 1e12  # executed flops / time
+                entry[g + "_roofline"] = {"bound": "mfma", "achieved": ach, "peak": MFMA_PEAK_TFLOPS[prec],
+                                          "unit": "TFLOP/s", "frac": ach / MFMA_PEAK_TFLOPS[prec]}
+        res[prec] = entry
+        log(f"[bench-ace] {prec}: {1e3 * el:.1f} ms, err {float(err):.2e}")
+    main_p = "ace_fp32r"
+    dom = max(("gemm_cn", "gemm_nn"), key=lambda g: res[main_p]["kernels"].get(g, {"avg_ms": 0})["avg_ms"])
+    result = {
+        "metric": "ACE apply orbital-pair equivalents/s",
+        "value": N * R / (res[main_p]["ms_per_apply"] * 1e-3),
+        "unit": "pairs/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": res[main_p]["ms_per_apply"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"ACE apply K_ACE phi = -xi (xi^H phi), 96^3 grid, N = {N}, R = {R}, "
+                               "FP32 matrix cores + FP64-combined residual step", "build_s": t_build},
+        "roofline": res[main_p][dom + "_roofline"],
+        "precisions": res,
+    }
+    ace.free()
+    ctx.close()
+    print(json.dumps(result))
+
+
+def bench_serve(args):
+    """Serving replay: Poisson arrivals (200/s) over 12 resident trajectories of three cell sizes."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1905_01348_amd import Context, Server
+    from synth.requests import poisson_requests
+
+    classes = {0: "serveA", 1: "serveB", 2: "serveC"}
+    ctx = Context(0)
+    srv = Server(ctx, max_slots=8, n_streams=4, max_batch_pairs=1 << 15, hbm_budget_bytes=64 << 30)
+    by_class = {}
+    t0 = time.perf_counter()
+    for c, name in classes.items():
+        wl = synth.workload(name)
+        for t in range(4):
+            tid = 10 * c + t
+            psi = torch.from_numpy(synth.make_orbitals(wl["seed"] + t, wl["n"], wl["L"], wl["N"],
+                                                       dtype=np.complex64)).to("cuda:0")
+            srv.register(tid, psi, n=wl["n"], L=wl["L"], kernel="hse", omega=0.106, vx_prec="fp32acc64",
+                         ace_prec="ace_fp32r")
+            del psi
+            by_class.setdefault(c, []).append((tid, wl["N"]))
+            log(f"[bench-serve] registered {name} traj {tid}")
+    t_reg = time.perf_counter() - t0
+    mix = {0: 0.50, 1: 0.35, 2: 0.15}
+
+    def run(seed, nreq):
+        reqs = poisson_requests(seed, nreq, 200.0, by_class, mix, block=8)
+        outs = {}
+        for r in reqs:
+            wl = synth.workload(classes[r["traj"] // 10])
+            key = (r["traj"] // 10, r["count"])
+            if key not in outs:
+                outs[key] = torch.empty((r["count"], wl["n"], wl["n"], wl["n"]), dtype=torch.complex64,
+                                        device="cuda:0")
+            r["out"] = outs[key]
+        return srv.serve(reqs)
+
+    if args.warm_requests:
+        run(4, args.warm_requests)
+    st, lat, rep = run(5, args.requests)
+    ok = sum(1 for s in st if s == 0)
+    result = {
+        "metric": "serving p99 latency",
+        "value": rep["p99_ms"], "unit": "ms", "n_gpus": 1, "steps": args.requests, "warmup": args.warm_requests,
+        "ms_per_step": rep["mean_ms"], "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "Poisson 200 req/s; 50/35/15% classes 24^3 N=16, 48^3 N=128, 72^3 N=432; "
+                               "V_X or ACE on blocks of 8 orbitals; complex64; HSE",
+                   "register_s": t_reg},
+        "report": rep, "ok": ok, "offered_load": rep["busy_frac"],
+    }
+    srv.close()
     ctx.close()
     print(json.dumps(result))
 

@@ -29,8 +29,11 @@ typedef enum fx_kernel_id {
 fx_status fx_prof_enable(fx_ctx* ctx, int on);
 
 /* Wait for the recorded events and return, for kernel `id`, the number of timed
- * launches and their summed duration in milliseconds. */
-fx_status fx_prof_read(fx_ctx* ctx, int id, int64_t* launches, double* total_ms);
+ * launches, their summed duration in milliseconds and their summed algorithmic
+ * work: HBM bytes the launch must move as designed (FFT passes, conversions,
+ * splits, reductions) or floating-point operations it executes (GEMMs; the
+ * residual products included).  Any output pointer may be NULL. */
+fx_status fx_prof_read(fx_ctx* ctx, int id, int64_t* launches, double* total_ms, double* work);
 
 #ifdef __cplusplus
 }

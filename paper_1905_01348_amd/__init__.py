@@ -8,6 +8,7 @@ from .fock import (  # noqa: F401
     Ace,
     Context,
     FockError,
+    Server,
     debug_host_pair,
     load,
     make_cell,

@@ -181,8 +181,10 @@ fx_status ace_apply_impl(fx_ctx* ctx, Workspace* ws, const fx_ace* ac, const voi
     }
     void* C = nullptr;
     FX_TRY(ws_get(ctx, ws, "acea_C", zsz * n * nphi, &C));
+    // split count fixed by N_r alone: results do not depend on n_phi
+    const int nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(64, nr / 8192));
     FX_TRY(zgemm(ctx, ws, st, 1, 0, n, nphi, (int)nr, cpx<double>{1, 0}, a->xi, nr, p64, ldp, cpx<double>{0, 0}, C, n,
-                 1, 0, 0, 0, 0));
+                 1, 0, 0, 0, nsplit));
     void* y = out;
     int64_t ldy = ld_out;
     if (out_dtype == FX_C64) {

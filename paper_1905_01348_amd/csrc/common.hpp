@@ -92,6 +92,7 @@ struct GridTables {
 // One timed launch: events recorded before and after it on its stream.
 struct ProfRec {
   int id;
+  double work;  // algorithmic bytes (memory-bound kernels) or executed flops (GEMMs)
   hipEvent_t a, b;
 };
 
@@ -113,6 +114,7 @@ struct fx_ctx {
   std::vector<hipEvent_t> ev_pool;
   int64_t prof_launches[FX_K_COUNT] = {0};
   double prof_ms[FX_K_COUNT] = {0};
+  double prof_work[FX_K_COUNT] = {0};
 };
 
 namespace fx {
@@ -156,7 +158,7 @@ fx_status check_cell(const fx_cell* cell);
 fx_status check_kernel(const fx_kernel* k);
 
 // Bracket a launch with events when timing is on (no-ops otherwise).
-fx_status prof_begin(fx_ctx* ctx, hipStream_t st, int id, int* slot);
+fx_status prof_begin(fx_ctx* ctx, hipStream_t st, int id, double work, int* slot);
 fx_status prof_end(fx_ctx* ctx, hipStream_t st, int slot);
 
 inline size_t dtype_size(fx_dtype d) { return d == FX_C128 ? 16 : 8; }

@@ -174,7 +174,7 @@ fx_status zgemm(fx_ctx* ctx, Workspace* ws, hipStream_t st, int opa, int opb, in
   }
   dim3 grid((M + ZB - 1) / ZB, (N + ZB - 1) / ZB, nsplit * batch);
   int slot;
-  FX_TRY(prof_begin(ctx, st, opa ? FX_K_GEMM_CN : FX_K_GEMM_NN, &slot));
+  FX_TRY(prof_begin(ctx, st, opa ? FX_K_GEMM_CN : FX_K_GEMM_NN, 8.0 * M * N * (double)K * batch, &slot));
 #define FX_ZG(a, b)                                                                                                 \
   hipLaunchKernelGGL((k_zgemm<a, b>), grid, dim3(256), 0, st, M, N, K, (const z*)A, lda, sA, (const z*)B, ldb, sB, \
                      (z*)C, ldc, sC, alpha, beta, nsplit, kchunk, part)
@@ -190,7 +190,7 @@ fx_status zgemm(fx_ctx* ctx, Workspace* ws, hipStream_t st, int opa, int opb, in
   FX_LAUNCH_CHECK();
   FX_TRY(prof_end(ctx, st, slot));
   if (nsplit > 1) {
-    FX_TRY(prof_begin(ctx, st, FX_K_REDUCE, &slot));
+    FX_TRY(prof_begin(ctx, st, FX_K_REDUCE, 16.0 * M * N * batch * (nsplit + 2.0), &slot));
     hipLaunchKernelGGL(k_split_reduce, dim3(std::min<int64_t>(((int64_t)M * N * batch + 255) / 256, 4096)),
                        dim3(256), 0, st, M, N, nsplit, batch, (const z*)part, (z*)C, ldc, sC, alpha, beta);
     FX_LAUNCH_CHECK();

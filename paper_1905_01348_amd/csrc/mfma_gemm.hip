@@ -409,7 +409,7 @@ static fx_status apply_t(fx_ctx* ctx, Workspace* ws, fx_ace* a, AceSplit* sp, co
   FX_TRY(ws_get(ctx, ws, sizeof(S) == 4 ? "mf_phi_r32" : "mf_phi_r16", pb, &phr));
   const int64_t tp = (int64_t)R * sp->kc;
   int slot;
-  FX_TRY(prof_begin(ctx, st, FX_K_SPLIT, &slot));
+  FX_TRY(prof_begin(ctx, st, FX_K_SPLIT, (double)R * nr * (in_dtype == FX_C128 ? 16 : 8) + 2.0 * pb, &slot));
   if (in_dtype == FX_C128)
     hipLaunchKernelGGL((k_split_phi<S, double>), dim3((unsigned)std::min<int64_t>((tp + 255) / 256, 16384)),
                        dim3(256), 0, st, (const double*)phi, ld_phi, nr, R, sp->kc, (S*)php, (S*)phr);
@@ -425,7 +425,10 @@ static fx_status apply_t(fx_ctx* ctx, Workspace* ws, fx_ace* a, AceSplit* sp, co
     const int tiles_m = (n + TBM - 1) / TBM, tiles_n = (2 * R + TBN - 1) / TBN;
     const int tiles = tiles_m * tiles_n;
     const int64_t ksteps = sp->kc / BK;
-    int nsplit = (int)std::max<int64_t>(1, std::min<int64_t>((8 * ctx->n_cu + tiles - 1) / tiles, ksteps / 16));
+    // the split depends on the reduction length only, so a column's result
+    // does not depend on how many right-hand sides share the launch
+    (void)tiles;
+    int nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(32, ksteps / 16));
     if (const char* e = getenv("FX_ACE_NSPLIT")) nsplit = std::max(1, atoi(e));
     int64_t kchunk = (ksteps + nsplit - 1) / nsplit * BK;
     nsplit = (int)((sp->kc + kchunk - 1) / kchunk);
@@ -433,7 +436,7 @@ static fx_status apply_t(fx_ctx* ctx, Workspace* ws, fx_ace* a, AceSplit* sp, co
     FX_TRY(ws_get(ctx, ws, "mf_partial", sizeof(double) * (size_t)nsplit * n * 2 * R, &part));
     auto kern = k_tn_mfma<S, REFINE, true, 0>;
     FX_TRY(allow_lds_mfma(kern, lds));
-    FX_TRY(prof_begin(ctx, st, FX_K_GEMM_CN, &slot));
+    FX_TRY(prof_begin(ctx, st, FX_K_GEMM_CN, (REFINE ? 3.0 : 1.0) * 2.0 * n * 2.0 * R * (double)sp->kc, &slot));
     hipLaunchKernelGGL(kern, dim3((unsigned)(tiles * nsplit)), dim3(256), lds, st, n, 2 * R, (int)sp->kc,
                        (int)kchunk, (const S*)sp->col_p, (const S*)sp->col_r, sp->kc, (const S*)php, (const S*)phr,
                        sp->kc, (double*)part, (void*)nullptr, (int64_t)0, 0, 0.0, tiles_m, tiles_n);
@@ -445,7 +448,7 @@ static fx_status apply_t(fx_ctx* ctx, Workspace* ws, fx_ace* a, AceSplit* sp, co
     FX_TRY(ws_get(ctx, ws, sizeof(S) == 4 ? "mf_bnn_p32" : "mf_bnn_p16", bb, &bp));
     FX_TRY(ws_get(ctx, ws, sizeof(S) == 4 ? "mf_bnn_r32" : "mf_bnn_r16", bb, &br));
     const int64_t tr = (int64_t)R * (sp->kn / 2);
-    FX_TRY(prof_begin(ctx, st, FX_K_REDUCE, &slot));
+    FX_TRY(prof_begin(ctx, st, FX_K_REDUCE, 8.0 * nsplit * n * 2.0 * R + 2.0 * bb, &slot));
     hipLaunchKernelGGL((k_reduce_cn<S>), dim3((unsigned)std::min<int64_t>((tr + 255) / 256, 16384)), dim3(256), 0, st,
                        (const double*)part, nsplit, n, R, sp->kn, (S*)bp, (S*)br);
     FX_LAUNCH_CHECK();
@@ -454,7 +457,7 @@ static fx_status apply_t(fx_ctx* ctx, Workspace* ws, fx_ace* a, AceSplit* sp, co
     const int tm2 = (int)((nr + TBM - 1) / TBM), tn2 = (2 * R + TBN - 1) / TBN;
     auto kern2 = k_tn_mfma<S, REFINE, false, 1>;
     FX_TRY(allow_lds_mfma(kern2, lds));
-    FX_TRY(prof_begin(ctx, st, FX_K_GEMM_NN, &slot));
+    FX_TRY(prof_begin(ctx, st, FX_K_GEMM_NN, (REFINE ? 3.0 : 1.0) * 2.0 * (double)nr * 2.0 * R * (double)sp->kn, &slot));
     hipLaunchKernelGGL(kern2, dim3((unsigned)(tm2 * tn2)), dim3(256), lds, st, (int)nr, 2 * R, (int)sp->kn,
                        (int)sp->kn, (const S*)sp->row_p, (const S*)sp->row_r, sp->kn, (const S*)bp, (const S*)br,
                        sp->kn, (double*)nullptr, out, ld_out, out_dtype == FX_C64 ? 1 : 0, 1.0, tm2, tn2);

@@ -99,11 +99,12 @@ static fx_status take_event(fx_ctx* ctx, hipEvent_t* e) {
   return FX_OK;
 }
 
-fx_status prof_begin(fx_ctx* ctx, hipStream_t st, int id, int* slot) {
+fx_status prof_begin(fx_ctx* ctx, hipStream_t st, int id, double work, int* slot) {
   *slot = -1;
   if (!ctx || !ctx->prof) return FX_OK;
   ProfRec r;
   r.id = id;
+  r.work = work;
   FX_TRY(take_event(ctx, &r.a));
   FX_TRY(take_event(ctx, &r.b));
   FX_HIP(hipEventRecord(r.a, st));
@@ -126,6 +127,7 @@ static fx_status prof_drain(fx_ctx* ctx) {
     if (r.id >= 0 && r.id < FX_K_COUNT) {
       ctx->prof_launches[r.id] += 1;
       ctx->prof_ms[r.id] += ms;
+      ctx->prof_work[r.id] += r.work;
     }
     ctx->ev_pool.push_back(r.a);
     ctx->ev_pool.push_back(r.b);
@@ -375,12 +377,13 @@ fx_status fx_prof_enable(fx_ctx* ctx, int on) {
   for (int i = 0; i < FX_K_COUNT; ++i) {
     ctx->prof_launches[i] = 0;
     ctx->prof_ms[i] = 0.0;
+    ctx->prof_work[i] = 0.0;
   }
   ctx->prof = on != 0;
   return FX_OK;
 }
 
-fx_status fx_prof_read(fx_ctx* ctx, int id, int64_t* launches, double* total_ms) {
+fx_status fx_prof_read(fx_ctx* ctx, int id, int64_t* launches, double* total_ms, double* work) {
   clear_error();
   if (!ctx) FX_FAIL(FX_ERR_INVALID, "ctx is NULL");
   if (id < 0 || id >= FX_K_COUNT) FX_FAIL(FX_ERR_INVALID, "kernel id %d out of range", id);
@@ -388,6 +391,7 @@ fx_status fx_prof_read(fx_ctx* ctx, int id, int64_t* launches, double* total_ms)
   FX_TRY(prof_drain(ctx));
   if (launches) *launches = ctx->prof_launches[id];
   if (total_ms) *total_ms = ctx->prof_ms[id];
+  if (work) *work = ctx->prof_work[id];
   return FX_OK;
 }
 

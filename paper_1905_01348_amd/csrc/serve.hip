@@ -1,0 +1,429 @@
+// fx_serve: continuous batching of V_X and K_ACE requests over orbitals kept
+// resident on the device.
+//
+// One host loop replays the arrivals.  Waiting requests of the same
+// trajectory and operation are merged into one launch (their target orbitals
+// gathered into one block) up to max_batch_pairs pairs; a merged batch runs
+// on a free slot, each slot owning a stream and a workspace, so batches that
+// are in flight overlap on the device.  A slot's completion event stamps the
+// latency of every request in it.  Admission keeps resident orbitals, ACE
+// factors and slot workspaces inside the HBM budget: a batch whose workspace
+// does not fit waits for a slot to drain, and is refused (FX_ERR_OOM) only if
+// it cannot fit with every slot idle.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <deque>
+#include <map>
+#include <thread>
+#include <vector>
+
+#include "ace.hpp"
+#include "vx.hpp"
+
+using namespace fx;
+
+namespace {
+
+struct Traj {
+  fx_cell cell;
+  fx_kernel kern;
+  int n = 0;
+  int64_t nr = 0;
+  fx_dtype dtype = FX_C64;
+  fx_prec vx_prec = FX_PREC_FP32_ACC64, ace_prec = FX_PREC_ACE_FP32R;
+  void* psi = nullptr;  // owned, ld nr
+  size_t psi_bytes = 0;
+  fx_ace* ace = nullptr;
+};
+
+struct Slot {
+  hipStream_t st = nullptr;
+  hipEvent_t done = nullptr;
+  Workspace ws;
+  bool busy = false;
+  std::vector<int> reqs;
+  double t_launch = 0;
+};
+
+// gather columns [first, first+count) of each request's trajectory into a
+// contiguous block, or scatter a contiguous block back to request outputs
+__global__ void k_copy_cols(const char* __restrict__ src, int64_t ld_src_bytes, char* __restrict__ dst,
+                            int64_t ld_dst_bytes, int64_t col_bytes, int ncols) {
+  const int c = blockIdx.y;
+  if (c >= ncols) return;
+  const uint4* s = reinterpret_cast<const uint4*>(src + c * ld_src_bytes);
+  uint4* d = reinterpret_cast<uint4*>(dst + c * ld_dst_bytes);
+  const int64_t nv = col_bytes / 16;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nv; i += (int64_t)gridDim.x * blockDim.x)
+    d[i] = s[i];
+}
+
+fx_status copy_cols(const void* src, int64_t ld_src_bytes, void* dst, int64_t ld_dst_bytes, int64_t col_bytes,
+                    int ncols, hipStream_t st) {
+  if (col_bytes % 16 || ld_src_bytes % 16 || ld_dst_bytes % 16 || ((uintptr_t)src % 16) || ((uintptr_t)dst % 16)) {
+    for (int c = 0; c < ncols; ++c)
+      FX_HIP(hipMemcpyAsync((char*)dst + c * ld_dst_bytes, (const char*)src + c * ld_src_bytes, col_bytes,
+                            hipMemcpyDeviceToDevice, st));
+    return FX_OK;
+  }
+  const int64_t nv = col_bytes / 16;
+  dim3 grid((unsigned)std::min<int64_t>((nv + 255) / 256, 1024), (unsigned)ncols);
+  hipLaunchKernelGGL(k_copy_cols, grid, dim3(256), 0, st, (const char*)src, ld_src_bytes, (char*)dst, ld_dst_bytes,
+                     col_bytes, ncols);
+  FX_LAUNCH_CHECK();
+  return FX_OK;
+}
+
+}  // namespace
+
+struct fx_server {
+  fx_ctx* ctx = nullptr;
+  fx_serve_cfg cfg;
+  size_t saved_budget = 0;  // the context budget before the server capped it
+  std::map<int, Traj> trajs;
+  std::vector<Slot> slots;
+};
+
+static double now_s() {
+  using namespace std::chrono;
+  return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+static double percentile(std::vector<double> v, double q) {
+  if (v.empty()) return 0.0;
+  std::sort(v.begin(), v.end());
+  // nearest-rank
+  size_t k = (size_t)std::ceil(q * v.size());
+  if (k < 1) k = 1;
+  if (k > v.size()) k = v.size();
+  return v[k - 1];
+}
+
+extern "C" {
+
+fx_status fx_serve_create(fx_ctx* ctx, const fx_serve_cfg* cfg, fx_server** srv) {
+  clear_error();
+  if (!ctx || !cfg || !srv) FX_FAIL(FX_ERR_INVALID, "NULL argument");
+  if (cfg->max_slots <= 0 || cfg->max_slots > 64) FX_FAIL(FX_ERR_INVALID, "max_slots = %d not in [1, 64]", cfg->max_slots);
+  if (cfg->n_streams <= 0 || cfg->n_streams > cfg->max_slots)
+    FX_FAIL(FX_ERR_INVALID, "n_streams = %d not in [1, max_slots]", cfg->n_streams);
+  if (cfg->max_batch_pairs <= 0) FX_FAIL(FX_ERR_INVALID, "max_batch_pairs must be positive");
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  FX_HIP(hipSetDevice(ctx->device));
+  fx_server* s = new fx_server();
+  s->ctx = ctx;
+  s->cfg = *cfg;
+  s->saved_budget = ctx->budget;
+  if (cfg->hbm_budget_bytes && cfg->hbm_budget_bytes < ctx->budget) ctx->budget = cfg->hbm_budget_bytes;
+  s->slots.resize(cfg->max_slots);
+  std::vector<hipStream_t> streams(cfg->n_streams);
+  for (auto& st : streams) {
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+      delete s;
+      FX_FAIL(FX_ERR_DEVICE, "stream creation failed");
+    }
+  }
+  for (int i = 0; i < cfg->max_slots; ++i) {
+    s->slots[i].st = streams[i % cfg->n_streams];
+    if (hipEventCreateWithFlags(&s->slots[i].done, hipEventDisableTiming) != hipSuccess) {
+      delete s;
+      FX_FAIL(FX_ERR_DEVICE, "event creation failed");
+    }
+  }
+  *srv = s;
+  return FX_OK;
+}
+
+fx_status fx_serve_register(fx_server* srv, int32_t traj, const fx_cell* cell, const fx_kernel* kernel,
+                            const void* psi, int32_t n, int64_t ld, fx_dtype dtype, fx_prec vx_prec,
+                            fx_prec ace_prec) {
+  clear_error();
+  if (!srv) FX_FAIL(FX_ERR_INVALID, "srv is NULL");
+  fx_ctx* ctx = srv->ctx;
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  FX_HIP(hipSetDevice(ctx->device));
+  FX_TRY(check_cell(cell));
+  FX_TRY(check_kernel(kernel));
+  if (srv->trajs.count(traj)) FX_FAIL(FX_ERR_INVALID, "trajectory %d already registered", traj);
+  if (!psi || n <= 0) FX_FAIL(FX_ERR_INVALID, "psi NULL or n <= 0");
+  const int64_t nr = (int64_t)cell->n[0] * cell->n[1] * cell->n[2];
+  if (ld < nr) FX_FAIL(FX_ERR_INVALID, "ld < N_r");
+  if (dtype != FX_C128 && dtype != FX_C64) FX_FAIL(FX_ERR_UNSUPPORTED, "unknown dtype");
+  Traj t;
+  t.cell = *cell;
+  t.kern = *kernel;
+  t.n = n;
+  t.nr = nr;
+  t.dtype = dtype;
+  t.vx_prec = vx_prec;
+  t.ace_prec = ace_prec;
+  t.psi_bytes = dtype_size(dtype) * (size_t)nr * n;
+  FX_TRY(ctx_alloc(ctx, t.psi_bytes, &t.psi));
+  const int64_t cb = (int64_t)dtype_size(dtype) * nr;
+  fx_status s = copy_cols(psi, ld * (int64_t)dtype_size(dtype), t.psi, cb, cb, n, nullptr);
+  if (s == FX_OK) {
+    s = ace_build_impl(ctx, &ctx->ws, cell, kernel, t.psi, n, nr, dtype, vx_prec, ace_prec, nullptr, &t.ace,
+                       nullptr);
+  }
+  if (s != FX_OK) {
+    ctx_free(ctx, t.psi, t.psi_bytes);
+    return s;
+  }
+  // the build's scratch is not needed while serving
+  FX_HIP(hipDeviceSynchronize());
+  ws_release(ctx, &ctx->ws);
+  srv->trajs[traj] = t;
+  return FX_OK;
+}
+
+fx_status fx_serve(fx_server* srv, const fx_request* reqs, int32_t n_reqs, fx_status* per_status,
+                   double* per_lat_ms, fx_serve_report* report) {
+  clear_error();
+  if (!srv) FX_FAIL(FX_ERR_INVALID, "srv is NULL");
+  if (n_reqs < 0 || (n_reqs > 0 && !reqs)) FX_FAIL(FX_ERR_INVALID, "bad request array");
+  fx_ctx* ctx = srv->ctx;
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  FX_HIP(hipSetDevice(ctx->device));
+  const int nq = n_reqs;
+  std::vector<fx_status> status(nq, FX_ERR_CANCELLED);
+  std::vector<double> lat(nq, -1.0), t_done(nq, 0.0);
+  std::vector<int> order(nq);
+  for (int i = 0; i < nq; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int a, int b) { return reqs[a].t_arrival_s < reqs[b].t_arrival_s; });
+  // validation
+  std::vector<char> valid(nq, 1);
+  for (int i = 0; i < nq; ++i) {
+    const fx_request& r = reqs[i];
+    auto it = srv->trajs.find(r.traj);
+    if (it == srv->trajs.end() || (r.op != 0 && r.op != 1) || r.count <= 0 || r.first < 0 ||
+        r.first + r.count > it->second.n || !r.out || r.ld_out < it->second.nr) {
+      valid[i] = 0;
+      status[i] = FX_ERR_INVALID;
+    }
+  }
+  std::deque<int> waiting;
+  size_t next = 0;
+  int64_t done_count = 0, rejected = 0, batches = 0;
+  double pairs_done = 0.0, busy_time = 0.0, busy_since = -1.0;
+  int nbusy = 0;
+  const double t0 = now_s();
+  size_t hbm_peak = ctx->in_use;
+  fx_status fatal = FX_OK;
+
+  auto finish_slot = [&](Slot& sl, double t) {
+    for (int i : sl.reqs) {
+      t_done[i] = t;
+      lat[i] = 1e3 * (t - (t0 + reqs[i].t_arrival_s));
+      status[i] = FX_OK;
+      ++done_count;
+    }
+    sl.reqs.clear();
+    sl.busy = false;
+    if (--nbusy == 0 && busy_since >= 0) {
+      busy_time += t - busy_since;
+      busy_since = -1.0;
+    }
+  };
+
+  // launch one merged batch on slot `sl`; returns FX_ERR_OOM if its workspace
+  // does not fit right now
+  auto launch = [&](Slot& sl, const std::vector<int>& batch) -> fx_status {
+    const fx_request& r0 = reqs[batch[0]];
+    Traj& t = srv->trajs[r0.traj];
+    const size_t esz = dtype_size(t.dtype);
+    const int64_t cb = (int64_t)esz * t.nr;
+    int total = 0;
+    for (int i : batch) total += reqs[i].count;
+    const void* phi = nullptr;
+    void* out = nullptr;
+    const bool single = batch.size() == 1;
+    if (single) {
+      phi = (const char*)t.psi + (int64_t)r0.first * cb;
+      out = r0.out;
+    } else {
+      void *g = nullptr, *o = nullptr;
+      FX_TRY(ws_get(ctx, &sl.ws, "srv_gather", (size_t)cb * total, &g));
+      FX_TRY(ws_get(ctx, &sl.ws, "srv_out", (size_t)cb * total, &o));
+      int off = 0;
+      for (int i : batch) {
+        FX_TRY(copy_cols((const char*)t.psi + (int64_t)reqs[i].first * cb, cb, (char*)g + (int64_t)off * cb, cb, cb,
+                         reqs[i].count, sl.st));
+        off += reqs[i].count;
+      }
+      phi = g;
+      out = o;
+    }
+    const int64_t ld_out = single ? r0.ld_out : t.nr;
+    if (r0.op == 0) {
+      VxArgs va;
+      va.cell = &t.cell;
+      va.kern = &t.kern;
+      va.psi = t.psi;
+      va.n_psi = t.n;
+      va.ld_psi = t.nr;
+      va.phi = phi;
+      va.n_phi = total;
+      va.ld_phi = t.nr;
+      va.out = out;
+      va.ld_out = ld_out;
+      va.in_dtype = t.dtype;
+      va.out_dtype = t.dtype;
+      va.prec = t.vx_prec;
+      FX_TRY(vx_apply(ctx, &sl.ws, va, sl.st, nullptr));
+      pairs_done += (double)t.n * total;
+    } else {
+      FX_TRY(ace_apply_impl(ctx, &sl.ws, t.ace, phi, total, t.nr, out, ld_out, t.dtype, t.dtype, t.ace_prec, sl.st));
+      pairs_done += (double)t.n * total;
+    }
+    if (!single) {
+      int off = 0;
+      for (int i : batch) {
+        FX_TRY(copy_cols((char*)out + (int64_t)off * cb, cb, reqs[i].out, reqs[i].ld_out * (int64_t)esz, cb,
+                         reqs[i].count, sl.st));
+        off += reqs[i].count;
+      }
+    }
+    FX_HIP(hipEventRecord(sl.done, sl.st));
+    return FX_OK;
+  };
+
+  while (done_count + rejected < (int64_t)std::count(valid.begin(), valid.end(), 1) || !waiting.empty() || nbusy) {
+    const double t = now_s() - t0;
+    // arrivals
+    while (next < (size_t)nq && reqs[order[next]].t_arrival_s <= t) {
+      if (valid[order[next]]) waiting.push_back(order[next]);
+      ++next;
+    }
+    // completions
+    for (auto& sl : srv->slots) {
+      if (!sl.busy) continue;
+      hipError_t q = hipEventQuery(sl.done);
+      if (q == hipSuccess) {
+        finish_slot(sl, now_s());
+      } else if (q != hipErrorNotReady) {
+        set_error("device error while serving: %s", hipGetErrorString(q));
+        fatal = FX_ERR_DEVICE;
+        break;
+      }
+    }
+    if (fatal != FX_OK) break;
+    // dispatch
+    bool progressed = false;
+    for (auto& sl : srv->slots) {
+      if (sl.busy || waiting.empty()) continue;
+      // merge: oldest request first, then same trajectory and op in arrival order
+      const int head = waiting.front();
+      const fx_request& rh = reqs[head];
+      const Traj& th = srv->trajs[rh.traj];
+      std::vector<int> batch{head};
+      int64_t pairs = (int64_t)th.n * rh.count;
+      for (size_t w = 1; w < waiting.size(); ++w) {
+        const fx_request& rw = reqs[waiting[w]];
+        if (rw.traj != rh.traj || rw.op != rh.op) continue;
+        const int64_t p = (int64_t)th.n * rw.count;
+        if (pairs + p > srv->cfg.max_batch_pairs) break;
+        batch.push_back(waiting[w]);
+        pairs += p;
+      }
+      fx_status s = launch(sl, batch);
+      if (s == FX_ERR_OOM) {
+        if (nbusy > 0) break;  // wait for memory to drain
+        for (int i : batch) {
+          status[i] = FX_ERR_OOM;
+          ++rejected;
+        }
+      } else if (s != FX_OK) {
+        fatal = s;
+        break;
+      } else {
+        sl.busy = true;
+        sl.reqs = batch;
+        if (nbusy++ == 0) busy_since = now_s();
+        ++batches;
+        progressed = true;
+      }
+      // drop the batch from the waiting queue
+      std::deque<int> rest;
+      for (int w : waiting)
+        if (std::find(batch.begin(), batch.end(), w) == batch.end()) rest.push_back(w);
+      waiting.swap(rest);
+      hbm_peak = std::max(hbm_peak, ctx->in_use);
+    }
+    if (fatal != FX_OK) break;
+    if (!progressed) {
+      // nothing to launch: sleep until the next arrival or a short poll interval
+      double wait = 2e-4;
+      if (next < (size_t)nq && waiting.empty() && nbusy == 0) wait = std::max(0.0, reqs[order[next]].t_arrival_s - t);
+      std::this_thread::sleep_for(std::chrono::duration<double>(std::min(wait, 5e-5)));
+    }
+    if (next >= (size_t)nq && waiting.empty() && nbusy == 0) break;
+  }
+  if (fatal != FX_OK) {
+    (void)hipDeviceSynchronize();
+    for (auto& sl : srv->slots) {
+      sl.busy = false;
+      sl.reqs.clear();
+    }
+    return fatal;
+  }
+  const double wall = now_s() - t0;
+  std::vector<double> ok;
+  for (int i = 0; i < nq; ++i) {
+    if (per_status) per_status[i] = status[i];
+    if (per_lat_ms) per_lat_ms[i] = lat[i];
+    if (status[i] == FX_OK) ok.push_back(lat[i]);
+  }
+  if (report) {
+    fx_serve_report& R = *report;
+    R.p50_ms = percentile(ok, 0.50);
+    R.p99_ms = percentile(ok, 0.99);
+    double sum = 0, mx = 0;
+    for (double v : ok) {
+      sum += v;
+      mx = std::max(mx, v);
+    }
+    R.mean_ms = ok.empty() ? 0.0 : sum / ok.size();
+    R.max_ms = mx;
+    R.wall_s = wall;
+    R.req_per_s = wall > 0 ? ok.size() / wall : 0.0;
+    R.pairs_per_s = wall > 0 ? pairs_done / wall : 0.0;
+    R.busy_frac = wall > 0 ? busy_time / wall : 0.0;
+    R.n_done = (int64_t)ok.size();
+    R.n_rejected = rejected;
+    R.n_batches = batches;
+    R.hbm_peak_bytes = hbm_peak;
+  }
+  return FX_OK;
+}
+
+fx_status fx_serve_destroy(fx_server* srv) {
+  clear_error();
+  if (!srv) FX_FAIL(FX_ERR_INVALID, "srv is NULL");
+  fx_ctx* ctx = srv->ctx;
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  FX_HIP(hipSetDevice(ctx->device));
+  FX_HIP(hipDeviceSynchronize());
+  for (auto& kv : srv->trajs) {
+    Traj& t = kv.second;
+    if (t.ace) {
+      for (auto& b : t.ace->owned) ctx_free(ctx, b.first, b.second);
+      ws_release(ctx, &t.ace->ws);
+      delete t.ace;
+    }
+    ctx_free(ctx, t.psi, t.psi_bytes);
+  }
+  std::vector<hipStream_t> streams;
+  for (auto& sl : srv->slots) {
+    ws_release(ctx, &sl.ws);
+    if (sl.done) (void)hipEventDestroy(sl.done);
+    if (std::find(streams.begin(), streams.end(), sl.st) == streams.end()) streams.push_back(sl.st);
+  }
+  for (auto st : streams) (void)hipStreamDestroy(st);
+  ctx->budget = srv->saved_budget;
+  delete srv;
+  return FX_OK;
+}
+
+}  // extern "C"

@@ -203,7 +203,7 @@ static fx_status allow_lds(K kernel, size_t bytes) {
 }
 
 static size_t work_cap_bytes(fx_ctx* ctx) {
-  size_t cap = (size_t)2048 << 20;
+  size_t cap = (size_t)4096 << 20;
   if (const char* e = getenv("FX_WORK_MB")) cap = (size_t)atol(e) << 20;
   if (cap > ctx->budget / 4) cap = ctx->budget / 4;
   return cap;
@@ -254,10 +254,17 @@ static fx_status run_batches(fx_ctx* ctx, Workspace* ws, const VxArgs& a, const 
   const int64_t nr = (int64_t)g.nx * g.ny * g.nz;
   const size_t pair_bytes = (size_t)nr * sizeof(cpx<T>);
   size_t cap = a.work_cap ? a.work_cap : work_cap_bytes(ctx);
-  int64_t pairs_cap = (int64_t)std::max<size_t>(1, cap / pair_bytes);
-  int nk = (int)std::min<int64_t>(a.n_phi, pairs_cap);
-  int nj = (int)std::min<int64_t>(a.n_psi, std::max<int64_t>(1, pairs_cap / nk));
+  const int64_t pairs_cap = (int64_t)std::max<size_t>(1, cap / pair_bytes);
+  // Batch shape: up to 16 orbitals per batch first (the plane-inverse pass
+  // reads and writes its partial sums once per batch), then as many targets
+  // as fit, balanced over the target blocks, then any leftover capacity
+  // back to orbitals.
+  int nj = (int)std::min<int64_t>(a.n_psi, std::min<int64_t>(16, pairs_cap));
   if (a.force_nj > 0) nj = std::min(nj, a.force_nj);
+  const int64_t nk_max = std::max<int64_t>(1, pairs_cap / nj);
+  const int64_t kblocks = (a.n_phi + nk_max - 1) / nk_max;
+  const int nk = (int)((a.n_phi + kblocks - 1) / kblocks);
+  if (a.force_nj <= 0) nj = (int)std::min<int64_t>(a.n_psi, std::max<int64_t>(nj, pairs_cap / nk));
   void* work = nullptr;
   FX_TRY(ws_get(ctx, ws, "vx_work", (size_t)nk * nj * pair_bytes, &work));
   const bool out_c64 = a.out_dtype == FX_C64;
@@ -293,18 +300,23 @@ static fx_status run_batches(fx_ctx* ctx, Workspace* ws, const VxArgs& a, const 
       const int jb = std::min(nj, a.n_psi - j0);
       const int first = j0 == 0, last = j0 + jb >= a.n_psi;
       const int npairs = kb * jb;
+      // algorithmic bytes of each pass (see the pass descriptions)
+      const double vol = (double)npairs * nr * sizeof(cpx<T>);
+      const double accb = (double)kb * nr *
+                          ((first ? 0.0 : (double)sizeof(cpx<A>)) +
+                           (last ? (out_c64 ? 8.0 : 16.0) : (double)sizeof(cpx<A>)));
       int slot;
-      FX_TRY(prof_begin(ctx, st, FX_K_VX_PLANE_FWD, &slot));
+      FX_TRY(prof_begin(ctx, st, FX_K_VX_PLANE_FWD, 3.0 * vol, &slot));
       hipLaunchKernelGGL((k_pass_a<T>), dim3((unsigned)(npairs * g.nz)), dim3(nthr_a), lds_plane, st, psi, ld_psi,
                          phi, ld_phi, reinterpret_cast<cpx<T>*>(work), j0, jb, k0, g, twx, twy);
       FX_LAUNCH_CHECK();
       FX_TRY(prof_end(ctx, st, slot));
-      FX_TRY(prof_begin(ctx, st, FX_K_VX_PENCIL_Z, &slot));
+      FX_TRY(prof_begin(ctx, st, FX_K_VX_PENCIL_Z, 2.0 * vol, &slot));
       hipLaunchKernelGGL((k_pass_b<T>), dim3((unsigned)(npairs * g.ny)), dim3(nthr_b), lds_xz, st,
                          reinterpret_cast<cpx<T>*>(work), g, twz, kf, tb->fold[0], tb->fold[1], tb->fold[2]);
       FX_LAUNCH_CHECK();
       FX_TRY(prof_end(ctx, st, slot));
-      FX_TRY(prof_begin(ctx, st, FX_K_VX_PLANE_INV, &slot));
+      FX_TRY(prof_begin(ctx, st, FX_K_VX_PLANE_INV, 2.0 * vol + accb, &slot));
       FX_TRY((launch_pass_c<T, A>(g, 0, dim3((unsigned)(kb * g.nz)), lds_plane, st, psi, ld_psi,
                                   reinterpret_cast<const cpx<T>*>(work), j0, jb, k0, acc, ld_acc, first, a.out,
                                   a.ld_out, out_c64 ? 1 : 0, last, twx, twy)));

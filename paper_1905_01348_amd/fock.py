@@ -85,7 +85,8 @@ _SIGS = {
                            C.POINTER(C.c_double), C.POINTER(FxServeReport)]),
     "fx_serve_destroy": (C.c_int, [C.c_void_p]),
     "fx_prof_enable": (C.c_int, [C.c_void_p, C.c_int]),
-    "fx_prof_read": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
+    "fx_prof_read": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double),
+                               C.POINTER(C.c_double)]),
     "fx_debug_host_pair": (C.c_int, [C.POINTER(FxCell), C.POINTER(FxKernel), C.c_int, C.c_void_p, C.c_void_p,
                                       C.c_void_p]),
 }
@@ -210,9 +211,10 @@ class Context:
         _check(load().fx_prof_enable(self.h, 1 if on else 0))
 
     def prof_read(self, kid):
-        n, ms = C.c_int64(), C.c_double()
-        _check(load().fx_prof_read(self.h, int(kid), C.byref(n), C.byref(ms)))
-        return n.value, ms.value
+        """(launches, total_ms, algorithmic work: bytes or executed flops) of one kernel id."""
+        n, ms, wk = C.c_int64(), C.c_double(), C.c_double()
+        _check(load().fx_prof_read(self.h, int(kid), C.byref(n), C.byref(ms), C.byref(wk)))
+        return n.value, ms.value, wk.value
 
     # -- V_X ------------------------------------------------------------------
     def apply_vx(self, psi, phi=None, *, n, L, kernel="hse", omega=0.106, scale=1.0, prec="fp32acc64",
@@ -290,6 +292,63 @@ class Ace:
     def __del__(self):
         try:
             self.free()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching server over resident trajectories (fx_serve_*)."""
+
+    def __init__(self, ctx, max_slots=8, n_streams=4, max_batch_pairs=1 << 16, hbm_budget_bytes=0):
+        cfg = FxServeCfg()
+        cfg.max_slots, cfg.n_streams, cfg.max_batch_pairs = int(max_slots), int(n_streams), int(max_batch_pairs)
+        cfg.hbm_budget_bytes = int(hbm_budget_bytes)
+        h = C.c_void_p()
+        _check(load().fx_serve_create(ctx.h, C.byref(cfg), C.byref(h)))
+        self.ctx, self.h = ctx, h
+        self.trajs = {}
+
+    def register(self, traj, psi, *, n, L, kernel="hse", omega=0.106, scale=1.0, vx_prec="fp32acc64",
+                 ace_prec="ace_fp32r"):
+        cell = make_cell(n, L)
+        nr = cell.n[0] * cell.n[1] * cell.n[2]
+        kern = make_kernel(kernel, omega, scale)
+        pp, npsi, ldp = _cols(psi, nr)
+        _check(load().fx_serve_register(self.h, int(traj), C.byref(cell), C.byref(kern), pp, npsi, ldp,
+                                        _dtype_code(psi), PREC[vx_prec], PREC[ace_prec]))
+        self.trajs[traj] = (nr, npsi, psi.dtype)
+
+    def serve(self, requests):
+        """requests: list of dicts(traj, op, first, count, t, out).  Returns (status, latency_ms, report dict)."""
+        n = len(requests)
+        arr = (FxRequest * max(n, 1))()
+        for i, r in enumerate(requests):
+            o = r["out"]
+            if o is None:
+                op_, ld = None, 0
+            elif r["traj"] in self.trajs:
+                op_, _, ld = _cols(o, self.trajs[r["traj"]][0])
+            else:  # unknown trajectory: the library reports it per request
+                op_, ld = o.data_ptr(), o.stride(0)
+            arr[i].traj, arr[i].op, arr[i].first, arr[i].count = r["traj"], r["op"], r["first"], r["count"]
+            arr[i].t_arrival_s = float(r["t"])
+            arr[i].out = op_
+            arr[i].ld_out = ld
+        st = (C.c_int * max(n, 1))()
+        lat = (C.c_double * max(n, 1))()
+        rep = FxServeReport()
+        _check(load().fx_serve(self.h, arr, n, st, lat, C.byref(rep)))
+        report = {f: getattr(rep, f) for f, _ in FxServeReport._fields_}
+        return [st[i] for i in range(n)], [lat[i] for i in range(n)], report
+
+    def close(self):
+        if self.h:
+            _check(load().fx_serve_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
         except Exception:
             pass
 

@@ -36,7 +36,7 @@ def _case(n3, L3, N, kind, seed, R):
 
 
 CASES = [
-    ((6, 4, 5), (4.0, 3.0, 3.5), 5, "hse", 3),
+    ((6, 4, 3), (4.0, 3.0, 3.5), 5, "hse", 3),
     ((8, 8, 8), (5.0, 5.0, 5.0), 37, "coulomb", 65),
     ((12, 9, 8), (6.0, 4.5, 4.0), 70, "hse", 1),
     ((16, 16, 16), (7.0, 7.0, 7.0), 130, "hse", 131),

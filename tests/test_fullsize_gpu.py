@@ -1,0 +1,102 @@
+"""Full-size parity: one GPU's share of the 512-atom cell (96^3, 1024 orbitals).
+
+The FP64 oracle cannot redo the whole workload in test time (a full V_X
+column is 1024 pair FFTs of 96^3), so the checks are: sampled output columns
+recomputed by the oracle one by one, properties that hold at any size
+(Hermiticity and sign of the projected operator), and the FP32 forms against
+the GPU FP64 form on every column.  Launch configuration as in bench.py.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_util import col_err, host, say, workers
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def share():
+    import torch
+
+    w = synth.workload("cfg2")
+    say("generating the 96^3 share (1024 orbitals)")
+    psi = synth.make_orbitals(w["seed"], w["n"], w["L"], w["N"], dtype=np.complex64)
+    P = torch.from_numpy(psi).to("cuda:0")
+    return w, psi, P
+
+
+@pytest.mark.timeout(900)
+def test_vx_share_fullsize(share):
+    import torch
+    from paper_1905_01348_amd import Context
+
+    w, psi, P = share
+    n, L, Nt = w["n"], w["L"], w["n_targets"]
+    ctx = Context(0)
+    out = ctx.apply_vx(P, P[:Nt], n=n, L=L, kernel="hse", omega=0.106, prec="fp32acc64")
+    torch.cuda.synchronize()
+    o = host(out)
+    k = 5
+    say("oracle column", k)
+    ref = oracle.apply_vx(psi, psi[k:k + 1], n, L, "hse", 0.106, workers=workers())
+    err = col_err(o[k:k + 1], ref)
+    say("fp32acc64 column err", err)
+    assert err <= 1e-5
+    # projected operator on the 32 targets: Hermitian, negative diagonal
+    T = psi[:Nt].reshape(Nt, -1).astype(np.complex128)
+    Mb = T.conj() @ o.reshape(Nt, -1).T
+    assert np.abs(Mb - Mb.conj().T).max() <= 1e-6 * np.abs(Mb).max()
+    assert np.all(np.diag(Mb).real < 0)
+    # FP64 form on every column
+    P64 = P.to(torch.complex128)
+    out64 = ctx.apply_vx(P64, P64[:Nt], n=n, L=L, kernel="hse", omega=0.106, prec="fp64")
+    torch.cuda.synchronize()
+    e64 = col_err(o, host(out64))
+    say("fp32acc64 vs fp64 (all columns)", e64)
+    assert e64 <= 1e-5
+    assert col_err(host(out64[k:k + 1]), ref) <= 1e-10
+    del P64, out64
+    ctx.close()
+
+
+@pytest.mark.timeout(1200)
+def test_ace_fullsize(share):
+    """ACE at N = R = 1024 on 96^3: K_ACE psi_k = V_X psi_k (oracle column), precision forms vs FP64."""
+    import torch
+    from paper_1905_01348_amd import Context
+
+    w, psi, P = share
+    n, L, N = w["n"], w["L"], w["N"]
+    ctx = Context(0)
+    say("building ACE (1024^2 pairs)")
+    ace = ctx.build_ace(P, n=n, L=L, kernel="hse", omega=0.106, vx_prec="fp32acc64", ace_prec="ace_fp64")
+    k = 5
+    ref = oracle.apply_vx(psi, psi[k:k + 1], n, L, "hse", 0.106, workers=workers())
+    for prec, tol in (("ace_fp64", 1e-5), ("ace_fp32r", 1e-5), ("ace_bf16r", 1e-4)):
+        y = ace.apply(P[k:k + 1], prec=prec, out_dtype=torch.complex128)
+        torch.cuda.synchronize()
+        err = col_err(host(y), ref)
+        say("K_ACE psi_k vs oracle V_X psi_k", prec, err)
+        assert err <= tol
+    say("right-hand sides (seed 3)")
+    phi = torch.from_numpy(synth.make_orbitals(3, n, L, N, dtype=np.complex64)).to("cuda:0")
+    y64 = ace.apply(phi, prec="ace_fp64", out_dtype=torch.complex128)
+    r64 = host(y64)
+    del y64
+    for prec, tol in (("ace_fp32r", 1e-5), ("ace_bf16r", 1e-4)):
+        y = ace.apply(phi, prec=prec, out_dtype=torch.complex64)
+        torch.cuda.synchronize()
+        err = col_err(host(y), r64)
+        say(prec, "vs fp64 on 1024 columns", err)
+        assert err <= tol
+        del y
+    # K_ACE Hermitian on a sample of the right-hand sides
+    S = phi[:16].reshape(16, -1).to(torch.complex128)
+    KS = torch.from_numpy(r64[:16].reshape(16, -1)).to("cuda:0")
+    G = (S.conj() @ KS.T).cpu().numpy()
+    assert np.abs(G - G.conj().T).max() <= 1e-8 * np.abs(G).max()
+    assert np.all(np.diag(G).real <= 0)
+    ace.free()
+    ctx.close()

@@ -189,14 +189,20 @@ def test_error_paths(ctx, cfg0):
     with pytest.raises(FockError) as ei:
         ctx.apply_vx(P, n=w["n"], L=w["L"], prec="ace_fp64")
     assert ei.value.status == -2
-    # budget too small -> OOM, reported, context still usable afterwards
+    # a 1 MiB budget still works (one pair per batch) and gives the same bits
     from paper_1905_01348_amd import Context
 
     small = Context(0, hbm_budget_bytes=1 << 20)
-    with pytest.raises(FockError) as ei:
-        small.apply_vx(P, n=w["n"], L=w["L"], prec="fp64")
-    assert ei.value.status == -3
+    o_small = host(small.apply_vx(P, n=w["n"], L=w["L"], prec="fp64", kernel="coulomb"))
+    o_ref = host(ctx.apply_vx(P, n=w["n"], L=w["L"], prec="fp64", kernel="coulomb"))
+    assert np.array_equal(o_small.view(np.float64), o_ref.view(np.float64))
     small.close()
+    # budget below one pair volume -> FX_ERR_OOM, context still usable afterwards
+    tiny = Context(0, hbm_budget_bytes=64 << 10)
+    with pytest.raises(FockError) as ei:
+        tiny.apply_vx(P, n=w["n"], L=w["L"], prec="fp64")
+    assert ei.value.status == -3
+    tiny.close()
     out = ctx.apply_vx(P, n=w["n"], L=w["L"], prec="fp64", kernel="coulomb")
     torch.cuda.synchronize()
     assert torch.isfinite(torch.view_as_real(out)).all()
