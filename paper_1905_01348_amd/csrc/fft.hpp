@@ -206,13 +206,19 @@ FX_HD void stage_bfly(cpx<T>* s, int n, int L, int count, int es, int fs, const 
   cpx<T> x[R];
 #pragma unroll
   for (int m = 0; m < R; ++m) x[m] = s[base + m * step];
+  // the last forward stage (first inverse stage) has span 1: i2 = 0 and
+  // every twiddle is 1
   if (FWD) {
     Dft<R, -1, T>::run(x);
+    if (span > 1) {
 #pragma unroll
-    for (int k = 1; k < R; ++k) x[k] = cmul(x[k], tw[i2 * k * tstep]);
+      for (int k = 1; k < R; ++k) x[k] = cmul(x[k], tw[i2 * k * tstep]);
+    }
   } else {
+    if (span > 1) {
 #pragma unroll
-    for (int k = 1; k < R; ++k) x[k] = cmulc(x[k], tw[i2 * k * tstep]);
+      for (int k = 1; k < R; ++k) x[k] = cmulc(x[k], tw[i2 * k * tstep]);
+    }
     Dft<R, 1, T>::run(x);
   }
 #pragma unroll

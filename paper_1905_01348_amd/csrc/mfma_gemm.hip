@@ -139,26 +139,33 @@ __global__ void __launch_bounds__(256) k_tn_mfma(int M, int N, int K, int kchunk
   // rows: 128 (plain) or 64 source rows (BDOUBLE, 2 vectors per thread)
   constexpr int BV = BDOUBLE ? 2 : 4;
   uint4 ra[2][4], rb[2][BV];
-  auto gload = [&](int k0) {
+  // rows past the edge load a clamped (valid) row and are zeroed by value,
+  // so the loads need no branches
+  auto zsel = [](uint4 v, bool keep) __attribute__((always_inline)) {
+    return uint4{keep ? v.x : 0u, keep ? v.y : 0u, keep ? v.z : 0u, keep ? v.w : 0u};
+  };
+  auto gload = [&](int k0) __attribute__((always_inline)) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int v = tid + 256 * u, row = v / VPR, c = v % VPR;
       const int m = m0 + row;
-      uint4 z = {0, 0, 0, 0};
-      ra[0][u] = m < M ? *reinterpret_cast<const uint4*>(Ap + (int64_t)m * lda + k0 + c * EPV) : z;
-      if (REFINE) ra[1][u] = m < M ? *reinterpret_cast<const uint4*>(Ar + (int64_t)m * lda + k0 + c * EPV) : z;
+      const int mc = m < M ? m : M - 1;
+      const int64_t off = (int64_t)mc * lda + k0 + c * EPV;
+      ra[0][u] = zsel(*reinterpret_cast<const uint4*>(Ap + off), m < M);
+      if (REFINE) ra[1][u] = zsel(*reinterpret_cast<const uint4*>(Ar + off), m < M);
     }
 #pragma unroll
     for (int u = 0; u < BV; ++u) {
       const int v = tid + 256 * u, row = v / VPR, c = v % VPR;
       const int n = BDOUBLE ? n0 / 2 + row : n0 + row;
       const int nlim = BDOUBLE ? N / 2 : N;
-      uint4 z = {0, 0, 0, 0};
-      rb[0][u] = n < nlim ? *reinterpret_cast<const uint4*>(Bp + (int64_t)n * ldb + k0 + c * EPV) : z;
-      if (REFINE) rb[1][u] = n < nlim ? *reinterpret_cast<const uint4*>(Br + (int64_t)n * ldb + k0 + c * EPV) : z;
+      const int nc = n < nlim ? n : nlim - 1;
+      const int64_t off = (int64_t)nc * ldb + k0 + c * EPV;
+      rb[0][u] = zsel(*reinterpret_cast<const uint4*>(Bp + off), n < nlim);
+      if (REFINE) rb[1][u] = zsel(*reinterpret_cast<const uint4*>(Br + off), n < nlim);
     }
   };
-  auto sstore = [&]() {
+  auto sstore = [&]() __attribute__((always_inline)) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int v = tid + 256 * u, row = v / VPR, c = v % VPR;
