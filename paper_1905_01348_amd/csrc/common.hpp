@@ -134,7 +134,7 @@ fx_status grid_tables(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* kern, i
                       const GridTables** out);
 
 // Plan of an FFT axis: n = R[0] * R[1] * ... (at most 4 radices from
-// {2,3,4,6,8,9,12,16}); DIF stages run in this order.
+// {2,3,4,6,8,9,12}); DIF stages run in this order.
 struct AxisPlan {
   int n;
   int nst;

@@ -8,7 +8,7 @@
 // The spectrum is therefore never un-permuted: the pointwise kernel multiply
 // between the forward and inverse transforms reads K at the permuted
 // positions.  Inside a stage each thread runs whole radix-R butterflies in
-// registers (R in {2,3,4,6,8,9,12,16}); composite radices are evaluated in
+// registers (R in {2,3,4,6,8,9,12}); composite radices are evaluated in
 // registers by a nested four-step with compile-time twiddles.
 //
 // Everything here is __host__ __device__ so the same stage code can be run on
@@ -19,7 +19,9 @@
 
 #include "common.hpp"
 
-#define FX_HD __host__ __device__ inline
+// Everything is force-inlined: a call inside a kernel would cost a stack
+// frame in scratch memory and block register allocation across the stages.
+#define FX_HD __host__ __device__ inline __attribute__((always_inline))
 
 namespace fx {
 
@@ -243,7 +245,6 @@ FX_HD void stage_dispatch(int R, cpx<T>* s, int n, int L, int count, int es, int
     case 8: stage_loop<8, FWD, T>(s, n, L, count, es, fs, tw, tid, nthr); break;
     case 9: stage_loop<9, FWD, T>(s, n, L, count, es, fs, tw, tid, nthr); break;
     case 12: stage_loop<12, FWD, T>(s, n, L, count, es, fs, tw, tid, nthr); break;
-    case 16: stage_loop<16, FWD, T>(s, n, L, count, es, fs, tw, tid, nthr); break;
     default: break;
   }
 }
@@ -285,6 +286,67 @@ FX_HD void lds_fft(cpx<T>* s, const AxisArg& a, int count, int es, int fs, const
       stage_dispatch<false, T>(a.R[st], s, a.n, L, count, es, fs, tw, tid, nthr);
       sync();
     }
+  }
+}
+
+// ---- convolution along one axis: forward FFT, pointwise factor, inverse ----
+// The last forward stage has span 1, so each of its butterflies owns R
+// consecutive positions — exactly the points the first inverse stage
+// combines.  That stage, the pointwise factor and the first inverse stage
+// therefore run in registers as one pass.  kf(pos, f) is the real factor at
+// digit-reversed position pos of transform f.
+template <int R, typename T, class KF>
+FX_HD void mid_bfly(cpx<T>* s, int count, int es, int fs, int b, KF kf) {
+  const int f = b % count;
+  const int blk = b / count;
+  const int base = f * fs + blk * R * es;
+  cpx<T> x[R];
+#pragma unroll
+  for (int m = 0; m < R; ++m) x[m] = s[base + m * es];
+  Dft<R, -1, T>::run(x);
+#pragma unroll
+  for (int k = 0; k < R; ++k) x[k] = cscale(x[k], kf(blk * R + k, f));
+  Dft<R, 1, T>::run(x);
+#pragma unroll
+  for (int m = 0; m < R; ++m) s[base + m * es] = x[m];
+}
+
+template <int R, typename T, class KF>
+FX_HD void mid_loop(cpx<T>* s, int n, int count, int es, int fs, KF kf, int tid, int nthr) {
+  const int total = count * (n / R);
+  for (int b = tid; b < total; b += nthr) mid_bfly<R, T>(s, count, es, fs, b, kf);
+}
+
+template <typename T, class KF>
+FX_HD void mid_dispatch(int R, cpx<T>* s, int n, int count, int es, int fs, KF kf, int tid, int nthr) {
+  switch (R) {
+    case 2: mid_loop<2, T>(s, n, count, es, fs, kf, tid, nthr); break;
+    case 3: mid_loop<3, T>(s, n, count, es, fs, kf, tid, nthr); break;
+    case 4: mid_loop<4, T>(s, n, count, es, fs, kf, tid, nthr); break;
+    case 6: mid_loop<6, T>(s, n, count, es, fs, kf, tid, nthr); break;
+    case 8: mid_loop<8, T>(s, n, count, es, fs, kf, tid, nthr); break;
+    case 9: mid_loop<9, T>(s, n, count, es, fs, kf, tid, nthr); break;
+    case 12: mid_loop<12, T>(s, n, count, es, fs, kf, tid, nthr); break;
+    default: break;
+  }
+}
+
+template <typename T, class KF, class Sync>
+FX_HD void lds_conv(cpx<T>* s, const AxisArg& a, int count, int es, int fs, const cpx<T>* tw, KF kf, int tid,
+                    int nthr, Sync sync) {
+  int L = a.n;
+  for (int st = 0; st + 1 < a.nst; ++st) {
+    stage_dispatch<true, T>(a.R[st], s, a.n, L, count, es, fs, tw, tid, nthr);
+    sync();
+    L /= a.R[st];
+  }
+  mid_dispatch<T>(a.R[a.nst - 1], s, a.n, count, es, fs, kf, tid, nthr);
+  sync();
+  for (int st = a.nst - 2; st >= 0; --st) {
+    int Ls = a.n;
+    for (int u = 0; u < st; ++u) Ls /= a.R[u];
+    stage_dispatch<false, T>(a.R[st], s, a.n, Ls, count, es, fs, tw, tid, nthr);
+    sync();
   }
 }
 

@@ -1,0 +1,142 @@
+// Compile-time-specialised FFT stages for cubic grids with a two-stage plan.
+//
+// Same algorithm as fft.hpp (in-place DIF forward stages, adjoint inverse
+// stages, digit-reversed spectra), but the edge, the plan, the number of
+// transforms, the LDS strides and the thread count are template constants:
+// butterfly indices come from divisions by constants, LDS addresses fold
+// into instruction offsets, each kernel carries only the two radices its
+// edge needs, and the butterfly loop is fully unrolled.
+#pragma once
+
+#include "fft.hpp"
+
+namespace fx {
+
+// Two-stage plan of an edge; must equal make_axis_plan (checked on the host).
+template <int N>
+struct Plan2;
+template <>
+struct Plan2<24> {
+  static constexpr int R0 = 6, R1 = 4;
+};
+template <>
+struct Plan2<48> {
+  static constexpr int R0 = 8, R1 = 6;
+};
+template <>
+struct Plan2<72> {
+  static constexpr int R0 = 9, R1 = 8;
+};
+template <>
+struct Plan2<96> {
+  static constexpr int R0 = 12, R1 = 8;
+};
+
+// One stage: transforms f < COUNT, element i of transform f at f*FS + i*ES;
+// current sub-length L, radix R; NTHR threads deal the butterflies.
+template <int R, bool FWD, typename T, int N, int L, int COUNT, int ES, int FS, int NTHR>
+FX_HD void ct_stage(cpx<T>* s, const cpx<T>* tw, int tid) {
+  constexpr int SPAN = L / R, TOTAL = COUNT * (N / R), TSTEP = N / L, STEP = SPAN * ES;
+  constexpr int ITERS = (TOTAL + NTHR - 1) / NTHR;
+#pragma unroll
+  for (int it = 0; it < ITERS; ++it) {
+    const int b = tid + it * NTHR;
+    if (TOTAL % NTHR == 0 || b < TOTAL) {
+      const int f = b % COUNT;
+      const int q = b / COUNT;
+      const int blk = q / SPAN;
+      const int i2 = q - blk * SPAN;
+      const int base = f * FS + (blk * L + i2) * ES;
+      cpx<T> x[R];
+#pragma unroll
+      for (int m = 0; m < R; ++m) x[m] = s[base + m * STEP];
+      if (FWD) {
+        Dft<R, -1, T>::run(x);
+        if (SPAN > 1) {
+#pragma unroll
+          for (int k = 1; k < R; ++k) x[k] = cmul(x[k], tw[i2 * k * TSTEP]);
+        }
+      } else {
+        if (SPAN > 1) {
+#pragma unroll
+          for (int k = 1; k < R; ++k) x[k] = cmulc(x[k], tw[i2 * k * TSTEP]);
+        }
+        Dft<R, 1, T>::run(x);
+      }
+#pragma unroll
+      for (int m = 0; m < R; ++m) s[base + m * STEP] = x[m];
+    }
+  }
+}
+
+// Full forward or inverse transform along one axis (two stages + barriers).
+template <bool FWD, typename T, int N, int COUNT, int ES, int FS, int NTHR>
+__device__ inline void ct_fft(cpx<T>* s, const cpx<T>* tw, int tid) {
+  constexpr int R0 = Plan2<N>::R0, R1 = Plan2<N>::R1;
+  if (FWD) {
+    ct_stage<R0, true, T, N, N, COUNT, ES, FS, NTHR>(s, tw, tid);
+    __syncthreads();
+    ct_stage<R1, true, T, N, R1, COUNT, ES, FS, NTHR>(s, tw, tid);
+    __syncthreads();
+  } else {
+    ct_stage<R1, false, T, N, R1, COUNT, ES, FS, NTHR>(s, tw, tid);
+    __syncthreads();
+    ct_stage<R0, false, T, N, N, COUNT, ES, FS, NTHR>(s, tw, tid);
+    __syncthreads();
+  }
+}
+
+// Convolution along one axis: first forward stage, then the last forward
+// stage + pointwise factor + first inverse stage in registers, then the last
+// inverse stage.  kf(pos, f) as in lds_conv.
+template <typename T, int N, int COUNT, int ES, int FS, int NTHR, class KF>
+__device__ inline void ct_conv(cpx<T>* s, const cpx<T>* tw, KF kf, int tid) {
+  constexpr int R0 = Plan2<N>::R0, R1 = Plan2<N>::R1;
+  ct_stage<R0, true, T, N, N, COUNT, ES, FS, NTHR>(s, tw, tid);
+  __syncthreads();
+  constexpr int TOTAL = COUNT * (N / R1);
+  constexpr int ITERS = (TOTAL + NTHR - 1) / NTHR;
+#pragma unroll
+  for (int it = 0; it < ITERS; ++it) {
+    const int b = tid + it * NTHR;
+    if (TOTAL % NTHR == 0 || b < TOTAL) {
+      const int f = b % COUNT;
+      const int blk = b / COUNT;
+      const int base = f * FS + blk * R1 * ES;
+      cpx<T> x[R1];
+#pragma unroll
+      for (int m = 0; m < R1; ++m) x[m] = s[base + m * ES];
+      Dft<R1, -1, T>::run(x);
+#pragma unroll
+      for (int k = 0; k < R1; ++k) x[k] = cscale(x[k], kf(blk * R1 + k, f));
+      Dft<R1, 1, T>::run(x);
+#pragma unroll
+      for (int m = 0; m < R1; ++m) s[base + m * ES] = x[m];
+    }
+  }
+  __syncthreads();
+  ct_stage<R0, false, T, N, N, COUNT, ES, FS, NTHR>(s, tw, tid);
+  __syncthreads();
+}
+
+// Launch shapes per edge: plane passes (threads), pencil pass (x tile, threads).
+template <int N>
+struct CubeShape;
+template <>
+struct CubeShape<24> {
+  static constexpr int NT_P = 192, XT = 24, NT_B = 192;
+};
+template <>
+struct CubeShape<48> {
+  static constexpr int NT_P = 256, XT = 48, NT_B = 256;
+};
+template <>
+struct CubeShape<72> {
+  static constexpr int NT_P = 512, XT = 24, NT_B = 256;
+};
+template <>
+struct CubeShape<96> {
+  static constexpr int NT_P = 512, XT = 48, NT_B = 512;
+};
+
+}  // namespace fx

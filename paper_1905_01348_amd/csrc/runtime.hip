@@ -145,7 +145,7 @@ bool supported_edge(int n) {
 }
 
 static bool is_radix(int r) {
-  return r == 2 || r == 3 || r == 4 || r == 6 || r == 8 || r == 9 || r == 12 || r == 16;
+  return r == 2 || r == 3 || r == 4 || r == 6 || r == 8 || r == 9 || r == 12;
 }
 
 bool make_axis_plan(int n, AxisPlan* p) {
@@ -160,7 +160,7 @@ bool make_axis_plan(int n, AxisPlan* p) {
   }
   // two stages, as balanced as possible, larger radix first on ties
   int best = -1, bestmax = 1 << 30;
-  const int cand[] = {16, 12, 9, 8, 6, 4, 3, 2};
+  const int cand[] = {12, 9, 8, 6, 4, 3, 2};
   for (int r : cand) {
     if (n % r || !is_radix(n / r)) continue;
     int mx = r > n / r ? r : n / r;

@@ -14,12 +14,20 @@ namespace fx {
 
 // ---------------------------------------------------------------------------
 // kernels
+//
+// The plane passes are persistent: each workgroup walks items (pair, z) or
+// (target, z) with stride gridDim.x, and issues the global loads of the next
+// plane into registers (EPT elements per thread) before running the FFT of
+// the current one, so the loads are in flight while the LDS stages run.
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ void __launch_bounds__(256) k_pass_a(const cpx<T>* __restrict__ psi, int64_t ld_psi,
-                                                const cpx<T>* __restrict__ phi, int64_t ld_phi,
-                                                cpx<T>* __restrict__ work, int j0, int nj, int k0, PassGeom g,
-                                                const cpx<T>* __restrict__ twx_g, const cpx<T>* __restrict__ twy_g) {
+constexpr int kPlaneThreads = 512;
+
+template <typename T, int EPT>
+__global__ void __launch_bounds__(kPlaneThreads) k_pass_a(const cpx<T>* __restrict__ psi, int64_t ld_psi,
+                                                 const cpx<T>* __restrict__ phi, int64_t ld_phi,
+                                                 cpx<T>* __restrict__ work, int j0, int nj, int k0, int nitems,
+                                                 PassGeom g, const cpx<T>* __restrict__ twx_g,
+                                                 const cpx<T>* __restrict__ twy_g) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* s = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* twx = s + plane_lds_elems(g);
@@ -27,42 +35,118 @@ __global__ void __launch_bounds__(256) k_pass_a(const cpx<T>* __restrict__ psi, 
   const int tid = threadIdx.x, nthr = blockDim.x;
   for (int i = tid; i < g.nx; i += nthr) twx[i] = twx_g[i];
   for (int i = tid; i < g.ny; i += nthr) twy[i] = twy_g[i];
-  const int z = blockIdx.x % g.nz;
-  const int p = blockIdx.x / g.nz;
-  const int j = j0 + p % nj, k = k0 + p / nj;
-  const size_t nxy = (size_t)g.nx * g.ny, nr = nxy * g.nz;
-  pass_a_body<T>(psi + j * ld_psi + z * nxy, phi + k * ld_phi + z * nxy, work + p * nr + z * nxy, s, twx, twy, g,
-                 tid, nthr, DeviceSync{});
+  const int nxy = g.nx * g.ny;
+  const size_t nr = (size_t)nxy * g.nz;
+  cpx<T> va[EPT], vb[EPT];
+  auto fetch = [&](int it) __attribute__((always_inline)) {
+    if (it >= nitems) return;
+    const int z = it % g.nz, p = it / g.nz;
+    const cpx<T>* a = psi + (int64_t)(j0 + p % nj) * ld_psi + (size_t)z * nxy;
+    const cpx<T>* b = phi + (int64_t)(k0 + p / nj) * ld_phi + (size_t)z * nxy;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int e = tid + i * nthr;
+      if (e < nxy) {
+        va[i] = a[e];
+        vb[i] = b[e];
+      }
+    }
+  };
+  // FP32: the next plane loads while this one transforms; FP64 planes do
+  // not leave room in registers for that, so they load just before use
+  constexpr bool kPipe = sizeof(T) == 4;
+  int item = blockIdx.x;
+  if (kPipe) fetch(item);
+  for (; item < nitems; item += gridDim.x) {
+    if (!kPipe) fetch(item);
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int e = tid + i * nthr;
+      if (e < nxy) {
+        const int y = e / g.nx, x = e - y * g.nx;
+        s[y * g.sx + x] = cconjmul(va[i], vb[i]);
+      }
+    }
+    __syncthreads();
+    if (kPipe) fetch(item + gridDim.x);
+    lds_fft<true, T>(s, g.ax, g.ny, 1, g.sx, twx, tid, nthr, DeviceSync{});
+    lds_fft<true, T>(s, g.ay, g.nx, g.sx, 1, twy, tid, nthr, DeviceSync{});
+    const int z = item % g.nz, p = item / g.nz;
+    cpx<T>* o = work + p * nr + (size_t)z * nxy;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int e = tid + i * nthr;
+      if (e < nxy) {
+        const int y = e / g.nx, x = e - y * g.nx;
+        o[e] = s[y * g.sx + x];
+      }
+    }
+    __syncthreads();
+  }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256) k_pass_b(cpx<T>* __restrict__ work, PassGeom g,
+// Pass B: one (pair, y, x-tile) per workgroup; many small workgroups per CU.
+template <typename T, int EPT>
+__global__ void __launch_bounds__(256) k_pass_b(cpx<T>* __restrict__ work, int xt, int ntx, PassGeom g,
                                                 const cpx<T>* __restrict__ twz_g, const T* __restrict__ kfold,
                                                 const int* __restrict__ foldx_g, const int* __restrict__ foldy_g,
                                                 const int* __restrict__ foldz_g) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int n = g.nz * xt;
   cpx<T>* s = reinterpret_cast<cpx<T>*>(smem_raw);
-  cpx<T>* twz = s + xz_lds_elems(g);
-  int* fxl = reinterpret_cast<int*>(twz + g.nz);
+  cpx<T>* twz = s + n;
+  T* kl = reinterpret_cast<T*>(twz + g.nz);
+  int* fxl = reinterpret_cast<int*>(kl + g.hz * g.hx);
   int* fzl = fxl + g.nx;
   const int tid = threadIdx.x, nthr = blockDim.x;
+  const int tx = blockIdx.x % ntx;
+  const int rest = blockIdx.x / ntx;
+  const int y = rest % g.ny;
+  const int p = rest / g.ny;
+  const int x0 = tx * xt;
+  cpx<T>* vol = work + (size_t)p * g.nx * g.ny * g.nz;
+  cpx<T> v[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = tid + i * nthr;
+    const int z = e / xt, x = x0 + (e - z * xt);
+    v[i] = cpx<T>{0, 0};
+    if (e < n && x < g.nx) v[i] = vol[((size_t)z * g.ny + y) * g.nx + x];
+  }
+  // tables while the loads are in flight
+  const int fy = foldy_g[y];
   for (int i = tid; i < g.nz; i += nthr) {
     twz[i] = twz_g[i];
     fzl[i] = foldz_g[i];
   }
   for (int i = tid; i < g.nx; i += nthr) fxl[i] = foldx_g[i];
-  const int y = blockIdx.x % g.ny;
-  const int p = blockIdx.x / g.ny;
-  const size_t nr = (size_t)g.nx * g.ny * g.nz;
-  pass_b_body<T>(work + p * nr, y, s, twz, kfold, fxl, fzl, foldy_g[y], g, tid, nthr, DeviceSync{});
+  for (int i = tid; i < g.hz * g.hx; i += nthr) {
+    const int fz = i / g.hx, fx = i - fz * g.hx;
+    kl[i] = kfold[((size_t)fz * g.hy + fy) * g.hx + fx];
+  }
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = tid + i * nthr;
+    if (e < n) s[e] = v[i];
+  }
+  __syncthreads();
+  const KSlice<T> kf{kl, fxl, fzl, x0, g.nx, g.hx};
+  lds_conv<T>(s, g.az, xt, xt, 1, twz, kf, tid, nthr, DeviceSync{});
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = tid + i * nthr;
+    const int z = e / xt, x = x0 + (e - z * xt);
+    if (e < n && x < g.nx) vol[((size_t)z * g.ny + y) * g.nx + x] = s[e];
+  }
 }
 
 // Pass C.  acc (ld_acc) holds the running sum over j of the targets in the
 // accumulation precision A; when `last` is set the final sum goes to `out`
-// in its own dtype instead (out may be the same memory as acc).
-template <typename T, typename A, int EPT>
-__global__ void __launch_bounds__(1024) k_pass_c(const cpx<T>* __restrict__ psi, int64_t ld_psi,
-                                                 const cpx<T>* __restrict__ work, int j0, int nj, int k0,
+// in its own dtype instead (out may be the same memory as acc).  While the
+// FFT of orbital j runs, psi_j and the work plane of orbital j+1 are loading.
+template <typename T, typename A, int EPT, bool PIPE>
+__global__ void __launch_bounds__(kPlaneThreads) k_pass_c(const cpx<T>* __restrict__ psi, int64_t ld_psi,
+                                                 const cpx<T>* __restrict__ work, int j0, int nj, int k0, int nitems,
                                                  cpx<A>* acc, int64_t ld_acc, int first, void* out, int64_t ld_out,
                                                  int out_c64, int last, PassGeom g,
                                                  const cpx<T>* __restrict__ twx_g, const cpx<T>* __restrict__ twy_g) {
@@ -73,47 +157,74 @@ __global__ void __launch_bounds__(1024) k_pass_c(const cpx<T>* __restrict__ psi,
   const int tid = threadIdx.x, nthr = blockDim.x;
   for (int i = tid; i < g.nx; i += nthr) twx[i] = twx_g[i];
   for (int i = tid; i < g.ny; i += nthr) twy[i] = twy_g[i];
-  const int z = blockIdx.x % g.nz;
-  const int kk = blockIdx.x / g.nz;
-  const int k = k0 + kk;
   const int nxy = g.nx * g.ny;
   const size_t nr = (size_t)nxy * g.nz;
-  cpx<A> a[EPT];
-#pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    const int e = tid + i * nthr;
-    a[i] = cpx<A>{0, 0};
-    if (!first && e < nxy) a[i] = acc[k * ld_acc + (size_t)z * nxy + e];
-  }
-  for (int jj = 0; jj < nj; ++jj) {
-    const int j = j0 + jj;
-    const size_t p = (size_t)kk * nj + jj;
-    pass_c_fft<T>(work + p * nr + (size_t)z * nxy, s, twx, twy, g, tid, nthr, DeviceSync{});
-    const cpx<T>* pj = psi + j * ld_psi + (size_t)z * nxy;
+  for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+    const int z = item % g.nz;
+    const int kk = item / g.nz;
+    const int k = k0 + kk;
+    cpx<A> a[EPT];
+    cpx<T> vt[EPT], vp[EPT];
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
       const int e = tid + i * nthr;
-      if (e < nxy) {
-        const int y = e / g.nx, x = e - y * g.nx;
-        const cpx<T> v = s[y * g.sx + x];
-        const cpx<T> w = pj[e];
-        a[i] = cadd(a[i], cmul(cpx<A>{(A)w.x, (A)w.y}, cpx<A>{(A)v.x, (A)v.y}));
-      }
+      a[i] = cpx<A>{0, 0};
+      if (!first && e < nxy) a[i] = acc[k * ld_acc + (size_t)z * nxy + e];
     }
-    __syncthreads();
-  }
+    constexpr bool kPipe = PIPE;  // prefetch the next work plane during the FFT
+    auto tload = [&](int jj) __attribute__((always_inline)) {
+      const cpx<T>* tp = work + ((size_t)kk * nj + jj) * nr + (size_t)z * nxy;
 #pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    const int e = tid + i * nthr;
-    if (e >= nxy) continue;
-    const size_t off = (size_t)z * nxy + e;
-    if (last) {
-      if (out_c64)
-        reinterpret_cast<cpx<float>*>(out)[k * ld_out + off] = cpx<float>{(float)a[i].x, (float)a[i].y};
-      else
-        reinterpret_cast<cpx<double>*>(out)[k * ld_out + off] = cpx<double>{(double)a[i].x, (double)a[i].y};
-    } else {
-      acc[k * ld_acc + off] = a[i];
+      for (int i = 0; i < EPT; ++i) {
+        const int e = tid + i * nthr;
+        if (e < nxy) vt[i] = tp[e];
+      }
+    };
+    if (kPipe) tload(0);
+    for (int jj = 0; jj < nj; ++jj) {
+      if (!kPipe) tload(jj);
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) {
+        const int e = tid + i * nthr;
+        if (e < nxy) {
+          const int y = e / g.nx, x = e - y * g.nx;
+          s[y * g.sx + x] = vt[i];
+        }
+      }
+      __syncthreads();
+      const cpx<T>* pj = psi + (int64_t)(j0 + jj) * ld_psi + (size_t)z * nxy;
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) {
+        const int e = tid + i * nthr;
+        if (e < nxy) vp[i] = pj[e];
+      }
+      if (kPipe && jj + 1 < nj) tload(jj + 1);
+      lds_fft<false, T>(s, g.ay, g.nx, g.sx, 1, twy, tid, nthr, DeviceSync{});
+      lds_fft<false, T>(s, g.ax, g.ny, 1, g.sx, twx, tid, nthr, DeviceSync{});
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) {
+        const int e = tid + i * nthr;
+        if (e < nxy) {
+          const int y = e / g.nx, x = e - y * g.nx;
+          const cpx<T> v = s[y * g.sx + x];
+          a[i] = cadd(a[i], cmul(cpx<A>{(A)vp[i].x, (A)vp[i].y}, cpx<A>{(A)v.x, (A)v.y}));
+        }
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int e = tid + i * nthr;
+      if (e >= nxy) continue;
+      const size_t off = (size_t)z * nxy + e;
+      if (last) {
+        if (out_c64)
+          reinterpret_cast<cpx<float>*>(out)[k * ld_out + off] = cpx<float>{(float)a[i].x, (float)a[i].y};
+        else
+          reinterpret_cast<cpx<double>*>(out)[k * ld_out + off] = cpx<double>{(double)a[i].x, (double)a[i].y};
+      } else {
+        acc[k * ld_acc + off] = a[i];
+      }
     }
   }
 }
@@ -186,6 +297,7 @@ PassGeom make_geom(const fx_cell* cell) {
   g.az = to_arg(p);
   g.hx = g.nx / 2 + 1;
   g.hy = g.ny / 2 + 1;
+  g.hz = g.nz / 2 + 1;
   return g;
 }
 
@@ -202,6 +314,16 @@ static fx_status allow_lds(K kernel, size_t bytes) {
   return FX_OK;
 }
 
+// Workgroups of a persistent kernel: resident workgroups per CU x CUs.
+template <typename K>
+static fx_status persistent_grid(fx_ctx* ctx, K kernel, int nthr, size_t lds, int items, int* grid) {
+  int per_cu = 0;
+  FX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kernel), nthr, lds));
+  if (per_cu < 1) per_cu = 1;
+  *grid = std::max(1, std::min(items, per_cu * std::max(ctx->n_cu, 1)));
+  return FX_OK;
+}
+
 static size_t work_cap_bytes(fx_ctx* ctx) {
   size_t cap = (size_t)4096 << 20;
   if (const char* e = getenv("FX_WORK_MB")) cap = (size_t)atol(e) << 20;
@@ -209,42 +331,32 @@ static size_t work_cap_bytes(fx_ctx* ctx) {
   return cap;
 }
 
-// Pass C launch with the EPT (elements per thread) that fits the plane.
-template <typename T, typename A>
-static fx_status launch_pass_c(const PassGeom& g, int nthr_hint, dim3 grid, size_t lds, hipStream_t st,
-                               const cpx<T>* psi, int64_t ld_psi, const cpx<T>* work, int j0, int nj, int k0,
-                               cpx<A>* acc, int64_t ld_acc, int first, void* out, int64_t ld_out, int out_c64,
-                               int last, const cpx<T>* twx, const cpx<T>* twy) {
-  const int nxy = g.nx * g.ny;
-  (void)nthr_hint;
-  static const int epts[] = {4, 6, 9, 12, 16};
-  int ept = 0, nthr = 0;
-  for (int e : epts) {
-    int t = round64((nxy + e - 1) / e);
-    if (t <= 1024) {
-      ept = e;
-      nthr = t;
-      break;
+// Elements per thread (a compile-time register count) and threads for
+// `elems` elements and at most max_thr threads.
+static const int kEpts[] = {1, 2, 3, 4, 6, 9, 18};
+static bool pick_ept(int elems, int max_thr, int* ept, int* nthr) {
+  for (int e : kEpts) {
+    const int t = round64((elems + e - 1) / e);
+    if (t <= max_thr) {
+      *ept = e;
+      *nthr = t;
+      return true;
     }
   }
-  if (!ept) FX_FAIL(FX_ERR_UNSUPPORTED, "plane of %d points is too large", nxy);
-#define FX_PASSC(E)                                                                                       \
-  case E:                                                                                                 \
-    FX_TRY(allow_lds(k_pass_c<T, A, E>, lds));                                                            \
-    hipLaunchKernelGGL((k_pass_c<T, A, E>), grid, dim3(nthr), lds, st, psi, ld_psi, work, j0, nj, k0, acc, \
-                       ld_acc, first, out, ld_out, out_c64, last, g, twx, twy);                           \
-    break;
-  switch (ept) {
-    FX_PASSC(4)
-    FX_PASSC(6)
-    FX_PASSC(9)
-    FX_PASSC(12)
-    FX_PASSC(16)
-  }
-#undef FX_PASSC
-  FX_LAUNCH_CHECK();
-  return FX_OK;
+  return false;
 }
+
+#define FX_EPT_SWITCH(EPT_VAR, ...) \
+  switch (EPT_VAR) {                 \
+    case 1: { constexpr int E = 1; __VA_ARGS__; } break;   \
+    case 2: { constexpr int E = 2; __VA_ARGS__; } break;   \
+    case 3: { constexpr int E = 3; __VA_ARGS__; } break;   \
+    case 4: { constexpr int E = 4; __VA_ARGS__; } break;   \
+    case 6: { constexpr int E = 6; __VA_ARGS__; } break;   \
+    case 9: { constexpr int E = 9; __VA_ARGS__; } break;   \
+    case 18: { constexpr int E = 18; __VA_ARGS__; } break; \
+    default: FX_FAIL(FX_ERR_UNSUPPORTED, "no kernel for %d elements per thread", EPT_VAR); \
+  }
 
 template <typename T, typename A>
 static fx_status run_batches(fx_ctx* ctx, Workspace* ws, const VxArgs& a, const GridTables* tb,
@@ -252,6 +364,7 @@ static fx_status run_batches(fx_ctx* ctx, Workspace* ws, const VxArgs& a, const 
                              VxStats* stats) {
   const PassGeom g = make_geom(a.cell);
   const int64_t nr = (int64_t)g.nx * g.ny * g.nz;
+  const int nxy = g.nx * g.ny;
   const size_t pair_bytes = (size_t)nr * sizeof(cpx<T>);
   size_t cap = a.work_cap ? a.work_cap : work_cap_bytes(ctx);
   const int64_t pairs_cap = (int64_t)std::max<size_t>(1, cap / pair_bytes);
@@ -287,12 +400,23 @@ static fx_status run_batches(fx_ctx* ctx, Workspace* ws, const VxArgs& a, const 
   const cpx<T>* twy = reinterpret_cast<const cpx<T>*>(tb->tw[1]);
   const cpx<T>* twz = reinterpret_cast<const cpx<T>*>(tb->tw[2]);
   const T* kf = reinterpret_cast<const T*>(tb->kfold);
+
+  // launch shapes
+  int ept_p = 0, nthr_p = 0;
+  if (!pick_ept(nxy, kPlaneThreads, &ept_p, &nthr_p)) FX_FAIL(FX_ERR_UNSUPPORTED, "plane of %d points is too large", nxy);
+  const bool pipe_c = a.pipe >= 0 ? a.pipe != 0 : ept_p < 18;
+  int xt = g.nx < 32 ? g.nx : 32;
+  if (a.xtile > 0) xt = std::min(g.nx, a.xtile);
+  const int ntx = (g.nx + xt - 1) / xt;
+  int ept_b = 0, nthr_b = 0;
+  if (!pick_ept(g.nz * xt, a.nthr_b > 0 ? a.nthr_b : 256, &ept_b, &nthr_b))
+    FX_FAIL(FX_ERR_UNSUPPORTED, "pencil tile of %d points is too large", g.nz * xt);
   const size_t lds_plane = ((size_t)plane_lds_elems(g) + g.nx + g.ny) * sizeof(cpx<T>);
-  const size_t lds_xz = ((size_t)xz_lds_elems(g) + g.nz) * sizeof(cpx<T>) + (size_t)(g.nx + g.nz) * sizeof(int);
-  FX_TRY(allow_lds(k_pass_a<T>, lds_plane));
-  FX_TRY(allow_lds(k_pass_b<T>, lds_xz));
-  const int nthr_a = a.nthr_a > 0 ? a.nthr_a : 256;
-  const int nthr_b = a.nthr_b > 0 ? a.nthr_b : 256;
+  const size_t lds_b = ((size_t)g.nz * xt + g.nz) * sizeof(cpx<T>) + (size_t)g.hz * g.hx * sizeof(T) +
+                       (size_t)(g.nx + g.nz) * sizeof(int);
+
+  // cubic grids of the workload edges run the compile-time-specialised kernels
+  const bool use_ct = ct_supported(a.cell);
   int64_t launches = 0;
   for (int k0 = 0; k0 < a.n_phi; k0 += nk) {
     const int kb = std::min(nk, a.n_phi - k0);
@@ -306,20 +430,56 @@ static fx_status run_batches(fx_ctx* ctx, Workspace* ws, const VxArgs& a, const 
                           ((first ? 0.0 : (double)sizeof(cpx<A>)) +
                            (last ? (out_c64 ? 8.0 : 16.0) : (double)sizeof(cpx<A>)));
       int slot;
+      if (use_ct) {
+        CtBatch<T> cb{psi, ld_psi, phi, ld_phi, reinterpret_cast<cpx<T>*>(work), j0, jb, k0, kb, npairs, twx, kf,
+                      tb->fold[0]};
+        CtAcc<A> ca{acc, ld_acc, first, a.out, a.ld_out, out_c64 ? 1 : 0, last, a.pipe};
+        FX_TRY(prof_begin(ctx, st, FX_K_VX_PLANE_FWD, 3.0 * vol, &slot));
+        FX_TRY(ct_pass_a<T>(ctx, st, g.nx, cb));
+        FX_TRY(prof_end(ctx, st, slot));
+        FX_TRY(prof_begin(ctx, st, FX_K_VX_PENCIL_Z, 2.0 * vol, &slot));
+        FX_TRY(ct_pass_b<T>(ctx, st, g.nx, cb));
+        FX_TRY(prof_end(ctx, st, slot));
+        FX_TRY(prof_begin(ctx, st, FX_K_VX_PLANE_INV, 2.0 * vol + accb, &slot));
+        FX_TRY((ct_pass_c<T, A>(ctx, st, g.nx, cb, ca)));
+        FX_TRY(prof_end(ctx, st, slot));
+        launches += 3;
+        continue;
+      }
       FX_TRY(prof_begin(ctx, st, FX_K_VX_PLANE_FWD, 3.0 * vol, &slot));
-      hipLaunchKernelGGL((k_pass_a<T>), dim3((unsigned)(npairs * g.nz)), dim3(nthr_a), lds_plane, st, psi, ld_psi,
-                         phi, ld_phi, reinterpret_cast<cpx<T>*>(work), j0, jb, k0, g, twx, twy);
+      FX_EPT_SWITCH(ept_p, {
+        auto kern = k_pass_a<T, E>;
+        FX_TRY(allow_lds(kern, lds_plane));
+        int grid = 0;
+        FX_TRY(persistent_grid(ctx, kern, nthr_p, lds_plane, npairs * g.nz, &grid));
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(nthr_p), lds_plane, st, psi, ld_psi, phi, ld_phi,
+                           reinterpret_cast<cpx<T>*>(work), j0, jb, k0, npairs * g.nz, g, twx, twy);
+      });
       FX_LAUNCH_CHECK();
       FX_TRY(prof_end(ctx, st, slot));
       FX_TRY(prof_begin(ctx, st, FX_K_VX_PENCIL_Z, 2.0 * vol, &slot));
-      hipLaunchKernelGGL((k_pass_b<T>), dim3((unsigned)(npairs * g.ny)), dim3(nthr_b), lds_xz, st,
-                         reinterpret_cast<cpx<T>*>(work), g, twz, kf, tb->fold[0], tb->fold[1], tb->fold[2]);
+      FX_EPT_SWITCH(ept_b, {
+        auto kern = k_pass_b<T, E>;
+        FX_TRY(allow_lds(kern, lds_b));
+        hipLaunchKernelGGL(kern, dim3((unsigned)((int64_t)npairs * g.ny * ntx)), dim3(nthr_b), lds_b, st,
+                           reinterpret_cast<cpx<T>*>(work), xt, ntx, g, twz, kf, tb->fold[0], tb->fold[1],
+                           tb->fold[2]);
+      });
       FX_LAUNCH_CHECK();
       FX_TRY(prof_end(ctx, st, slot));
       FX_TRY(prof_begin(ctx, st, FX_K_VX_PLANE_INV, 2.0 * vol + accb, &slot));
-      FX_TRY((launch_pass_c<T, A>(g, 0, dim3((unsigned)(kb * g.nz)), lds_plane, st, psi, ld_psi,
-                                  reinterpret_cast<const cpx<T>*>(work), j0, jb, k0, acc, ld_acc, first, a.out,
-                                  a.ld_out, out_c64 ? 1 : 0, last, twx, twy)));
+      FX_EPT_SWITCH(ept_p, {
+        // prefetching the next work plane needs registers the FP64 form and
+        // the largest planes do not have
+        auto kern = pipe_c ? k_pass_c<T, A, E, sizeof(T) == 4> : k_pass_c<T, A, E, false>;
+        FX_TRY(allow_lds(kern, lds_plane));
+        int grid = 0;
+        FX_TRY(persistent_grid(ctx, kern, nthr_p, lds_plane, kb * g.nz, &grid));
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(nthr_p), lds_plane, st, psi, ld_psi,
+                           reinterpret_cast<const cpx<T>*>(work), j0, jb, k0, kb * g.nz, acc, ld_acc, first, a.out,
+                           a.ld_out, out_c64 ? 1 : 0, last, g, twx, twy);
+      });
+      FX_LAUNCH_CHECK();
       FX_TRY(prof_end(ctx, st, slot));
       launches += 3;
     }
@@ -448,11 +608,12 @@ fx_status vx_apply(fx_ctx* ctx, Workspace* ws, const VxArgs& a, hipStream_t st, 
 }
 
 // Host run of the pass bodies for one pair: v = (-scale/Omega) *
-// IFFT_u[K FFT_u(conj(psi_j) phi_k)], with the device code's plans, twiddles
-// and folded kernel table, in FP64 (prec 0) or FP32 (prec 1).  Inputs and
-// outputs are host arrays of N_r interleaved complex doubles.
+// IFFT_u[K FFT_u(conj(psi_j) phi_k)], with the device code's plans, twiddles,
+// folded kernel table and z-tiling, in FP64 (prec 0) or FP32 (prec 1).
+// Inputs and outputs are host arrays of N_r interleaved complex doubles.
 template <typename T>
-static void host_pair(const fx_cell* cell, const HostTables& h, const double* psi_j, const double* phi_k, double* v) {
+static void host_pair(const fx_cell* cell, const HostTables& h, const double* psi_j, const double* phi_k, double* v,
+                      int xtile) {
   const PassGeom g = make_geom(cell);
   const size_t nxy = (size_t)g.nx * g.ny, nr = nxy * g.nz;
   std::vector<cpx<T>> a(nr), b(nr), vol(nr);
@@ -463,14 +624,21 @@ static void host_pair(const fx_cell* cell, const HostTables& h, const double* ps
   std::vector<cpx<T>> tw[3];
   for (int ax = 0; ax < 3; ++ax)
     for (auto& c : h.tw[ax]) tw[ax].push_back({(T)c.x, (T)c.y});
-  std::vector<T> kf(h.kfold.begin(), h.kfold.end());
-  std::vector<cpx<T>> s((size_t)std::max(plane_lds_elems(g), xz_lds_elems(g)));
+  const int xt = std::max(1, std::min(g.nx, xtile));
+  std::vector<cpx<T>> s((size_t)std::max(plane_lds_elems(g), g.nz * xt));
   for (int z = 0; z < g.nz; ++z)
     pass_a_body<T>(a.data() + z * nxy, b.data() + z * nxy, vol.data() + z * nxy, s.data(), tw[0].data(), tw[1].data(),
                    g, 0, 1, HostSync{});
-  for (int y = 0; y < g.ny; ++y)
-    pass_b_body<T>(vol.data(), y, s.data(), tw[2].data(), kf.data(), h.fold[0].data(), h.fold[2].data(), h.fold[1][y], g,
-                   0, 1, HostSync{});
+  std::vector<T> kl((size_t)g.hz * g.hx);
+  for (int y = 0; y < g.ny; ++y) {
+    const int fy = h.fold[1][y];
+    for (int fz = 0; fz < g.hz; ++fz)
+      for (int fx = 0; fx < g.hx; ++fx) kl[fz * g.hx + fx] = (T)h.kfold[((size_t)fz * g.hy + fy) * g.hx + fx];
+    for (int x0 = 0; x0 < g.nx; x0 += xt) {
+      const KSlice<T> kf{kl.data(), h.fold[0].data(), h.fold[2].data(), x0, g.nx, g.hx};
+      pass_b_body<T>(vol.data(), y, x0, xt, s.data(), tw[2].data(), kf, g, 0, 1, HostSync{});
+    }
+  }
   for (int z = 0; z < g.nz; ++z) {
     pass_c_fft<T>(vol.data() + z * nxy, s.data(), tw[0].data(), tw[1].data(), g, 0, 1, HostSync{});
     for (size_t e = 0; e < nxy; ++e) {
@@ -510,7 +678,8 @@ fx_status fx_apply_vx(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* kernel,
   a.prec = prec;
   a.ex_dev = ex_energy_dev;
   if (const char* e = getenv("FX_VX_NJ")) a.force_nj = atoi(e);
-  if (const char* e = getenv("FX_VX_NTHR_A")) a.nthr_a = atoi(e);
+  if (const char* e = getenv("FX_VX_XT")) a.xtile = atoi(e);
+  if (const char* e = getenv("FX_VX_PIPE")) a.pipe = atoi(e);
   if (const char* e = getenv("FX_VX_NTHR_B")) a.nthr_b = atoi(e);
   hipStream_t st = (hipStream_t)stream;
   return vx_apply(ctx, &ctx->ws, a, st, nullptr);
@@ -518,6 +687,8 @@ fx_status fx_apply_vx(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* kernel,
 
 fx_status fx_debug_host_pair(const fx_cell* cell, const fx_kernel* kernel, int prec, const double* psi_j,
                              const double* phi_k, double* v) {
+  int xtile = cell ? cell->n[0] : 1;
+  if (const char* e = getenv("FX_VX_XT")) xtile = atoi(e);
   clear_error();
   FX_TRY(check_cell(cell));
   FX_TRY(check_kernel(kernel));
@@ -525,9 +696,9 @@ fx_status fx_debug_host_pair(const fx_cell* cell, const fx_kernel* kernel, int p
   HostTables h;
   host_tables(cell, kernel, &h);
   if (prec == 0)
-    host_pair<double>(cell, h, psi_j, phi_k, v);
+    host_pair<double>(cell, h, psi_j, phi_k, v, xtile);
   else
-    host_pair<float>(cell, h, psi_j, phi_k, v);
+    host_pair<float>(cell, h, psi_j, phi_k, v, xtile);
   return FX_OK;
 }
 

@@ -24,13 +24,46 @@ struct VxArgs {
   // tuning (0 = automatic)
   size_t work_cap = 0;  // bytes of pair work volume per batch
   int force_nj = 0;     // orbitals per batch
-  int nthr_a = 0, nthr_b = 0;
+  int nthr_b = 0;  // threads of the pencil pass
+  int xtile = 0;   // x columns per pencil-pass workgroup
+  int pipe = -1;   // plane-inverse pass prefetches the next plane: 1 yes, 0 no, -1 automatic
 };
 
 struct VxStats {
   int nk = 0, nj = 0;
   int64_t launches = 0;
 };
+
+// One batch of the pair passes for the compile-time-specialised kernels
+// (cubic grids of edge 24, 48, 72 or 96; vx_ct.hip).
+template <typename T>
+struct CtBatch {
+  const cpx<T>* psi;
+  int64_t ld_psi;
+  const cpx<T>* phi;
+  int64_t ld_phi;
+  cpx<T>* work;
+  int j0, nj, k0, nk, npairs;
+  const cpx<T>* tw;  // twiddles of the edge (all three axes share them)
+  const T* kfold;
+  const int* fold;  // folded frequency per digit-reversed position
+};
+template <typename A>
+struct CtAcc {
+  cpx<A>* acc;
+  int64_t ld_acc;
+  int first;
+  void* out;
+  int64_t ld_out;
+  int out_c64, last, pipe;
+};
+bool ct_supported(const fx_cell* cell);
+template <typename T>
+fx_status ct_pass_a(fx_ctx* ctx, hipStream_t st, int n, const CtBatch<T>& b);
+template <typename T>
+fx_status ct_pass_b(fx_ctx* ctx, hipStream_t st, int n, const CtBatch<T>& b);
+template <typename T, typename A>
+fx_status ct_pass_c(fx_ctx* ctx, hipStream_t st, int n, const CtBatch<T>& b, const CtAcc<A>& c);
 
 fx_status check_vx_args(const VxArgs& a);
 // Copy ncols columns of nr complex values between dtypes (strided).

@@ -1,0 +1,312 @@
+// V_X pair passes specialised at compile time for the cubic grids of the
+// workloads (edges 24, 48, 72, 96).  Same three passes and data layout as the
+// generic kernels in vx.hip (see vx_passes.hpp); every shape is a constant.
+#include <algorithm>
+
+#include "fft_ct.hpp"
+#include "vx.hpp"
+#include "vx_passes.hpp"
+
+namespace fx {
+
+template <int A, int B>
+struct CeilDiv {
+  static constexpr int value = (A + B - 1) / B;
+};
+
+// ---- pass A: pair product, forward FFT x and y (persistent, pipelined) ------
+template <typename T, int N>
+__global__ void __launch_bounds__(CubeShape<N>::NT_P) k_pass_a_ct(const cpx<T>* __restrict__ psi, int64_t ld_psi,
+                                                                  const cpx<T>* __restrict__ phi, int64_t ld_phi,
+                                                                  cpx<T>* __restrict__ work, int j0, int nj, int k0,
+                                                                  int nitems, const cpx<T>* __restrict__ twg) {
+  constexpr int NT = CubeShape<N>::NT_P, NXY = N * N, SX = N + 1, EPT = CeilDiv<NXY, NT>::value;
+  constexpr size_t NR = (size_t)NXY * N;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<T>* s = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* tw = s + N * SX;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < N; i += NT) tw[i] = twg[i];
+  cpx<T> va[EPT], vb[EPT];
+  auto fetch = [&](int it) __attribute__((always_inline)) {
+    if (it >= nitems) return;
+    const int z = it % N, p = it / N;
+    const cpx<T>* a = psi + (int64_t)(j0 + p % nj) * ld_psi + (size_t)z * NXY;
+    const cpx<T>* b = phi + (int64_t)(k0 + p / nj) * ld_phi + (size_t)z * NXY;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int e = tid + i * NT;
+      if (NXY % NT == 0 || e < NXY) {
+        va[i] = a[e];
+        vb[i] = b[e];
+      }
+    }
+  };
+  constexpr bool kPipe = sizeof(T) == 4;
+  int item = blockIdx.x;
+  if (kPipe) fetch(item);
+  for (; item < nitems; item += gridDim.x) {
+    if (!kPipe) fetch(item);
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int e = tid + i * NT;
+      if (NXY % NT == 0 || e < NXY) s[(e / N) * SX + e % N] = cconjmul(va[i], vb[i]);
+    }
+    __syncthreads();
+    if (kPipe) fetch(item + gridDim.x);
+    ct_fft<true, T, N, N, 1, SX, NT>(s, tw, tid);
+    ct_fft<true, T, N, N, SX, 1, NT>(s, tw, tid);
+    const int z = item % N, p = item / N;
+    cpx<T>* o = work + p * NR + (size_t)z * NXY;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int e = tid + i * NT;
+      if (NXY % NT == 0 || e < NXY) o[e] = s[(e / N) * SX + e % N];
+    }
+    __syncthreads();
+  }
+}
+
+// ---- pass B: z convolution on an x tile ---------------------------------------
+template <typename T, int N>
+__global__ void __launch_bounds__(CubeShape<N>::NT_B) k_pass_b_ct(cpx<T>* __restrict__ work,
+                                                                  const cpx<T>* __restrict__ twg,
+                                                                  const T* __restrict__ kfold,
+                                                                  const int* __restrict__ foldg) {
+  constexpr int NT = CubeShape<N>::NT_B, XT = CubeShape<N>::XT, NTX = N / XT, NE = N * XT;
+  constexpr int EPT = CeilDiv<NE, NT>::value, H = N / 2 + 1;
+  static_assert(N % XT == 0, "x tile must divide the edge");
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<T>* s = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* tw = s + NE;
+  T* kl = reinterpret_cast<T*>(tw + N);
+  int* fl = reinterpret_cast<int*>(kl + H * H);
+  const int tid = threadIdx.x;
+  const int tx = blockIdx.x % NTX;
+  const int rest = blockIdx.x / NTX;
+  const int y = rest % N;
+  const int p = rest / N;
+  const int x0 = tx * XT;
+  cpx<T>* vol = work + (size_t)p * N * N * N;
+  cpx<T> v[EPT];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = tid + i * NT;
+    if (NE % NT == 0 || e < NE) v[i] = vol[((size_t)(e / XT) * N + y) * N + x0 + e % XT];
+  }
+  const int fy = foldg[y];
+  for (int i = tid; i < N; i += NT) {
+    tw[i] = twg[i];
+    fl[i] = foldg[i];
+  }
+  for (int i = tid; i < H * H; i += NT) kl[i] = kfold[((size_t)(i / H) * H + fy) * H + i % H];
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = tid + i * NT;
+    if (NE % NT == 0 || e < NE) s[e] = v[i];
+  }
+  __syncthreads();
+  auto kf = [=](int pos, int f) __attribute__((always_inline)) { return kl[fl[pos] * H + fl[x0 + f]]; };
+  ct_conv<T, N, XT, XT, 1, NT>(s, tw, kf, tid);
+#pragma unroll
+  for (int i = 0; i < EPT; ++i) {
+    const int e = tid + i * NT;
+    if (NE % NT == 0 || e < NE) vol[((size_t)(e / XT) * N + y) * N + x0 + e % XT] = s[e];
+  }
+}
+
+// ---- pass C: inverse FFT y and x, times psi_j, j-sum in registers --------------
+template <typename T, typename A, int N, bool PIPE>
+__global__ void __launch_bounds__(CubeShape<N>::NT_P) k_pass_c_ct(const cpx<T>* __restrict__ psi, int64_t ld_psi,
+                                                                  const cpx<T>* __restrict__ work, int j0, int nj,
+                                                                  int k0, int nitems, cpx<A>* acc, int64_t ld_acc,
+                                                                  int first, void* out, int64_t ld_out, int out_c64,
+                                                                  int last, const cpx<T>* __restrict__ twg) {
+  constexpr int NT = CubeShape<N>::NT_P, NXY = N * N, SX = N + 1, EPT = CeilDiv<NXY, NT>::value;
+  constexpr size_t NR = (size_t)NXY * N;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<T>* s = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* tw = s + N * SX;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < N; i += NT) tw[i] = twg[i];
+  for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
+    const int z = item % N;
+    const int kk = item / N;
+    const int k = k0 + kk;
+    cpx<A> a[EPT];
+    cpx<T> vt[EPT], vp[EPT];
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int e = tid + i * NT;
+      a[i] = cpx<A>{0, 0};
+      if (!first && (NXY % NT == 0 || e < NXY)) a[i] = acc[k * ld_acc + (size_t)z * NXY + e];
+    }
+    auto tload = [&](int jj) __attribute__((always_inline)) {
+      const cpx<T>* tp = work + ((size_t)kk * nj + jj) * NR + (size_t)z * NXY;
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) {
+        const int e = tid + i * NT;
+        if (NXY % NT == 0 || e < NXY) vt[i] = tp[e];
+      }
+    };
+    if (PIPE) tload(0);
+    for (int jj = 0; jj < nj; ++jj) {
+      if (!PIPE) tload(jj);
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) {
+        const int e = tid + i * NT;
+        if (NXY % NT == 0 || e < NXY) s[(e / N) * SX + e % N] = vt[i];
+      }
+      __syncthreads();
+      const cpx<T>* pj = psi + (int64_t)(j0 + jj) * ld_psi + (size_t)z * NXY;
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) {
+        const int e = tid + i * NT;
+        if (NXY % NT == 0 || e < NXY) vp[i] = pj[e];
+      }
+      if (PIPE && jj + 1 < nj) tload(jj + 1);
+      ct_fft<false, T, N, N, SX, 1, NT>(s, tw, tid);
+      ct_fft<false, T, N, N, 1, SX, NT>(s, tw, tid);
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) {
+        const int e = tid + i * NT;
+        if (NXY % NT == 0 || e < NXY) {
+          const cpx<T> v = s[(e / N) * SX + e % N];
+          a[i] = cadd(a[i], cmul(cpx<A>{(A)vp[i].x, (A)vp[i].y}, cpx<A>{(A)v.x, (A)v.y}));
+        }
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int e = tid + i * NT;
+      if (!(NXY % NT == 0 || e < NXY)) continue;
+      const size_t off = (size_t)z * NXY + e;
+      if (last) {
+        if (out_c64)
+          reinterpret_cast<cpx<float>*>(out)[k * ld_out + off] = cpx<float>{(float)a[i].x, (float)a[i].y};
+        else
+          reinterpret_cast<cpx<double>*>(out)[k * ld_out + off] = cpx<double>{(double)a[i].x, (double)a[i].y};
+      } else {
+        acc[k * ld_acc + off] = a[i];
+      }
+    }
+  }
+}
+
+// ---- host side ------------------------------------------------------------------
+bool ct_supported(const fx_cell* cell) {
+  const int n = cell->n[0];
+  if (cell->n[1] != n || cell->n[2] != n) return false;
+  if (getenv("FX_VX_GENERIC")) return false;
+  AxisPlan p;
+  if (!make_axis_plan(n, &p) || p.nst != 2) return false;
+  switch (n) {
+    case 24: return p.R[0] == Plan2<24>::R0 && p.R[1] == Plan2<24>::R1;
+    case 48: return p.R[0] == Plan2<48>::R0 && p.R[1] == Plan2<48>::R1;
+    case 72: return p.R[0] == Plan2<72>::R0 && p.R[1] == Plan2<72>::R1;
+    case 96: return p.R[0] == Plan2<96>::R0 && p.R[1] == Plan2<96>::R1;
+    default: return false;
+  }
+}
+
+template <typename K>
+static fx_status ct_prepare(fx_ctx* ctx, K kernel, int nthr, size_t lds, int items, bool persistent, int* grid) {
+  if (lds > 65536)
+    FX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)lds));
+  if (!persistent) {
+    *grid = items;
+    return FX_OK;
+  }
+  int per_cu = 0;
+  FX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kernel), nthr, lds));
+  *grid = std::max(1, std::min(items, std::max(per_cu, 1) * std::max(ctx->n_cu, 1)));
+  return FX_OK;
+}
+
+template <typename T, int N>
+static fx_status pass_a_n(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b) {
+  constexpr int NT = CubeShape<N>::NT_P;
+  const size_t lds = ((size_t)N * (N + 1) + N) * sizeof(cpx<T>);
+  auto kern = k_pass_a_ct<T, N>;
+  const int items = b.npairs * N;
+  int grid = 0;
+  FX_TRY(ct_prepare(ctx, kern, NT, lds, items, true, &grid));
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, st, b.psi, b.ld_psi, b.phi, b.ld_phi, b.work, b.j0, b.nj, b.k0,
+                     items, b.tw);
+  FX_LAUNCH_CHECK();
+  return FX_OK;
+}
+
+template <typename T, int N>
+static fx_status pass_b_n(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b) {
+  constexpr int NT = CubeShape<N>::NT_B, XT = CubeShape<N>::XT, H = N / 2 + 1;
+  const size_t lds = ((size_t)N * XT + N) * sizeof(cpx<T>) + (size_t)H * H * sizeof(T) + (size_t)N * sizeof(int);
+  auto kern = k_pass_b_ct<T, N>;
+  const int items = b.npairs * N * (N / XT);
+  int grid = 0;
+  FX_TRY(ct_prepare(ctx, kern, NT, lds, items, false, &grid));
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, st, b.work, b.tw, b.kfold, b.fold);
+  FX_LAUNCH_CHECK();
+  return FX_OK;
+}
+
+template <typename T, typename A, int N>
+static fx_status pass_c_n(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b, const CtAcc<A>& c) {
+  constexpr int NT = CubeShape<N>::NT_P;
+  const size_t lds = ((size_t)N * (N + 1) + N) * sizeof(cpx<T>);
+  const int items = b.nk * N;
+  // prefetching the next plane: FP32 planes below 96^2 have the registers
+  const bool pipe = c.pipe >= 0 ? (c.pipe != 0 && sizeof(T) == 4) : (sizeof(T) == 4 && N < 96);
+  auto kern = pipe ? k_pass_c_ct<T, A, N, sizeof(T) == 4> : k_pass_c_ct<T, A, N, false>;
+  int grid = 0;
+  FX_TRY(ct_prepare(ctx, kern, NT, lds, items, true, &grid));
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, st, b.psi, b.ld_psi, (const cpx<T>*)b.work, b.j0, b.nj, b.k0,
+                     items, c.acc, c.ld_acc, c.first, c.out, c.ld_out, c.out_c64, c.last, b.tw);
+  FX_LAUNCH_CHECK();
+  return FX_OK;
+}
+
+template <typename T>
+fx_status ct_pass_a(fx_ctx* ctx, hipStream_t st, int n, const CtBatch<T>& b) {
+  switch (n) {
+    case 24: return pass_a_n<T, 24>(ctx, st, b);
+    case 48: return pass_a_n<T, 48>(ctx, st, b);
+    case 72: return pass_a_n<T, 72>(ctx, st, b);
+    case 96: return pass_a_n<T, 96>(ctx, st, b);
+    default: FX_FAIL(FX_ERR_UNSUPPORTED, "no specialised kernels for edge %d", n);
+  }
+}
+
+template <typename T>
+fx_status ct_pass_b(fx_ctx* ctx, hipStream_t st, int n, const CtBatch<T>& b) {
+  switch (n) {
+    case 24: return pass_b_n<T, 24>(ctx, st, b);
+    case 48: return pass_b_n<T, 48>(ctx, st, b);
+    case 72: return pass_b_n<T, 72>(ctx, st, b);
+    case 96: return pass_b_n<T, 96>(ctx, st, b);
+    default: FX_FAIL(FX_ERR_UNSUPPORTED, "no specialised kernels for edge %d", n);
+  }
+}
+
+template <typename T, typename A>
+fx_status ct_pass_c(fx_ctx* ctx, hipStream_t st, int n, const CtBatch<T>& b, const CtAcc<A>& c) {
+  switch (n) {
+    case 24: return pass_c_n<T, A, 24>(ctx, st, b, c);
+    case 48: return pass_c_n<T, A, 48>(ctx, st, b, c);
+    case 72: return pass_c_n<T, A, 72>(ctx, st, b, c);
+    case 96: return pass_c_n<T, A, 96>(ctx, st, b, c);
+    default: FX_FAIL(FX_ERR_UNSUPPORTED, "no specialised kernels for edge %d", n);
+  }
+}
+
+template fx_status ct_pass_a<float>(fx_ctx*, hipStream_t, int, const CtBatch<float>&);
+template fx_status ct_pass_a<double>(fx_ctx*, hipStream_t, int, const CtBatch<double>&);
+template fx_status ct_pass_b<float>(fx_ctx*, hipStream_t, int, const CtBatch<float>&);
+template fx_status ct_pass_b<double>(fx_ctx*, hipStream_t, int, const CtBatch<double>&);
+template fx_status ct_pass_c<float, double>(fx_ctx*, hipStream_t, int, const CtBatch<float>&, const CtAcc<double>&);
+template fx_status ct_pass_c<float, float>(fx_ctx*, hipStream_t, int, const CtBatch<float>&, const CtAcc<float>&);
+template fx_status ct_pass_c<double, double>(fx_ctx*, hipStream_t, int, const CtBatch<double>&, const CtAcc<double>&);
+
+}  // namespace fx

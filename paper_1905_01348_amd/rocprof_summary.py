@@ -1,0 +1,120 @@
+"""Summaries of rocprofv3 output for the profiles/ directory.
+
+    python -m paper_1905_01348_amd.rocprof_summary stats <kernel_stats.csv> [--title T] [--command C]
+        -> a Markdown table of per-kernel calls and durations.
+
+    python -m paper_1905_01348_amd.rocprof_summary counters --fetch <dir> --write <dir>
+           --copy-fetch <dir> --copy-write <dir> --kernel <substring> --prec <p> --source-hash <h>
+           [--out profiles/vx_counters.json] [--command C]
+        -> HBM traffic per launch of one kernel from FETCH_SIZE and WRITE_SIZE
+           (KiB per dispatch), each scaled by the factor that makes a plain
+           1 GiB device copy read and write exactly 1 GiB.
+
+Input directories are rocprofv3 -d output folders written with
+--output-format csv (the counter runs produce *counter_collection.csv).
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import json
+import os
+import sys
+
+
+def _find(d, pattern):
+    hits = sorted(glob.glob(os.path.join(d, "**", pattern), recursive=True))
+    if not hits:
+        raise FileNotFoundError(f"no {pattern} under {d}")
+    return hits[0]
+
+
+def stats(path, title=None, command=None):
+    rows = list(csv.DictReader(open(path)))
+    out = []
+    if title:
+        out.append(f"# {title}\n")
+    if command:
+        out.append(f"Command:\n\n```\n{command}\n```\n")
+    out.append("| kernel | calls | total ms | average ms | min ms | max ms | % |")
+    out.append("|---|---|---|---|---|---|---|")
+    for r in rows:
+        name = r.get("Name", r.get("KernelName", ""))
+        calls = int(float(r.get("Calls", 0)))
+        tot = float(r.get("TotalDurationNs", 0)) / 1e6
+        avg = float(r.get("AverageNs", 0)) / 1e6
+        mn = float(r.get("MinNs", 0)) / 1e6
+        mx = float(r.get("MaxNs", 0)) / 1e6
+        pct = float(r.get("Percentage", 0))
+        out.append(f"| `{name[:90]}` | {calls} | {tot:.2f} | {avg:.4f} | {mn:.4f} | {mx:.4f} | {pct:.1f} |")
+    return "\n".join(out) + "\n"
+
+
+def _counter_rows(d, counter):
+    path = _find(d, "*counter_collection.csv")
+    rows = []
+    for r in csv.DictReader(open(path)):
+        if r.get("Counter_Name", r.get("Counter-Name", "")) != counter:
+            continue
+        name = r.get("Kernel_Name", r.get("Kernel-Name", ""))
+        val = float(r.get("Counter_Value", r.get("Counter-Value", 0)))
+        disp = r.get("Dispatch_Id", r.get("Dispatch-Id", ""))
+        rows.append((disp, name, val))
+    return rows
+
+
+def _per_dispatch(rows):
+    acc = {}
+    for disp, name, val in rows:
+        key = (disp, name)
+        acc[key] = acc.get(key, 0.0) + val
+    return acc
+
+
+def counters(fetch, write, copy_fetch, copy_write, kernel, prec, source_hash, command=None):
+    one_gib_kib = float(1 << 20)
+    # calibration: the largest dispatch of the copy run is the 1 GiB copy
+    cf = max(_per_dispatch(_counter_rows(copy_fetch, "FETCH_SIZE")).values())
+    cw = max(_per_dispatch(_counter_rows(copy_write, "WRITE_SIZE")).values())
+    sf, sw = one_gib_kib / cf, one_gib_kib / cw
+    f = [v for (d, n), v in _per_dispatch(_counter_rows(fetch, "FETCH_SIZE")).items() if kernel in n]
+    w = [v for (d, n), v in _per_dispatch(_counter_rows(write, "WRITE_SIZE")).items() if kernel in n]
+    if not f or not w:
+        raise ValueError(f"kernel {kernel!r} not found in the counter runs")
+    fetch_b = sum(f) / len(f) * 1024 * sf
+    write_b = sum(w) / len(w) * 1024 * sw
+    return {
+        "kernel": kernel, "prec": prec, "source_hash": source_hash,
+        "fetch_bytes_per_launch": fetch_b, "write_bytes_per_launch": write_b,
+        "bytes_per_launch": fetch_b + write_b,
+        "copy_scale_fetch": sf, "copy_scale_write": sw, "launches": [len(f), len(w)],
+        "command": command,
+    }
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("csv")
+    s.add_argument("--title")
+    s.add_argument("--command")
+    c = sub.add_parser("counters")
+    for k in ("--fetch", "--write", "--copy-fetch", "--copy-write", "--kernel", "--prec", "--source-hash"):
+        c.add_argument(k, required=True)
+    c.add_argument("--out")
+    c.add_argument("--command")
+    a = ap.parse_args(argv)
+    if a.cmd == "stats":
+        sys.stdout.write(stats(a.csv, a.title, a.command))
+    else:
+        res = counters(a.fetch, a.write, a.copy_fetch, a.copy_write, a.kernel, a.prec, a.source_hash, a.command)
+        txt = json.dumps(res, indent=1)
+        if a.out:
+            open(a.out, "w").write(txt + "\n")
+        print(txt)
+
+
+if __name__ == "__main__":
+    main()

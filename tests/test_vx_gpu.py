@@ -206,3 +206,28 @@ def test_error_paths(ctx, cfg0):
     out = ctx.apply_vx(P, n=w["n"], L=w["L"], prec="fp64", kernel="coulomb")
     torch.cuda.synchronize()
     assert torch.isfinite(torch.view_as_real(out)).all()
+
+
+@pytest.mark.parametrize("n", [24, 48, 72, 96])
+def test_specialised_kernels_match_generic_and_oracle(ctx, n):
+    """Cubic workload edges run compile-time-specialised kernels; check them against
+    the generic kernels (FX_VX_GENERIC) and against the oracle on a small block."""
+    import torch
+
+    L = n * 10.26 / 24
+    N, Nt = 3, 2
+    psi = synth.make_orbitals(30 + n, n, L, N)
+    phi = synth.random_grid_vectors(31 + n, n, Nt)
+    ref = oracle.apply_vx(psi, phi, n, L, "hse", 0.106)
+    P, F = dev(psi), dev(phi)
+    for prec, tol in (("fp64", TOL64), ("fp32acc64", TOL32), ("fp32", TOL32)):
+        spec = host(ctx.apply_vx(P, F, n=n, L=L, kernel="hse", prec=prec))
+        os.environ["FX_VX_GENERIC"] = "1"
+        try:
+            gen = host(ctx.apply_vx(P, F, n=n, L=L, kernel="hse", prec=prec))
+        finally:
+            os.environ.pop("FX_VX_GENERIC", None)
+        torch.cuda.synchronize()
+        e_spec, e_gen = col_err(spec, ref), col_err(gen, ref)
+        say("edge", n, prec, "specialised", e_spec, "generic", e_gen, "diff", col_err(spec, gen))
+        assert e_spec <= tol and e_gen <= tol
