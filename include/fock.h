@@ -38,6 +38,15 @@
  *   read the Cholesky status) and fx_serve (runs to completion).  Workspace
  *   is allocated on the first use of a shape, inside the context's HBM
  *   budget; a later call with a shape already seen allocates nothing.
+ * Graph capture: fx_apply_vx and fx_apply_ace may be captured into a HIP
+ *   graph once the same call (same grid, kernel, precisions and sizes) has
+ *   run outside capture on the same context or fx_ace; a captured call that
+ *   would have to allocate or upload tables fails with FX_ERR_INVALID
+ *   instead.  The graph holds the workspace addresses of the time of
+ *   capture: a later uncaptured call that needs a larger workspace on that
+ *   context (or fx_ace) reallocates it, and graphs captured before must not
+ *   be replayed after that.  Per-kernel timing skips captured launches.
+ *   fx_build_ace and fx_serve wait on the host and refuse capture.
  * Errors: every call returns an fx_status.  Argument errors are reported
  *   synchronously before anything is enqueued; a text description of the
  *   last error on the calling thread is available from fx_last_error().

@@ -210,6 +210,8 @@ fx_status fx_build_ace(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* kernel
   if (!ctx) FX_FAIL(FX_ERR_INVALID, "ctx is NULL");
   std::lock_guard<std::recursive_mutex> lk(ctx->mu);
   FX_HIP(hipSetDevice(ctx->device));
+  FX_TRY(note_capture(ctx, (hipStream_t)stream));
+  if (ctx->capturing) FX_FAIL(FX_ERR_INVALID, "fx_build_ace waits on its stream and cannot be captured");
   return ace_build_impl(ctx, &ctx->ws, cell, kernel, psi, n_psi, ld_psi, in_dtype, vx_prec, ace_prec,
                         (hipStream_t)stream, ace, ex_energy);
 }
@@ -222,6 +224,7 @@ fx_status fx_apply_ace(fx_ctx* ctx, const fx_ace* ace, const void* phi, int32_t 
   if (ace->ctx != ctx) FX_FAIL(FX_ERR_INVALID, "ace was built on another context");
   std::lock_guard<std::recursive_mutex> lk(ctx->mu);
   FX_HIP(hipSetDevice(ctx->device));
+  FX_TRY(note_capture(ctx, (hipStream_t)stream));
   return ace_apply_impl(ctx, &const_cast<fx_ace*>(ace)->ws, ace, phi, n_phi, ld_phi, out, ld_out, in_dtype,
                         out_dtype, prec, (hipStream_t)stream);
 }

@@ -108,6 +108,9 @@ struct fx_ctx {
   std::recursive_mutex mu;
   fx::Workspace ws;  // workspace of the context's own calls
   std::map<fx::TableKey, fx::GridTables> tables;
+  // set by each entry point: the call's stream is being captured into a
+  // graph, so nothing may be allocated or uploaded synchronously
+  bool capturing = false;
   // per-kernel timing (fx_prof_enable)
   bool prof = false;
   std::vector<fx::ProfRec> prof_recs;
@@ -124,8 +127,16 @@ namespace fx {
 fx_status ctx_alloc(fx_ctx* ctx, size_t bytes, void** out);
 void ctx_free(fx_ctx* ctx, void* p, size_t bytes);
 
+// Let `kernel` use `bytes` of dynamic LDS on the current device (the
+// attribute is set once per device and kernel, never again afterwards).
+fx_status allow_dynamic_lds(const void* kernel, size_t bytes);
+
+// Record whether `st` is being captured into a graph (ctx->capturing).
+fx_status note_capture(fx_ctx* ctx, hipStream_t st);
+
 // Return workspace buffer `name` with at least `bytes`, growing it if needed
-// (growth waits for the device before freeing the old buffer).
+// (growth waits for the device before freeing the old buffer).  Under graph
+// capture growth is refused with FX_ERR_INVALID.
 fx_status ws_get(fx_ctx* ctx, Workspace* ws, const char* name, size_t bytes, void** out);
 void ws_release(fx_ctx* ctx, Workspace* ws);
 

@@ -69,6 +69,70 @@ FX_HD void ct_stage(cpx<T>* s, const cpx<T>* tw, int tid) {
   }
 }
 
+// A stage that reads its inputs from global memory (FROM_G) and/or writes its
+// outputs to global memory (TO_G) instead of LDS.  In global memory element i
+// of transform f is g[f*GFS + i*GES]; in LDS it is s[f*FS + i*ES].  With
+// consecutive threads on consecutive transforms f and GFS = 1, both accesses
+// are coalesced.  Used for the first stage of a pass (data straight from
+// HBM) and its last stage (results straight to HBM), saving an LDS round
+// trip and a barrier at each end.
+template <int R, bool FWD, typename T, int N, int L, int COUNT, int ES, int FS, int NTHR, bool FROM_G, bool TO_G,
+          int GES, int GFS>
+FX_HD void ct_stage_io(cpx<T>* s, const cpx<T>* gin, cpx<T>* gout, const cpx<T>* tw, int tid) {
+  constexpr int SPAN = L / R, TOTAL = COUNT * (N / R), TSTEP = N / L;
+  constexpr int ITERS = (TOTAL + NTHR - 1) / NTHR;
+  cpx<T> x[ITERS][R];
+  // loads of every butterfly of this thread first, so they are all in flight
+#pragma unroll
+  for (int it = 0; it < ITERS; ++it) {
+    const int b = tid + it * NTHR;
+    if (TOTAL % NTHR == 0 || b < TOTAL) {
+      const int f = b % COUNT;
+      const int q = b / COUNT;
+      const int blk = q / SPAN;
+      const int i2 = q - blk * SPAN;
+      const int pos0 = blk * L + i2;
+#pragma unroll
+      for (int m = 0; m < R; ++m) {
+        const int pos = pos0 + m * SPAN;
+        x[it][m] = FROM_G ? gin[f * GFS + pos * GES] : s[f * FS + pos * ES];
+      }
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < ITERS; ++it) {
+    const int b = tid + it * NTHR;
+    if (TOTAL % NTHR == 0 || b < TOTAL) {
+      const int f = b % COUNT;
+      const int q = b / COUNT;
+      const int blk = q / SPAN;
+      const int i2 = q - blk * SPAN;
+      const int pos0 = blk * L + i2;
+      if (FWD) {
+        Dft<R, -1, T>::run(x[it]);
+        if (SPAN > 1) {
+#pragma unroll
+          for (int k = 1; k < R; ++k) x[it][k] = cmul(x[it][k], tw[i2 * k * TSTEP]);
+        }
+      } else {
+        if (SPAN > 1) {
+#pragma unroll
+          for (int k = 1; k < R; ++k) x[it][k] = cmulc(x[it][k], tw[i2 * k * TSTEP]);
+        }
+        Dft<R, 1, T>::run(x[it]);
+      }
+#pragma unroll
+      for (int m = 0; m < R; ++m) {
+        const int pos = pos0 + m * SPAN;
+        if (TO_G)
+          gout[f * GFS + pos * GES] = x[it][m];
+        else
+          s[f * FS + pos * ES] = x[it][m];
+      }
+    }
+  }
+}
+
 // Full forward or inverse transform along one axis (two stages + barriers).
 template <bool FWD, typename T, int N, int COUNT, int ES, int FS, int NTHR>
 __device__ inline void ct_fft(cpx<T>* s, const cpx<T>* tw, int tid) {

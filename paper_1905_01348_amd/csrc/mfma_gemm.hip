@@ -367,9 +367,7 @@ __global__ void k_reduce_cn(const double* __restrict__ partial, int nsplit, int 
 // ---------------------------------------------------------------------------
 template <typename K>
 static fx_status allow_lds_mfma(K kernel, size_t bytes) {
-  if (bytes > 65536) FX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
-  return FX_OK;
+  return allow_dynamic_lds(reinterpret_cast<const void*>(kernel), bytes);
 }
 
 template <typename S>

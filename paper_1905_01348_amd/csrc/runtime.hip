@@ -64,12 +64,41 @@ void ctx_free(fx_ctx* ctx, void* p, size_t bytes) {
   ctx->in_use -= bytes;
 }
 
+fx_status allow_dynamic_lds(const void* kernel, size_t bytes) {
+  static std::mutex mu;
+  static std::map<std::pair<int, const void*>, size_t> done;
+  if (bytes <= 65536) return FX_OK;
+  int dev = 0;
+  FX_HIP(hipGetDevice(&dev));
+  const std::pair<int, const void*> key(dev, kernel);
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = done.find(key);
+  if (it != done.end() && it->second >= bytes) return FX_OK;
+  FX_HIP(hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  done[key] = bytes;
+  return FX_OK;
+}
+
+fx_status note_capture(fx_ctx* ctx, hipStream_t st) {
+  ctx->capturing = false;
+  if (!st) return FX_OK;  // the null stream is never captured
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  FX_HIP(hipStreamIsCapturing(st, &cs));
+  ctx->capturing = cs != hipStreamCaptureStatusNone;
+  return FX_OK;
+}
+
 fx_status ws_get(fx_ctx* ctx, Workspace* ws, const char* name, size_t bytes, void** out) {
   DevBuf& b = ws->bufs[name];
   if (b.bytes >= bytes && b.ptr) {
     *out = b.ptr;
     return FX_OK;
   }
+  if (ctx->capturing)
+    FX_FAIL(FX_ERR_INVALID,
+            "workspace '%s' must grow to %zu bytes while the stream is being captured; "
+            "run the same call once outside capture first",
+            name, bytes);
   if (b.ptr) {
     // the old buffer may still be in use by queued work
     FX_HIP(hipDeviceSynchronize());
@@ -101,7 +130,7 @@ static fx_status take_event(fx_ctx* ctx, hipEvent_t* e) {
 
 fx_status prof_begin(fx_ctx* ctx, hipStream_t st, int id, double work, int* slot) {
   *slot = -1;
-  if (!ctx || !ctx->prof) return FX_OK;
+  if (!ctx || !ctx->prof || ctx->capturing) return FX_OK;
   ProfRec r;
   r.id = id;
   r.work = work;
@@ -284,6 +313,10 @@ fx_status grid_tables(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* kern, i
     *out = &it->second;
     return FX_OK;
   }
+  if (ctx->capturing)
+    FX_FAIL(FX_ERR_INVALID,
+            "grid tables for this cell and kernel are not on the device yet and the stream is being captured; "
+            "run the same call once outside capture first");
   HostTables h;
   host_tables(cell, kern, &h);
   GridTables t;

@@ -142,6 +142,7 @@ fx_status fx_serve_register(fx_server* srv, int32_t traj, const fx_cell* cell, c
   if (!srv) FX_FAIL(FX_ERR_INVALID, "srv is NULL");
   fx_ctx* ctx = srv->ctx;
   std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  ctx->capturing = false;  // the serving loop runs on its own, uncaptured streams
   FX_HIP(hipSetDevice(ctx->device));
   FX_TRY(check_cell(cell));
   FX_TRY(check_kernel(kernel));
@@ -184,6 +185,7 @@ fx_status fx_serve(fx_server* srv, const fx_request* reqs, int32_t n_reqs, fx_st
   if (n_reqs < 0 || (n_reqs > 0 && !reqs)) FX_FAIL(FX_ERR_INVALID, "bad request array");
   fx_ctx* ctx = srv->ctx;
   std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  ctx->capturing = false;  // the serving loop runs on its own, uncaptured streams
   FX_HIP(hipSetDevice(ctx->device));
   const int nq = n_reqs;
   std::vector<fx_status> status(nq, FX_ERR_CANCELLED);

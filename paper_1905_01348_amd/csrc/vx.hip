@@ -305,13 +305,7 @@ static int round64(int v) { return (v + 63) / 64 * 64; }
 
 template <typename K>
 static fx_status allow_lds(K kernel, size_t bytes) {
-  static std::set<const void*> done;
-  const void* key = reinterpret_cast<const void*>(kernel);
-  if (bytes > 65536 && !done.count(key)) {
-    FX_HIP(hipFuncSetAttribute(key, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
-    done.insert(key);
-  }
-  return FX_OK;
+  return allow_dynamic_lds(reinterpret_cast<const void*>(kernel), bytes);
 }
 
 // Workgroups of a persistent kernel: resident workgroups per CU x CUs.
@@ -325,7 +319,9 @@ static fx_status persistent_grid(fx_ctx* ctx, K kernel, int nthr, size_t lds, in
 }
 
 static size_t work_cap_bytes(fx_ctx* ctx) {
-  size_t cap = (size_t)4096 << 20;
+  // pair work volume per batch: 8 GiB (a few percent of HBM) keeps launches
+  // long and partial-sum traffic low; capped at a quarter of the budget
+  size_t cap = (size_t)8192 << 20;
   if (const char* e = getenv("FX_WORK_MB")) cap = (size_t)atol(e) << 20;
   if (cap > ctx->budget / 4) cap = ctx->budget / 4;
   return cap;
@@ -682,6 +678,7 @@ fx_status fx_apply_vx(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* kernel,
   if (const char* e = getenv("FX_VX_PIPE")) a.pipe = atoi(e);
   if (const char* e = getenv("FX_VX_NTHR_B")) a.nthr_b = atoi(e);
   hipStream_t st = (hipStream_t)stream;
+  FX_TRY(note_capture(ctx, st));
   return vx_apply(ctx, &ctx->ws, a, st, nullptr);
 }
 

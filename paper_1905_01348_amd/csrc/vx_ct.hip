@@ -55,14 +55,13 @@ __global__ void __launch_bounds__(CubeShape<N>::NT_P) k_pass_a_ct(const cpx<T>* 
     __syncthreads();
     if (kPipe) fetch(item + gridDim.x);
     ct_fft<true, T, N, N, 1, SX, NT>(s, tw, tid);
-    ct_fft<true, T, N, N, SX, 1, NT>(s, tw, tid);
+    // y: first stage in LDS, last stage straight to the work plane
+    constexpr int R0 = Plan2<N>::R0, R1 = Plan2<N>::R1;
+    ct_stage<R0, true, T, N, N, N, SX, 1, NT>(s, tw, tid);
+    __syncthreads();
     const int z = item % N, p = item / N;
     cpx<T>* o = work + p * NR + (size_t)z * NXY;
-#pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-      const int e = tid + i * NT;
-      if (NXY % NT == 0 || e < NXY) o[e] = s[(e / N) * SX + e % N];
-    }
+    ct_stage_io<R1, true, T, N, R1, N, SX, 1, NT, false, true, N, 1>(s, nullptr, o, tw, tid);
     __syncthreads();
   }
 }
@@ -74,7 +73,7 @@ __global__ void __launch_bounds__(CubeShape<N>::NT_B) k_pass_b_ct(cpx<T>* __rest
                                                                   const T* __restrict__ kfold,
                                                                   const int* __restrict__ foldg) {
   constexpr int NT = CubeShape<N>::NT_B, XT = CubeShape<N>::XT, NTX = N / XT, NE = N * XT;
-  constexpr int EPT = CeilDiv<NE, NT>::value, H = N / 2 + 1;
+  constexpr int H = N / 2 + 1;
   static_assert(N % XT == 0, "x tile must divide the edge");
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* s = reinterpret_cast<cpx<T>*>(smem_raw);
@@ -88,35 +87,49 @@ __global__ void __launch_bounds__(CubeShape<N>::NT_B) k_pass_b_ct(cpx<T>* __rest
   const int p = rest / N;
   const int x0 = tx * XT;
   cpx<T>* vol = work + (size_t)p * N * N * N;
-  cpx<T> v[EPT];
-#pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    const int e = tid + i * NT;
-    if (NE % NT == 0 || e < NE) v[i] = vol[((size_t)(e / XT) * N + y) * N + x0 + e % XT];
-  }
+  cpx<T>* g0 = vol + (size_t)y * N + x0;  // element (xi, z) at g0[xi + z*N*N]
   const int fy = foldg[y];
   for (int i = tid; i < N; i += NT) {
     tw[i] = twg[i];
     fl[i] = foldg[i];
   }
   for (int i = tid; i < H * H; i += NT) kl[i] = kfold[((size_t)(i / H) * H + fy) * H + i % H];
+  constexpr int R0 = Plan2<N>::R0, R1 = Plan2<N>::R1;
+  // first forward stage straight from the work volume (twiddles from the
+  // cached global table: the LDS copy is not yet visible)
+  ct_stage_io<R0, true, T, N, N, XT, XT, 1, NT, true, false, N * N, 1>(s, g0, nullptr, twg, tid);
+  __syncthreads();
+  // last forward stage x K x first inverse stage, in registers
+  {
+    constexpr int TOTAL = XT * (N / R1);
+    constexpr int ITERS = (TOTAL + NT - 1) / NT;
 #pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    const int e = tid + i * NT;
-    if (NE % NT == 0 || e < NE) s[e] = v[i];
+    for (int it = 0; it < ITERS; ++it) {
+      const int b = tid + it * NT;
+      if (TOTAL % NT == 0 || b < TOTAL) {
+        const int f = b % XT;
+        const int blk = b / XT;
+        const int base = f + blk * R1 * XT;
+        const int kx = fl[x0 + f];
+        cpx<T> xv[R1];
+#pragma unroll
+        for (int m = 0; m < R1; ++m) xv[m] = s[base + m * XT];
+        Dft<R1, -1, T>::run(xv);
+#pragma unroll
+        for (int k = 0; k < R1; ++k) xv[k] = cscale(xv[k], kl[fl[blk * R1 + k] * H + kx]);
+        Dft<R1, 1, T>::run(xv);
+#pragma unroll
+        for (int m = 0; m < R1; ++m) s[base + m * XT] = xv[m];
+      }
+    }
   }
   __syncthreads();
-  auto kf = [=](int pos, int f) __attribute__((always_inline)) { return kl[fl[pos] * H + fl[x0 + f]]; };
-  ct_conv<T, N, XT, XT, 1, NT>(s, tw, kf, tid);
-#pragma unroll
-  for (int i = 0; i < EPT; ++i) {
-    const int e = tid + i * NT;
-    if (NE % NT == 0 || e < NE) vol[((size_t)(e / XT) * N + y) * N + x0 + e % XT] = s[e];
-  }
+  // last inverse stage straight back to the work volume
+  ct_stage_io<R0, false, T, N, N, XT, XT, 1, NT, false, true, N * N, 1>(s, nullptr, g0, tw, tid);
 }
 
 // ---- pass C: inverse FFT y and x, times psi_j, j-sum in registers --------------
-template <typename T, typename A, int N, bool PIPE>
+template <typename T, typename A, int N>
 __global__ void __launch_bounds__(CubeShape<N>::NT_P) k_pass_c_ct(const cpx<T>* __restrict__ psi, int64_t ld_psi,
                                                                   const cpx<T>* __restrict__ work, int j0, int nj,
                                                                   int k0, int nitems, cpx<A>* acc, int64_t ld_acc,
@@ -129,34 +142,24 @@ __global__ void __launch_bounds__(CubeShape<N>::NT_P) k_pass_c_ct(const cpx<T>* 
   cpx<T>* tw = s + N * SX;
   const int tid = threadIdx.x;
   for (int i = tid; i < N; i += NT) tw[i] = twg[i];
+  __syncthreads();
   for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
     const int z = item % N;
     const int kk = item / N;
     const int k = k0 + kk;
     cpx<A> a[EPT];
-    cpx<T> vt[EPT], vp[EPT];
+    cpx<T> vp[EPT];
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
       const int e = tid + i * NT;
       a[i] = cpx<A>{0, 0};
       if (!first && (NXY % NT == 0 || e < NXY)) a[i] = acc[k * ld_acc + (size_t)z * NXY + e];
     }
-    auto tload = [&](int jj) __attribute__((always_inline)) {
-      const cpx<T>* tp = work + ((size_t)kk * nj + jj) * NR + (size_t)z * NXY;
-#pragma unroll
-      for (int i = 0; i < EPT; ++i) {
-        const int e = tid + i * NT;
-        if (NXY % NT == 0 || e < NXY) vt[i] = tp[e];
-      }
-    };
-    if (PIPE) tload(0);
+    constexpr int R0 = Plan2<N>::R0, R1 = Plan2<N>::R1;
     for (int jj = 0; jj < nj; ++jj) {
-      if (!PIPE) tload(jj);
-#pragma unroll
-      for (int i = 0; i < EPT; ++i) {
-        const int e = tid + i * NT;
-        if (NXY % NT == 0 || e < NXY) s[(e / N) * SX + e % N] = vt[i];
-      }
+      // first inverse y stage straight from the work plane
+      const cpx<T>* tp = work + ((size_t)kk * nj + jj) * NR + (size_t)z * NXY;
+      ct_stage_io<R1, false, T, N, R1, N, SX, 1, NT, true, false, N, 1>(s, tp, nullptr, tw, tid);
       __syncthreads();
       const cpx<T>* pj = psi + (int64_t)(j0 + jj) * ld_psi + (size_t)z * NXY;
 #pragma unroll
@@ -164,8 +167,8 @@ __global__ void __launch_bounds__(CubeShape<N>::NT_P) k_pass_c_ct(const cpx<T>* 
         const int e = tid + i * NT;
         if (NXY % NT == 0 || e < NXY) vp[i] = pj[e];
       }
-      if (PIPE && jj + 1 < nj) tload(jj + 1);
-      ct_fft<false, T, N, N, SX, 1, NT>(s, tw, tid);
+      ct_stage<R0, false, T, N, N, N, SX, 1, NT>(s, tw, tid);
+      __syncthreads();
       ct_fft<false, T, N, N, 1, SX, NT>(s, tw, tid);
 #pragma unroll
       for (int i = 0; i < EPT; ++i) {
@@ -212,9 +215,7 @@ bool ct_supported(const fx_cell* cell) {
 
 template <typename K>
 static fx_status ct_prepare(fx_ctx* ctx, K kernel, int nthr, size_t lds, int items, bool persistent, int* grid) {
-  if (lds > 65536)
-    FX_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)lds));
+  FX_TRY(allow_dynamic_lds(reinterpret_cast<const void*>(kernel), lds));
   if (!persistent) {
     *grid = items;
     return FX_OK;
@@ -258,8 +259,7 @@ static fx_status pass_c_n(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b, cons
   const size_t lds = ((size_t)N * (N + 1) + N) * sizeof(cpx<T>);
   const int items = b.nk * N;
   // prefetching the next plane: FP32 planes below 96^2 have the registers
-  const bool pipe = c.pipe >= 0 ? (c.pipe != 0 && sizeof(T) == 4) : (sizeof(T) == 4 && N < 96);
-  auto kern = pipe ? k_pass_c_ct<T, A, N, sizeof(T) == 4> : k_pass_c_ct<T, A, N, false>;
+  auto kern = k_pass_c_ct<T, A, N>;
   int grid = 0;
   FX_TRY(ct_prepare(ctx, kern, NT, lds, items, true, &grid));
   hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, st, b.psi, b.ld_psi, (const cpx<T>*)b.work, b.j0, b.nj, b.k0,
