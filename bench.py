@@ -146,7 +146,7 @@ def main():
     cpath = os.path.join(ROOT, "profiles", "vx_counters.json")
     if os.path.exists(cpath):
         c = json.load(open(cpath))
-        if c.get("source_hash") == kernel_source_hash() and c.get("kernel") == dom and c.get("prec") == args.prec:
+        if c.get("source_hash") == kernel_source_hash() and c.get("name") == dom and c.get("prec") == args.prec:
             traffic = c.get("bytes_per_launch")
     path_bytes = sum(kern[k]["bytes_per_launch"] * kern[k]["launches"] for k in kern) / args.steps
 
@@ -178,6 +178,8 @@ def main():
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
+            # measured DRAM-side bytes (copy-calibrated counters) / launch duration
+            "traffic_GBps": traffic / (kern[dom]["avg_ms"] * 1e-3) / 1e9 if traffic else None,
             "algorithmic_bytes_per_launch": bytes_per_launch,
         },
         "kernels": kern,
@@ -251,11 +253,20 @@ def bench_ace(args):
     psi = torch.from_numpy(synth.make_orbitals(w["seed"], n, L, N, dtype=np.complex64)).to("cuda:0")
     phi = torch.from_numpy(synth.make_orbitals(3, n, L, R, dtype=np.complex64)).to("cuda:0")
     ctx = Context(0)
+    ctx.prof_enable(True)
     t0 = time.perf_counter()
     ace = ctx.build_ace(psi, n=n, L=L, kernel="hse", omega=0.106, vx_prec="fp32acc64", ace_prec="ace_fp64")
     torch.cuda.synchronize()
     t_build = time.perf_counter() - t0
-    log(f"[bench-ace] build {t_build:.2f} s ({N * N} pairs)")
+    build_k = {}
+    for name in ("vx_plane_fwd", "vx_pencil_z", "vx_plane_inv", "convert", "gemm_cn", "gemm_nn", "reduce", "linalg"):
+        cnt, ms, work = ctx.prof_read(fock.KERNEL_IDS[name])
+        if cnt:
+            build_k[name] = {"launches": cnt, "total_ms": ms}
+    ctx.prof_enable(False)
+    # W = V_X Psi with phi = Psi on a workload edge solves each unordered pair once
+    solves = N * (N + 1) // 2
+    log(f"[bench-ace] build {t_build:.2f} s ({N * N} logical pairs, {solves} Poisson solves)")
     out = torch.empty_like(phi)
     res = {}
     ref = None
@@ -303,7 +314,9 @@ def bench_ace(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"ACE apply K_ACE phi = -xi (xi^H phi), 96^3 grid, N = {N}, R = {R}, "
-                               "FP32 matrix cores + FP64-combined residual step", "build_s": t_build},
+                               "FP32 matrix cores + FP64-combined residual step", "build_s": t_build,
+                   "build_pairs_per_s": N * N / t_build, "build_solves_per_s": solves / t_build,
+                   "build_kernels_ms": build_k},
         "roofline": res[main_p][dom + "_roofline"],
         "precisions": res,
     }

@@ -142,6 +142,13 @@ fx_status fx_memory(const fx_ctx* ctx, size_t* in_use, size_t* peak);
  * prec: FX_PREC_FP64, FX_PREC_FP32 or FX_PREC_FP32_ACC64.  The j-sum runs in
  *       ascending j in the accumulation precision, so results are bitwise
  *       repeatable and independent of how the pairs are batched.
+ * When phi == psi with n_phi == n_psi and ld_phi == ld_psi on a cubic grid of
+ *       edge 24, 48, 72 or 96, each unordered pair is solved once (the kernel
+ *       is real and even, so the (k,j) solve is the conjugate of the (j,k)
+ *       one): N(N+1)/2 solves instead of N^2.  Term j of column k is then taken
+ *       from the solve of (min(j,k), max(j,k)); the result is still bitwise
+ *       repeatable and batch-independent, and equals the full form up to
+ *       rounding.
  * ex_energy_dev: optional device double receiving E_X = 1/2 Re sum_k
  *       <psi_k, out_k>; only allowed when phi == psi and ld_phi == ld_psi.
  * Errors: FX_ERR_INVALID, FX_ERR_UNSUPPORTED, FX_ERR_OOM, FX_ERR_DEVICE.

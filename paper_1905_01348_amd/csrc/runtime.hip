@@ -45,6 +45,11 @@ fx_status ctx_alloc(fx_ctx* ctx, size_t bytes, void** out) {
   const char* fi = getenv("FX_FAULT_INJECT");
   long n = __atomic_add_fetch(&g_alloc_count, 1, __ATOMIC_SEQ_CST);
   if (fi && atol(fi) == n) FX_FAIL(FX_ERR_OOM, "injected allocation failure (FX_FAULT_INJECT=%s)", fi);
+  if (ctx->capturing)
+    FX_FAIL(FX_ERR_INVALID,
+            "%zu bytes must be allocated while the stream is being captured; run the same call once outside "
+            "capture first",
+            bytes);
   if (ctx->in_use + bytes > ctx->budget)
     FX_FAIL(FX_ERR_OOM, "HBM budget exceeded: %zu in use + %zu requested > %zu budget", ctx->in_use, bytes,
             ctx->budget);

@@ -3,6 +3,7 @@
 // band-index share).  Pairs are processed in batches of nk targets x nj
 // orbitals; every batch runs the three passes of vx_passes.hpp.
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
 #include <set>
 
@@ -354,6 +355,93 @@ static bool pick_ept(int elems, int max_thr, int* ept, int* nthr) {
     default: FX_FAIL(FX_ERR_UNSUPPORTED, "no kernel for %d elements per thread", EPT_VAR); \
   }
 
+// Halved apply for phi == psi (all N targets): each unordered pair {j, k} is
+// solved once, as (min, max), since v_kj = conj(v_jk) for a real, even kernel.
+// Orbitals are cut into blocks of B; block pairs (J <= K) run in ascending
+// order of J, then K.  For each, pass C runs twice: role 0 adds the pairs to
+// the targets of block K, role 1 (conjugated) to those of block J.  Every
+// output column then receives its terms in ascending j, each term computed
+// from the ordered pair (min(j,k), max(j,k)), so the result does not depend
+// on B.  Diagonal block pairs hold only the B(B+1)/2 pairs j <= k.
+template <typename T, typename A>
+static fx_status run_halved(fx_ctx* ctx, Workspace* ws, const VxArgs& a, const GridTables* tb, const cpx<T>* psi,
+                            int64_t ld_psi, int64_t pairs_cap, hipStream_t st, VxStats* stats) {
+  const int n = a.cell->n[0];
+  const int64_t nr = (int64_t)n * n * n;
+  const size_t pair_bytes = (size_t)nr * sizeof(cpx<T>);
+  const int N = a.n_psi;
+  int B = (int)std::min<int64_t>(N, std::max<int64_t>(1, (int64_t)std::sqrt((double)pairs_cap)));
+  if (a.force_nj > 0) B = std::min(B, a.force_nj);
+  const int nblk = (N + B - 1) / B;
+  B = (N + nblk - 1) / nblk;
+  void* work = nullptr;
+  FX_TRY(ws_get(ctx, ws, "vx_work", (size_t)B * B * pair_bytes, &work));
+  const bool out_c64 = a.out_dtype == FX_C64;
+  const bool out_is_A = (sizeof(A) == 8) == !out_c64;
+  // partial sums live between the two roles of every block pair
+  cpx<A>* acc = nullptr;
+  int64_t ld_acc = 0;
+  if (out_is_A) {
+    acc = reinterpret_cast<cpx<A>*>(a.out);
+    ld_acc = a.ld_out;
+  } else {
+    void* p = nullptr;
+    FX_TRY(ws_get(ctx, ws, "vx_acc", (size_t)N * nr * sizeof(cpx<A>), &p));
+    acc = reinterpret_cast<cpx<A>*>(p);
+    ld_acc = nr;
+  }
+  const cpx<T>* tw = reinterpret_cast<const cpx<T>*>(tb->tw[0]);
+  const T* kf = reinterpret_cast<const T*>(tb->kfold);
+  const double sz = sizeof(cpx<T>), asz = sizeof(cpx<A>), osz = out_c64 ? 8.0 : 16.0;
+  int64_t launches = 0, solves = 0;
+  for (int J = 0; J < nblk; ++J) {
+    const int j0 = J * B, jb = std::min(B, N - j0);
+    for (int K = J; K < nblk; ++K) {
+      const int k0 = K * B, kb = std::min(B, N - k0);
+      const int tri = J == K;
+      const int npairs = tri ? jb * (jb + 1) / 2 : jb * kb;
+      CtBatch<T> cb{psi, ld_psi, psi, ld_psi, reinterpret_cast<cpx<T>*>(work), j0, jb, k0, kb, npairs, tw, kf,
+                    tb->fold[0], tri};
+      const double vol = (double)npairs * nr * sz;
+      int slot;
+      FX_TRY(prof_begin(ctx, st, FX_K_VX_PLANE_FWD, 3.0 * vol, &slot));
+      FX_TRY(ct_pass_a<T>(ctx, st, n, cb));
+      FX_TRY(prof_end(ctx, st, slot));
+      FX_TRY(prof_begin(ctx, st, FX_K_VX_PENCIL_Z, 2.0 * vol, &slot));
+      FX_TRY(ct_pass_b<T>(ctx, st, n, cb));
+      FX_TRY(prof_end(ctx, st, slot));
+      // role 0: targets of block K; the first contribution to them is J = 0
+      {
+        const int first = J == 0;
+        CtAcc<A> ca{acc, ld_acc, first, a.out, a.ld_out, out_c64 ? 1 : 0, 0, -1};
+        const double accb = (double)kb * nr * ((first ? 0.0 : asz) + asz);
+        FX_TRY(prof_begin(ctx, st, FX_K_VX_PLANE_INV, 2.0 * vol + accb, &slot));
+        FX_TRY((ct_pass_c<T, A>(ctx, st, n, cb, ca, 0)));
+        FX_TRY(prof_end(ctx, st, slot));
+      }
+      // role 1: targets of block J; their last contribution is K = nblk - 1
+      {
+        const int last = K == nblk - 1;
+        CtAcc<A> ca{acc, ld_acc, 0, a.out, a.ld_out, out_c64 ? 1 : 0, last, -1};
+        const double planes = tri ? (double)(npairs - jb) : (double)npairs;
+        const double accb = (double)jb * nr * (asz + (last ? osz : asz));
+        FX_TRY(prof_begin(ctx, st, FX_K_VX_PLANE_INV, 2.0 * planes * nr * sz + accb, &slot));
+        FX_TRY((ct_pass_c<T, A>(ctx, st, n, cb, ca, 1)));
+        FX_TRY(prof_end(ctx, st, slot));
+      }
+      launches += 4;
+      solves += npairs;
+    }
+  }
+  if (stats) {
+    stats->nk = B;
+    stats->nj = B;
+    stats->launches = launches;
+    stats->solves = solves;
+  }
+  return FX_OK;
+}
+
 template <typename T, typename A>
 static fx_status run_batches(fx_ctx* ctx, Workspace* ws, const VxArgs& a, const GridTables* tb,
                              const cpx<T>* psi, int64_t ld_psi, const cpx<T>* phi, int64_t ld_phi, hipStream_t st,
@@ -364,6 +452,10 @@ static fx_status run_batches(fx_ctx* ctx, Workspace* ws, const VxArgs& a, const 
   const size_t pair_bytes = (size_t)nr * sizeof(cpx<T>);
   size_t cap = a.work_cap ? a.work_cap : work_cap_bytes(ctx);
   const int64_t pairs_cap = (int64_t)std::max<size_t>(1, cap / pair_bytes);
+  // cubic grids of the workload edges run the compile-time-specialised kernels
+  const bool use_ct = ct_supported(a.cell);
+  if (use_ct && a.halve != 0 && psi == phi && ld_psi == ld_phi && a.n_psi == a.n_phi)
+    return run_halved<T, A>(ctx, ws, a, tb, psi, ld_psi, pairs_cap, st, stats);
   // Batch shape: up to 16 orbitals per batch first (the plane-inverse pass
   // reads and writes its partial sums once per batch), then as many targets
   // as fit, balanced over the target blocks, then any leftover capacity
@@ -411,8 +503,6 @@ static fx_status run_batches(fx_ctx* ctx, Workspace* ws, const VxArgs& a, const 
   const size_t lds_b = ((size_t)g.nz * xt + g.nz) * sizeof(cpx<T>) + (size_t)g.hz * g.hx * sizeof(T) +
                        (size_t)(g.nx + g.nz) * sizeof(int);
 
-  // cubic grids of the workload edges run the compile-time-specialised kernels
-  const bool use_ct = ct_supported(a.cell);
   int64_t launches = 0;
   for (int k0 = 0; k0 < a.n_phi; k0 += nk) {
     const int kb = std::min(nk, a.n_phi - k0);
@@ -428,7 +518,7 @@ static fx_status run_batches(fx_ctx* ctx, Workspace* ws, const VxArgs& a, const 
       int slot;
       if (use_ct) {
         CtBatch<T> cb{psi, ld_psi, phi, ld_phi, reinterpret_cast<cpx<T>*>(work), j0, jb, k0, kb, npairs, twx, kf,
-                      tb->fold[0]};
+                      tb->fold[0], 0};
         CtAcc<A> ca{acc, ld_acc, first, a.out, a.ld_out, out_c64 ? 1 : 0, last, a.pipe};
         FX_TRY(prof_begin(ctx, st, FX_K_VX_PLANE_FWD, 3.0 * vol, &slot));
         FX_TRY(ct_pass_a<T>(ctx, st, g.nx, cb));
@@ -437,7 +527,7 @@ static fx_status run_batches(fx_ctx* ctx, Workspace* ws, const VxArgs& a, const 
         FX_TRY(ct_pass_b<T>(ctx, st, g.nx, cb));
         FX_TRY(prof_end(ctx, st, slot));
         FX_TRY(prof_begin(ctx, st, FX_K_VX_PLANE_INV, 2.0 * vol + accb, &slot));
-        FX_TRY((ct_pass_c<T, A>(ctx, st, g.nx, cb, ca)));
+        FX_TRY((ct_pass_c<T, A>(ctx, st, g.nx, cb, ca, 0)));
         FX_TRY(prof_end(ctx, st, slot));
         launches += 3;
         continue;
@@ -484,6 +574,7 @@ static fx_status run_batches(fx_ctx* ctx, Workspace* ws, const VxArgs& a, const 
     stats->nk = nk;
     stats->nj = nj;
     stats->launches = launches;
+    stats->solves = (int64_t)a.n_psi * a.n_phi;
   }
   return FX_OK;
 }
@@ -677,6 +768,7 @@ fx_status fx_apply_vx(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* kernel,
   if (const char* e = getenv("FX_VX_XT")) a.xtile = atoi(e);
   if (const char* e = getenv("FX_VX_PIPE")) a.pipe = atoi(e);
   if (const char* e = getenv("FX_VX_NTHR_B")) a.nthr_b = atoi(e);
+  if (const char* e = getenv("FX_VX_HALVE")) a.halve = atoi(e);
   hipStream_t st = (hipStream_t)stream;
   FX_TRY(note_capture(ctx, st));
   return vx_apply(ctx, &ctx->ws, a, st, nullptr);

@@ -27,11 +27,13 @@ struct VxArgs {
   int nthr_b = 0;  // threads of the pencil pass
   int xtile = 0;   // x columns per pencil-pass workgroup
   int pipe = -1;   // plane-inverse pass prefetches the next plane: 1 yes, 0 no, -1 automatic
+  int halve = -1;  // phi == psi: solve each unordered pair once (1 yes, 0 no, -1 automatic)
 };
 
 struct VxStats {
   int nk = 0, nj = 0;
   int64_t launches = 0;
+  int64_t solves = 0;  // pair Poisson solves run (N*N_t, or N(N+1)/2 when halved)
 };
 
 // One batch of the pair passes for the compile-time-specialised kernels
@@ -47,6 +49,7 @@ struct CtBatch {
   const cpx<T>* tw;  // twiddles of the edge (all three axes share them)
   const T* kfold;
   const int* fold;  // folded frequency per digit-reversed position
+  int tri;          // diagonal batch of a halved apply: pairs jj <= kk only, packed
 };
 template <typename A>
 struct CtAcc {
@@ -62,8 +65,9 @@ template <typename T>
 fx_status ct_pass_a(fx_ctx* ctx, hipStream_t st, int n, const CtBatch<T>& b);
 template <typename T>
 fx_status ct_pass_b(fx_ctx* ctx, hipStream_t st, int n, const CtBatch<T>& b);
+// role 0: targets are the batch's k; role 1: targets are its j (halved apply)
 template <typename T, typename A>
-fx_status ct_pass_c(fx_ctx* ctx, hipStream_t st, int n, const CtBatch<T>& b, const CtAcc<A>& c);
+fx_status ct_pass_c(fx_ctx* ctx, hipStream_t st, int n, const CtBatch<T>& b, const CtAcc<A>& c, int role);
 
 fx_status check_vx_args(const VxArgs& a);
 // Copy ncols columns of nr complex values between dtypes (strided).

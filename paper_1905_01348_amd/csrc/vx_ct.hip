@@ -2,6 +2,7 @@
 // workloads (edges 24, 48, 72, 96).  Same three passes and data layout as the
 // generic kernels in vx.hip (see vx_passes.hpp); every shape is a constant.
 #include <algorithm>
+#include <cstdlib>
 
 #include "fft_ct.hpp"
 #include "vx.hpp"
@@ -14,12 +15,39 @@ struct CeilDiv {
   static constexpr int value = (A + B - 1) / B;
 };
 
+// Pair (jj, kk) of work plane p of a batch.  A rectangular batch stores its
+// pairs target-major (p = kk*nj + jj); a diagonal batch of a halved apply
+// (tri != 0, the same orbitals on both sides) stores only jj <= kk, packed
+// as p = kk*(kk+1)/2 + jj.
+FX_HD void pair_of(int p, int nj, int tri, int* jj, int* kk) {
+  if (!tri) {
+    *kk = p / nj;
+    *jj = p - *kk * nj;
+    return;
+  }
+  int k = (int)((sqrtf(8.0f * (float)p + 1.0f) - 1.0f) * 0.5f);
+  while (k > 0 && k * (k + 1) / 2 > p) --k;
+  while ((k + 1) * (k + 2) / 2 <= p) ++k;
+  *kk = k;
+  *jj = p - k * (k + 1) / 2;
+}
+
+FX_HD int plane_of(int jj, int kk, int nj, int tri) { return tri ? kk * (kk + 1) / 2 + jj : kk * nj + jj; }
+
 // ---- pass A: pair product, forward FFT x and y (persistent, pipelined) ------
-template <typename T, int N>
-__global__ void __launch_bounds__(CubeShape<N>::NT_P) k_pass_a_ct(const cpx<T>* __restrict__ psi, int64_t ld_psi,
+// PIPE: the next plane's loads are issued into registers before the current
+// plane is transformed (one workgroup per CU at 96^2); without it the kernel
+// is held to 128 VGPRs so that two workgroups share a CU instead.
+template <typename T, bool PIPE>
+struct PassAWaves {
+  static constexpr int value = (sizeof(T) == 4 && !PIPE) ? 4 : 1;
+};
+
+template <typename T, int N, bool PIPE>
+__global__ void __launch_bounds__(CubeShape<N>::NT_P, (PassAWaves<T, PIPE>::value)) k_pass_a_ct(const cpx<T>* __restrict__ psi, int64_t ld_psi,
                                                                   const cpx<T>* __restrict__ phi, int64_t ld_phi,
                                                                   cpx<T>* __restrict__ work, int j0, int nj, int k0,
-                                                                  int nitems, const cpx<T>* __restrict__ twg) {
+                                                                  int tri, int nitems, const cpx<T>* __restrict__ twg) {
   constexpr int NT = CubeShape<N>::NT_P, NXY = N * N, SX = N + 1, EPT = CeilDiv<NXY, NT>::value;
   constexpr size_t NR = (size_t)NXY * N;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -31,8 +59,10 @@ __global__ void __launch_bounds__(CubeShape<N>::NT_P) k_pass_a_ct(const cpx<T>* 
   auto fetch = [&](int it) __attribute__((always_inline)) {
     if (it >= nitems) return;
     const int z = it % N, p = it / N;
-    const cpx<T>* a = psi + (int64_t)(j0 + p % nj) * ld_psi + (size_t)z * NXY;
-    const cpx<T>* b = phi + (int64_t)(k0 + p / nj) * ld_phi + (size_t)z * NXY;
+    int jj, kk;
+    pair_of(p, nj, tri, &jj, &kk);
+    const cpx<T>* a = psi + (int64_t)(j0 + jj) * ld_psi + (size_t)z * NXY;
+    const cpx<T>* b = phi + (int64_t)(k0 + kk) * ld_phi + (size_t)z * NXY;
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
       const int e = tid + i * NT;
@@ -42,7 +72,7 @@ __global__ void __launch_bounds__(CubeShape<N>::NT_P) k_pass_a_ct(const cpx<T>* 
       }
     }
   };
-  constexpr bool kPipe = sizeof(T) == 4;
+  constexpr bool kPipe = PIPE;
   int item = blockIdx.x;
   if (kPipe) fetch(item);
   for (; item < nitems; item += gridDim.x) {
@@ -129,12 +159,19 @@ __global__ void __launch_bounds__(CubeShape<N>::NT_B) k_pass_b_ct(cpx<T>* __rest
 }
 
 // ---- pass C: inverse FFT y and x, times psi_j, j-sum in registers --------------
-template <typename T, typename A, int N>
-__global__ void __launch_bounds__(CubeShape<N>::NT_P) k_pass_c_ct(const cpx<T>* __restrict__ psi, int64_t ld_psi,
-                                                                  const cpx<T>* __restrict__ work, int j0, int nj,
-                                                                  int k0, int nitems, cpx<A>* acc, int64_t ld_acc,
-                                                                  int first, void* out, int64_t ld_out, int out_c64,
-                                                                  int last, const cpx<T>* __restrict__ twg) {
+// One item = (target tt of the batch, plane z).  Role 0 (CONJ false): the
+// targets are the batch's k (output column t0 + kk) and the sum runs over its
+// j in ascending order, adding psi_{m0+jj} * v_{jk}.  Role 1 (CONJ true, the
+// second half of a halved apply): the targets are the batch's j and the sum
+// runs over its k in ascending order, adding psi_{m0+kk} * conj(v_{jk}),
+// which is v_{kj} since the kernel is real and even.  On a diagonal batch
+// (tri) role 0 takes jj <= kk and role 1 kk > jj.
+template <typename T, typename A, int N, bool CONJ>
+__global__ void __launch_bounds__(CubeShape<N>::NT_P) k_pass_c_ct(const cpx<T>* __restrict__ mult, int64_t ld_mult,
+                                                                  const cpx<T>* __restrict__ work, int nj, int nk,
+                                                                  int tri, int m0, int t0, int nitems, cpx<A>* acc,
+                                                                  int64_t ld_acc, int first, void* out, int64_t ld_out,
+                                                                  int out_c64, int last, const cpx<T>* __restrict__ twg) {
   constexpr int NT = CubeShape<N>::NT_P, NXY = N * N, SX = N + 1, EPT = CeilDiv<NXY, NT>::value;
   constexpr size_t NR = (size_t)NXY * N;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -145,27 +182,30 @@ __global__ void __launch_bounds__(CubeShape<N>::NT_P) k_pass_c_ct(const cpx<T>* 
   __syncthreads();
   for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
     const int z = item % N;
-    const int kk = item / N;
-    const int k = k0 + kk;
+    const int tt = item / N;
+    const int t = t0 + tt;
     cpx<A> a[EPT];
     cpx<T> vp[EPT];
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
       const int e = tid + i * NT;
       a[i] = cpx<A>{0, 0};
-      if (!first && (NXY % NT == 0 || e < NXY)) a[i] = acc[k * ld_acc + (size_t)z * NXY + e];
+      if (!first && (NXY % NT == 0 || e < NXY)) a[i] = acc[t * ld_acc + (size_t)z * NXY + e];
     }
     constexpr int R0 = Plan2<N>::R0, R1 = Plan2<N>::R1;
-    for (int jj = 0; jj < nj; ++jj) {
+    const int lo = CONJ ? (tri ? tt + 1 : 0) : 0;
+    const int hi = CONJ ? nk : (tri ? tt + 1 : nj);
+    for (int l = lo; l < hi; ++l) {
+      const int pl = CONJ ? plane_of(tt, l, nj, tri) : plane_of(l, tt, nj, tri);
       // first inverse y stage straight from the work plane
-      const cpx<T>* tp = work + ((size_t)kk * nj + jj) * NR + (size_t)z * NXY;
+      const cpx<T>* tp = work + (size_t)pl * NR + (size_t)z * NXY;
       ct_stage_io<R1, false, T, N, R1, N, SX, 1, NT, true, false, N, 1>(s, tp, nullptr, tw, tid);
       __syncthreads();
-      const cpx<T>* pj = psi + (int64_t)(j0 + jj) * ld_psi + (size_t)z * NXY;
+      const cpx<T>* pm = mult + (int64_t)(m0 + l) * ld_mult + (size_t)z * NXY;
 #pragma unroll
       for (int i = 0; i < EPT; ++i) {
         const int e = tid + i * NT;
-        if (NXY % NT == 0 || e < NXY) vp[i] = pj[e];
+        if (NXY % NT == 0 || e < NXY) vp[i] = pm[e];
       }
       ct_stage<R0, false, T, N, N, N, SX, 1, NT>(s, tw, tid);
       __syncthreads();
@@ -175,7 +215,8 @@ __global__ void __launch_bounds__(CubeShape<N>::NT_P) k_pass_c_ct(const cpx<T>* 
         const int e = tid + i * NT;
         if (NXY % NT == 0 || e < NXY) {
           const cpx<T> v = s[(e / N) * SX + e % N];
-          a[i] = cadd(a[i], cmul(cpx<A>{(A)vp[i].x, (A)vp[i].y}, cpx<A>{(A)v.x, (A)v.y}));
+          const cpx<A> va{(A)v.x, CONJ ? -(A)v.y : (A)v.y};
+          a[i] = cadd(a[i], cmul(cpx<A>{(A)vp[i].x, (A)vp[i].y}, va));
         }
       }
       __syncthreads();
@@ -187,11 +228,11 @@ __global__ void __launch_bounds__(CubeShape<N>::NT_P) k_pass_c_ct(const cpx<T>* 
       const size_t off = (size_t)z * NXY + e;
       if (last) {
         if (out_c64)
-          reinterpret_cast<cpx<float>*>(out)[k * ld_out + off] = cpx<float>{(float)a[i].x, (float)a[i].y};
+          reinterpret_cast<cpx<float>*>(out)[t * ld_out + off] = cpx<float>{(float)a[i].x, (float)a[i].y};
         else
-          reinterpret_cast<cpx<double>*>(out)[k * ld_out + off] = cpx<double>{(double)a[i].x, (double)a[i].y};
+          reinterpret_cast<cpx<double>*>(out)[t * ld_out + off] = cpx<double>{(double)a[i].x, (double)a[i].y};
       } else {
-        acc[k * ld_acc + off] = a[i];
+        acc[t * ld_acc + off] = a[i];
       }
     }
   }
@@ -230,12 +271,14 @@ template <typename T, int N>
 static fx_status pass_a_n(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b) {
   constexpr int NT = CubeShape<N>::NT_P;
   const size_t lds = ((size_t)N * (N + 1) + N) * sizeof(cpx<T>);
-  auto kern = k_pass_a_ct<T, N>;
+  bool pipe = sizeof(T) == 4;
+  if (const char* e = getenv("FX_VX_A_PIPE")) pipe = pipe && atoi(e) != 0;
+  auto kern = pipe ? k_pass_a_ct<T, N, sizeof(T) == 4> : k_pass_a_ct<T, N, false>;
   const int items = b.npairs * N;
   int grid = 0;
   FX_TRY(ct_prepare(ctx, kern, NT, lds, items, true, &grid));
   hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, st, b.psi, b.ld_psi, b.phi, b.ld_phi, b.work, b.j0, b.nj, b.k0,
-                     items, b.tw);
+                     b.tri, items, b.tw);
   FX_LAUNCH_CHECK();
   return FX_OK;
 }
@@ -254,16 +297,19 @@ static fx_status pass_b_n(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b) {
 }
 
 template <typename T, typename A, int N>
-static fx_status pass_c_n(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b, const CtAcc<A>& c) {
+static fx_status pass_c_n(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b, const CtAcc<A>& c, int role) {
   constexpr int NT = CubeShape<N>::NT_P;
   const size_t lds = ((size_t)N * (N + 1) + N) * sizeof(cpx<T>);
-  const int items = b.nk * N;
-  // prefetching the next plane: FP32 planes below 96^2 have the registers
-  auto kern = k_pass_c_ct<T, A, N>;
+  const int items = (role ? b.nj : b.nk) * N;
+  auto kern = role ? k_pass_c_ct<T, A, N, true> : k_pass_c_ct<T, A, N, false>;
   int grid = 0;
   FX_TRY(ct_prepare(ctx, kern, NT, lds, items, true, &grid));
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, st, b.psi, b.ld_psi, (const cpx<T>*)b.work, b.j0, b.nj, b.k0,
-                     items, c.acc, c.ld_acc, c.first, c.out, c.ld_out, c.out_c64, c.last, b.tw);
+  if (role)
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, st, b.phi, b.ld_phi, (const cpx<T>*)b.work, b.nj, b.nk, b.tri,
+                       b.k0, b.j0, items, c.acc, c.ld_acc, c.first, c.out, c.ld_out, c.out_c64, c.last, b.tw);
+  else
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, st, b.psi, b.ld_psi, (const cpx<T>*)b.work, b.nj, b.nk, b.tri,
+                       b.j0, b.k0, items, c.acc, c.ld_acc, c.first, c.out, c.ld_out, c.out_c64, c.last, b.tw);
   FX_LAUNCH_CHECK();
   return FX_OK;
 }
@@ -291,12 +337,12 @@ fx_status ct_pass_b(fx_ctx* ctx, hipStream_t st, int n, const CtBatch<T>& b) {
 }
 
 template <typename T, typename A>
-fx_status ct_pass_c(fx_ctx* ctx, hipStream_t st, int n, const CtBatch<T>& b, const CtAcc<A>& c) {
+fx_status ct_pass_c(fx_ctx* ctx, hipStream_t st, int n, const CtBatch<T>& b, const CtAcc<A>& c, int role) {
   switch (n) {
-    case 24: return pass_c_n<T, A, 24>(ctx, st, b, c);
-    case 48: return pass_c_n<T, A, 48>(ctx, st, b, c);
-    case 72: return pass_c_n<T, A, 72>(ctx, st, b, c);
-    case 96: return pass_c_n<T, A, 96>(ctx, st, b, c);
+    case 24: return pass_c_n<T, A, 24>(ctx, st, b, c, role);
+    case 48: return pass_c_n<T, A, 48>(ctx, st, b, c, role);
+    case 72: return pass_c_n<T, A, 72>(ctx, st, b, c, role);
+    case 96: return pass_c_n<T, A, 96>(ctx, st, b, c, role);
     default: FX_FAIL(FX_ERR_UNSUPPORTED, "no specialised kernels for edge %d", n);
   }
 }
@@ -305,8 +351,10 @@ template fx_status ct_pass_a<float>(fx_ctx*, hipStream_t, int, const CtBatch<flo
 template fx_status ct_pass_a<double>(fx_ctx*, hipStream_t, int, const CtBatch<double>&);
 template fx_status ct_pass_b<float>(fx_ctx*, hipStream_t, int, const CtBatch<float>&);
 template fx_status ct_pass_b<double>(fx_ctx*, hipStream_t, int, const CtBatch<double>&);
-template fx_status ct_pass_c<float, double>(fx_ctx*, hipStream_t, int, const CtBatch<float>&, const CtAcc<double>&);
-template fx_status ct_pass_c<float, float>(fx_ctx*, hipStream_t, int, const CtBatch<float>&, const CtAcc<float>&);
-template fx_status ct_pass_c<double, double>(fx_ctx*, hipStream_t, int, const CtBatch<double>&, const CtAcc<double>&);
+template fx_status ct_pass_c<float, double>(fx_ctx*, hipStream_t, int, const CtBatch<float>&, const CtAcc<double>&,
+                                            int);
+template fx_status ct_pass_c<float, float>(fx_ctx*, hipStream_t, int, const CtBatch<float>&, const CtAcc<float>&, int);
+template fx_status ct_pass_c<double, double>(fx_ctx*, hipStream_t, int, const CtBatch<double>&, const CtAcc<double>&,
+                                             int);
 
 }  // namespace fx

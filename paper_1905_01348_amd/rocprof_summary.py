@@ -3,9 +3,13 @@
     python -m paper_1905_01348_amd.rocprof_summary stats <kernel_stats.csv> [--title T] [--command C]
         -> a Markdown table of per-kernel calls and durations.
 
+    python -m paper_1905_01348_amd.rocprof_summary traffic --fetch <dir> --write <dir>
+           --copy-fetch <dir> --copy-write <dir> --kernels a,b,c [--durations <kernel_stats.csv>]
+        -> a Markdown table of calibrated DRAM bytes per dispatch for several kernels.
+
     python -m paper_1905_01348_amd.rocprof_summary counters --fetch <dir> --write <dir>
            --copy-fetch <dir> --copy-write <dir> --kernel <substring> --prec <p> --source-hash <h>
-           [--out profiles/vx_counters.json] [--command C]
+           [--name <library kernel id>] [--out profiles/vx_counters.json] [--command C]
         -> HBM traffic per launch of one kernel from FETCH_SIZE and WRITE_SIZE
            (KiB per dispatch), each scaled by the factor that makes a plain
            1 GiB device copy read and write exactly 1 GiB.
@@ -72,7 +76,7 @@ def _per_dispatch(rows):
     return acc
 
 
-def counters(fetch, write, copy_fetch, copy_write, kernel, prec, source_hash, command=None):
+def counters(fetch, write, copy_fetch, copy_write, kernel, prec, source_hash, command=None, name=None):
     one_gib_kib = float(1 << 20)
     # calibration: the largest dispatch of the copy run is the 1 GiB copy
     cf = max(_per_dispatch(_counter_rows(copy_fetch, "FETCH_SIZE")).values())
@@ -85,12 +89,50 @@ def counters(fetch, write, copy_fetch, copy_write, kernel, prec, source_hash, co
     fetch_b = sum(f) / len(f) * 1024 * sf
     write_b = sum(w) / len(w) * 1024 * sw
     return {
-        "kernel": kernel, "prec": prec, "source_hash": source_hash,
+        "kernel": kernel, "name": name, "prec": prec, "source_hash": source_hash,
         "fetch_bytes_per_launch": fetch_b, "write_bytes_per_launch": write_b,
         "bytes_per_launch": fetch_b + write_b,
         "copy_scale_fetch": sf, "copy_scale_write": sw, "launches": [len(f), len(w)],
         "command": command,
     }
+
+
+def traffic_table(fetch, write, copy_fetch, copy_write, kernels, title=None, command=None, durations=None):
+    """Markdown table: calibrated DRAM read/write bytes per dispatch for each kernel
+    whose name contains one of `kernels`; with `durations` (kernel_stats.csv of a
+    kernel-trace run of the same command) also the measured rate."""
+    one_gib_kib = float(1 << 20)
+    cf = max(_per_dispatch(_counter_rows(copy_fetch, "FETCH_SIZE")).values())
+    cw = max(_per_dispatch(_counter_rows(copy_write, "WRITE_SIZE")).values())
+    sf, sw = one_gib_kib / cf, one_gib_kib / cw
+    fr = _per_dispatch(_counter_rows(fetch, "FETCH_SIZE"))
+    wr = _per_dispatch(_counter_rows(write, "WRITE_SIZE"))
+    avg_ms = {}
+    if durations:
+        for r in csv.DictReader(open(durations)):
+            avg_ms[r.get("Name", r.get("KernelName", ""))] = float(r.get("AverageNs", 0)) / 1e6
+    out = []
+    if title:
+        out.append(f"# {title}\n")
+    if command:
+        out.append(f"Commands:\n\n```\n{command}\n```\n")
+    out.append(f"Calibration: a 1 GiB device copy reads {cf / one_gib_kib:.4f} GiB by FETCH_SIZE and writes "
+               f"{cw / one_gib_kib:.4f} GiB by WRITE_SIZE; counts below are scaled by {sf:.4f} and {sw:.4f}.\n")
+    out.append("| kernel | dispatches | read GB / dispatch | write GB / dispatch | total GB | avg ms | DRAM GB/s |")
+    out.append("|---|---|---|---|---|---|---|")
+    for k in kernels:
+        f = [v for (d, n), v in fr.items() if k in n]
+        w = [v for (d, n), v in wr.items() if k in n]
+        if not f or not w:
+            continue
+        fb = sum(f) / len(f) * 1024 * sf / 1e9
+        wb = sum(w) / len(w) * 1024 * sw / 1e9
+        ms = [v for n, v in avg_ms.items() if k in n]
+        msv = sum(ms) / len(ms) if ms else None
+        rate = f"{(fb + wb) / (msv * 1e-3):.0f}" if msv else "-"
+        mss = f"{msv:.3f}" if msv else "-"
+        out.append(f"| `{k}` | {len(f)} | {fb:.3f} | {wb:.3f} | {fb + wb:.3f} | {mss} | {rate} |")
+    return "\n".join(out) + "\n"
 
 
 def main(argv=None):
@@ -103,13 +145,25 @@ def main(argv=None):
     c = sub.add_parser("counters")
     for k in ("--fetch", "--write", "--copy-fetch", "--copy-write", "--kernel", "--prec", "--source-hash"):
         c.add_argument(k, required=True)
+    c.add_argument("--name", help="the library's id of the kernel (fock_prof.h), e.g. vx_plane_fwd")
     c.add_argument("--out")
     c.add_argument("--command")
+    t = sub.add_parser("traffic")
+    for k in ("--fetch", "--write", "--copy-fetch", "--copy-write"):
+        t.add_argument(k, required=True)
+    t.add_argument("--kernels", required=True, help="comma-separated name substrings")
+    t.add_argument("--durations")
+    t.add_argument("--title")
+    t.add_argument("--command")
     a = ap.parse_args(argv)
     if a.cmd == "stats":
         sys.stdout.write(stats(a.csv, a.title, a.command))
+    elif a.cmd == "traffic":
+        sys.stdout.write(traffic_table(a.fetch, a.write, a.copy_fetch, a.copy_write, a.kernels.split(","), a.title,
+                                       a.command, a.durations))
     else:
-        res = counters(a.fetch, a.write, a.copy_fetch, a.copy_write, a.kernel, a.prec, a.source_hash, a.command)
+        res = counters(a.fetch, a.write, a.copy_fetch, a.copy_write, a.kernel, a.prec, a.source_hash, a.command,
+                       a.name)
         txt = json.dumps(res, indent=1)
         if a.out:
             open(a.out, "w").write(txt + "\n")

@@ -40,6 +40,8 @@ CASES = [
     ((8, 8, 8), (5.0, 5.0, 5.0), 37, "coulomb", 65),
     ((12, 9, 8), (6.0, 4.5, 4.0), 70, "hse", 1),
     ((16, 16, 16), (7.0, 7.0, 7.0), 130, "hse", 131),
+    # a workload edge: W = V_X Psi runs the halved pair path
+    ((24, 24, 24), (10.26, 10.26, 10.26), 40, "hse", 9),
 ]
 
 

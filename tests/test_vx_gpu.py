@@ -231,3 +231,54 @@ def test_specialised_kernels_match_generic_and_oracle(ctx, n):
         e_spec, e_gen = col_err(spec, ref), col_err(gen, ref)
         say("edge", n, prec, "specialised", e_spec, "generic", e_gen, "diff", col_err(spec, gen))
         assert e_spec <= tol and e_gen <= tol
+
+
+@pytest.mark.parametrize("n", [24, 48, 72, 96])
+def test_halved_apply_matches_oracle_and_unhalved(ctx, n):
+    """phi == psi on a workload edge solves each unordered pair once (v_kj = conj v_jk).
+    Against the oracle and the unhalved path, for several block sizes (ragged last
+    block), and bitwise independent of the block size."""
+    import torch
+
+    L = n * 10.26 / 24
+    N = 11 if n < 96 else 5
+    psi = synth.make_orbitals(40 + n, n, L, N)
+    ref = oracle.apply_vx(psi, psi, n, L, "hse", 0.106)
+    P = dev(psi)
+    for prec, tol in (("fp64", TOL64), ("fp32acc64", TOL32), ("fp32", TOL32)):
+        outs = []
+        for nj in ("", "1", "4", "5"):
+            os.environ["FX_VX_NJ"] = nj
+            try:
+                outs.append(host(ctx.apply_vx(P, n=n, L=L, kernel="hse", prec=prec)))
+            finally:
+                os.environ.pop("FX_VX_NJ", None)
+        os.environ["FX_VX_HALVE"] = "0"
+        try:
+            full = host(ctx.apply_vx(P, n=n, L=L, kernel="hse", prec=prec))
+        finally:
+            os.environ.pop("FX_VX_HALVE", None)
+        torch.cuda.synchronize()
+        e_h, e_f = col_err(outs[0], ref), col_err(full, ref)
+        say("halved edge", n, prec, "halved", e_h, "unhalved", e_f, "diff", col_err(outs[0], full))
+        assert e_h <= tol and e_f <= tol
+        bits = np.float64 if outs[0].dtype == np.complex128 else np.float32
+        for o in outs[1:]:
+            assert np.array_equal(o.view(bits), outs[0].view(bits))
+
+
+def test_halved_energy_and_hermitian_projection(ctx):
+    """E_X from the halved path equals the oracle's; Psi^H V_X Psi stays Hermitian."""
+    import torch
+
+    n, L, N = 24, 10.26, 13
+    psi = synth.make_orbitals(77, n, L, N)
+    ref = oracle.apply_vx(psi, psi, n, L, "coulomb")
+    out, ex = ctx.apply_vx(dev(psi), n=n, L=L, kernel="coulomb", prec="fp64", energy=True)
+    torch.cuda.synchronize()
+    got = host(out)
+    assert col_err(got, ref) <= TOL64
+    ex_ref = oracle.exchange_energy(psi, ref)
+    assert abs(ex.item() - ex_ref) <= 1e-12 * abs(ex_ref)
+    M = psi.reshape(N, -1).conj() @ got.reshape(N, -1).T
+    assert np.abs(M - M.conj().T).max() <= 1e-12 * np.abs(M).max()
