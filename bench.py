@@ -77,6 +77,8 @@ def main():
     ap.add_argument("--prec", default="fp32acc64", choices=["fp32acc64", "fp32", "fp64"])
     ap.add_argument("--fp64-steps", type=int, default=2, help="timed FP64 steps for the comparison (0 = skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU oracle budget (0 = skip)")
+    ap.add_argument("--no-autotune", dest="autotune", action="store_false",
+                    help="vx leg: skip the launch-configuration autotuner (run the automatic configuration)")
     ap.add_argument("--leg", default="vx", choices=["vx", "ace", "serve", "copy"],
                     help="vx: V_X apply (default); ace: ACE build + apply at 96^3, N = R = 1024; serve: serving replay")
     ap.add_argument("--requests", type=int, default=12000, help="serve leg: measured requests")
@@ -113,6 +115,12 @@ def main():
     out = torch.empty((Nt, n, n, n), dtype=torch.complex128 if args.prec != "fp32" else torch.complex64, device=dev)
     ctx = Context(0)
     kw = dict(n=n, L=L, kernel="hse", omega=0.106, prec=args.prec, out=out)
+    tune = None
+    if args.autotune:
+        t0 = time.perf_counter()
+        cfg, ms_k = ctx.vx_autotune(n=n, L=L, n_psi=N, n_phi=Nt, phi_is_psi=False, prec=args.prec)
+        tune = {"config": cfg, "ms_per_1000_pairs_probe": ms_k, "seconds": time.perf_counter() - t0}
+        log(f"[bench] autotuned in {tune['seconds']:.1f} s: {cfg}")
 
     for i in range(args.warmup):
         ctx.apply_vx(P, phi, **kw)
@@ -169,6 +177,7 @@ def main():
             "prec": args.prec,
             "accumulation": "f64" if args.prec in ("fp64", "fp32acc64") else "f32",
             "pairs_per_step": pairs,
+            "autotune": tune,
         },
         "roofline": {
             "bound": "hbm",
@@ -253,6 +262,12 @@ def bench_ace(args):
     psi = torch.from_numpy(synth.make_orbitals(w["seed"], n, L, N, dtype=np.complex64)).to("cuda:0")
     phi = torch.from_numpy(synth.make_orbitals(3, n, L, R, dtype=np.complex64)).to("cuda:0")
     ctx = Context(0)
+    tune = None
+    if args.autotune:
+        t0 = time.perf_counter()
+        cfg, ms_k = ctx.vx_autotune(n=n, L=L, n_psi=N, n_phi=N, phi_is_psi=True, prec="fp32acc64")
+        tune = {"config": cfg, "ms_per_1000_pairs_probe": ms_k, "seconds": time.perf_counter() - t0}
+        log(f"[bench-ace] autotuned W = V_X Psi in {tune['seconds']:.1f} s: {cfg}")
     ctx.prof_enable(True)
     t0 = time.perf_counter()
     ace = ctx.build_ace(psi, n=n, L=L, kernel="hse", omega=0.106, vx_prec="fp32acc64", ace_prec="ace_fp64")
@@ -316,7 +331,7 @@ def bench_ace(args):
         "config": {"workload": f"ACE apply K_ACE phi = -xi (xi^H phi), 96^3 grid, N = {N}, R = {R}, "
                                "FP32 matrix cores + FP64-combined residual step", "build_s": t_build,
                    "build_pairs_per_s": N * N / t_build, "build_solves_per_s": solves / t_build,
-                   "build_kernels_ms": build_k},
+                   "build_kernels_ms": build_k, "build_autotune": tune},
         "roofline": res[main_p][dom + "_roofline"],
         "precisions": res,
     }

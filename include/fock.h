@@ -161,6 +161,59 @@ fx_status fx_apply_vx(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* kernel,
                       void* stream, double* ex_energy_dev);
 
 /*
+ * Launch configuration of the V_X pair path for one grid, one V_X precision
+ * and one form (phi == psi with all N targets, or not).  The batching of pair
+ * solves into launches is the paper's batched-FFT step (Sec. 3.2); the
+ * choices below are this library's.  Zero (or -1 where stated) means
+ * automatic.  A configuration changes speed and rounding only: results stay
+ * within the precision's tolerance (other kernel instantiations may fuse
+ * multiply-adds differently), and are bitwise the same for every work_mb.
+ */
+typedef struct fx_vx_config {
+  int32_t kernels;     /* 1 compile-time-specialised (cubic grids of edge 24, 48, 72, 96), 2 generic */
+  int32_t work_mb;     /* pair work volume per batch, MiB (automatic: 8192, at most budget/4) */
+  int32_t a_prefetch;  /* specialised plane-forward pass: 1 prefetch the next plane into
+                          registers, 0 two workgroups per CU instead, -1 automatic (0) */
+  int32_t b_variant;   /* specialised z pass x-tile: 1 the edge's default, 2 half of it */
+  int32_t c_variant;   /* specialised plane-inverse pass threads: 1 the edge's default,
+                          2 a larger count (fewer accumulators per thread, more waves) */
+  int32_t b_xtile;     /* generic z pass: x columns per workgroup */
+  int32_t b_threads;   /* generic z pass: most threads per workgroup (64, 128, 192 or 256) */
+  int32_t radix[3][4]; /* generic: radix schedule of each axis (x, y, z), stages in
+                          order, 0-terminated; radices from {2,3,4,6,8,9,12} with
+                          product n; an all-zero row is the default schedule */
+} fx_vx_config;
+
+/*
+ * Autotuner: times candidate configurations for V_X applies of this shape
+ * (n_psi orbitals, n_phi targets, phi_is_psi != 0 for the phi == psi form)
+ * on synthetic data it allocates itself, by coordinate descent over the
+ * fields above (kernel family; for the specialised kernels the prefetch form,
+ * the z-pass tile and the plane-inverse threads; for the generic kernels the radix schedule of each
+ * axis, the z-pass tile and threads; then the batch volume), and stores the
+ * fastest in the context, where every later fx_apply_vx, fx_build_ace and
+ * served request of that grid, precision and form uses it.  Each candidate
+ * is timed on a probe of at most ~2 full batches of pairs with HIP events on
+ * `stream`; the call waits for the device.  *best (nullable) receives the
+ * winner and *best_ms_per_kpair (nullable) its time per 1000 pair solves.
+ * Errors: FX_ERR_INVALID, FX_ERR_UNSUPPORTED, FX_ERR_OOM, FX_ERR_DEVICE.
+ */
+fx_status fx_vx_autotune(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* kernel, int32_t n_psi, int32_t n_phi,
+                         int32_t phi_is_psi, fx_prec prec, void* stream, fx_vx_config* best,
+                         double* best_ms_per_kpair);
+
+/* Store `cfg` as the context's configuration for (grid, prec, form); NULL
+ * clears it.  Errors: FX_ERR_INVALID (a field out of range, a radix schedule
+ * that does not multiply to its edge, specialised kernels on another grid). */
+fx_status fx_vx_set_config(fx_ctx* ctx, const fx_cell* cell, fx_prec prec, int32_t phi_is_psi,
+                           const fx_vx_config* cfg);
+
+/* The stored configuration for (grid, prec, form): *is_set = 1 and *cfg, or
+ * *is_set = 0 and an all-automatic *cfg. */
+fx_status fx_vx_get_config(fx_ctx* ctx, const fx_cell* cell, fx_prec prec, int32_t phi_is_psi, fx_vx_config* cfg,
+                           int32_t* is_set);
+
+/*
  * Build the ACE factors of V_X[psi]: W = V_X psi (with vx_prec), M = psi^H W in
  * FP64, Hermitised, FP64 Cholesky -M = L L^H, L^{-1} in FP64, xi = W L^{-H}.
  * The handle keeps xi (FP64) and, on first use, the split forms needed by

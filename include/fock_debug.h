@@ -19,6 +19,20 @@ extern "C" {
 fx_status fx_debug_host_pair(const fx_cell* cell, const fx_kernel* kernel, int prec, const double* psi_j,
                              const double* phi_k, double* v);
 
+/* As fx_debug_host_pair, with the radix schedule of each axis given as in
+ * fx_vx_config.radix: `radix` points to 3 rows of 4 int32 (x, y, z), stages
+ * in order, 0-terminated, an all-zero row meaning the default schedule;
+ * NULL means all defaults.  Errors: FX_ERR_INVALID (a row that is not a
+ * schedule of its edge), FX_ERR_UNSUPPORTED. */
+fx_status fx_debug_host_pair_plan(const fx_cell* cell, const fx_kernel* kernel, int prec, const int32_t* radix,
+                                  const double* psi_j, const double* phi_k, double* v);
+
+/* The radix schedules the autotuner considers for edge n (at most three
+ * stages, radices from {2,3,4,6,8,9,12}, the default first): up to
+ * max_plans rows of 4 int32 written to radix_out (0-terminated), their
+ * number to *count.  Errors: FX_ERR_INVALID, FX_ERR_UNSUPPORTED. */
+fx_status fx_debug_axis_plans(int32_t n, int32_t max_plans, int32_t* radix_out, int32_t* count);
+
 #ifdef __cplusplus
 }
 #endif

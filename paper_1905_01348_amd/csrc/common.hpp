@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
+#include <array>
 #include <cstdint>
 #include <map>
 #include <memory>
@@ -75,6 +76,7 @@ struct TableKey {
   int kind;
   double omega, scale;
   int prec;  // 0 = fp64 tables, 1 = fp32 tables
+  int radix[3][4];  // radix schedule of each axis (the fold maps depend on it)
   bool operator<(const TableKey& o) const;
 };
 
@@ -108,6 +110,8 @@ struct fx_ctx {
   std::recursive_mutex mu;
   fx::Workspace ws;  // workspace of the context's own calls
   std::map<fx::TableKey, fx::GridTables> tables;
+  // tuned V_X launch configurations, keyed by (n[3], prec, phi == psi form)
+  std::map<std::array<int, 5>, fx_vx_config> vx_tuning;
   // set by each entry point: the call's stream is being captured into a
   // graph, so nothing may be allocated or uploaded synchronously
   bool capturing = false;
@@ -140,10 +144,6 @@ fx_status note_capture(fx_ctx* ctx, hipStream_t st);
 fx_status ws_get(fx_ctx* ctx, Workspace* ws, const char* name, size_t bytes, void** out);
 void ws_release(fx_ctx* ctx, Workspace* ws);
 
-// Device tables for one grid/kernel/precision (built on the host in FP64).
-fx_status grid_tables(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* kern, int prec,
-                      const GridTables** out);
-
 // Plan of an FFT axis: n = R[0] * R[1] * ... (at most 4 radices from
 // {2,3,4,6,8,9,12}); DIF stages run in this order.
 struct AxisPlan {
@@ -151,9 +151,28 @@ struct AxisPlan {
   int nst;
   int R[4];
 };
+// The default plan: one stage if n is a radix, else two stages as balanced
+// as possible, else up to four.
 bool make_axis_plan(int n, AxisPlan* p);
+// Whether p is a valid schedule for its n (radices from the set, product n).
+bool valid_axis_plan(const AxisPlan& p);
+// Schedules of n with at most three stages, fewest stages and most balanced
+// first; returns how many were written (at most max_out).
+int enumerate_axis_plans(int n, AxisPlan* out, int max_out);
 // Frequency index held at each position after the forward DIF stages.
 void plan_positions(const AxisPlan& p, std::vector<int>* freq_of_pos);
+
+// The schedules of the three axes of one grid.
+struct PlanSet {
+  AxisPlan ax[3];
+};
+void default_plans(const fx_cell* cell, PlanSet* ps);
+bool same_plans(const PlanSet& a, const PlanSet& b);
+
+// Device tables for one grid/kernel/precision (built on the host in FP64),
+// for the given radix schedules (nullptr: the default ones).
+fx_status grid_tables(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* kern, int prec, const PlanSet* plans,
+                      const GridTables** out);
 
 // Host copies of the tables (FP64), used to upload and by the host check.
 struct HostTables {
@@ -162,7 +181,7 @@ struct HostTables {
   std::vector<int> fold[3];
   std::vector<double> kfold;
 };
-void host_tables(const fx_cell* cell, const fx_kernel* kern, HostTables* h);
+void host_tables(const fx_cell* cell, const fx_kernel* kern, HostTables* h, const PlanSet* plans = nullptr);
 
 bool supported_edge(int n);
 fx_status check_cell(const fx_cell* cell);

@@ -1,5 +1,6 @@
 // libfock runtime: errors, contexts, the HBM-budgeted allocator, workspaces
 // and the host-built constant tables (FFT plans, twiddles, kernel K(G)).
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -32,7 +33,11 @@ bool TableKey::operator<(const TableKey& o) const {
   if (kind != o.kind) return kind < o.kind;
   if (omega != o.omega) return omega < o.omega;
   if (scale != o.scale) return scale < o.scale;
-  return prec < o.prec;
+  if (prec != o.prec) return prec < o.prec;
+  for (int a = 0; a < 3; ++a)
+    for (int i = 0; i < 4; ++i)
+      if (radix[a][i] != o.radix[a][i]) return radix[a][i] < o.radix[a][i];
+  return false;
 }
 
 // Optional fault injection for error-path tests: FX_FAULT_INJECT=<k> makes the
@@ -236,6 +241,76 @@ static void positions_rec(const int* R, int nst, int n, std::vector<int>& f) {
     for (int q = 0; q < span; ++q) f[k1 * span + q] = k1 + r * sub[q];
 }
 
+bool valid_axis_plan(const AxisPlan& p) {
+  if (p.nst < 1 || p.nst > 4 || !supported_edge(p.n)) return false;
+  int prod = 1;
+  for (int i = 0; i < p.nst; ++i) {
+    if (!is_radix(p.R[i])) return false;
+    prod *= p.R[i];
+  }
+  for (int i = p.nst; i < 4; ++i)
+    if (p.R[i] != 1) return false;
+  return prod == p.n;
+}
+
+int enumerate_axis_plans(int n, AxisPlan* out, int max_out) {
+  std::vector<AxisPlan> all;
+  const int rad[] = {2, 3, 4, 6, 8, 9, 12};
+  auto push = [&](int nst, int a, int b, int c) {
+    AxisPlan p;
+    p.n = n;
+    p.nst = nst;
+    p.R[0] = a;
+    p.R[1] = b;
+    p.R[2] = c;
+    p.R[3] = 1;
+    if (valid_axis_plan(p)) all.push_back(p);
+  };
+  if (is_radix(n)) push(1, n, 1, 1);
+  for (int a : rad)
+    if (n % a == 0 && is_radix(n / a)) push(2, a, n / a, 1);
+  for (int a : rad)
+    for (int b : rad)
+      if (n % (a * b) == 0 && is_radix(n / (a * b))) push(3, a, b, n / (a * b));
+  auto maxr = [](const AxisPlan& p) {
+    int m = 0;
+    for (int i = 0; i < p.nst; ++i) m = p.R[i] > m ? p.R[i] : m;
+    return m;
+  };
+  std::stable_sort(all.begin(), all.end(), [&](const AxisPlan& x, const AxisPlan& y) {
+    if (x.nst != y.nst) return x.nst < y.nst;
+    return maxr(x) < maxr(y);
+  });
+  // the default plan first
+  AxisPlan d;
+  int k = 0;
+  if (make_axis_plan(n, &d) && max_out > 0) out[k++] = d;
+  for (const AxisPlan& p : all) {
+    if (k >= max_out) break;
+    bool dup = false;
+    for (int i = 0; i < k; ++i) {
+      bool eq = out[i].nst == p.nst;
+      for (int r = 0; eq && r < p.nst; ++r) eq = out[i].R[r] == p.R[r];
+      dup = dup || eq;
+    }
+    if (!dup) out[k++] = p;
+  }
+  return k;
+}
+
+void default_plans(const fx_cell* cell, PlanSet* ps) {
+  for (int a = 0; a < 3; ++a) make_axis_plan(cell->n[a], &ps->ax[a]);
+}
+
+bool same_plans(const PlanSet& a, const PlanSet& b) {
+  for (int x = 0; x < 3; ++x) {
+    if (a.ax[x].n != b.ax[x].n || a.ax[x].nst != b.ax[x].nst) return false;
+    for (int i = 0; i < a.ax[x].nst; ++i)
+      if (a.ax[x].R[i] != b.ax[x].R[i]) return false;
+  }
+  return true;
+}
+
 void plan_positions(const AxisPlan& p, std::vector<int>* freq_of_pos) {
   positions_rec(p.R, p.nst, p.n, *freq_of_pos);
 }
@@ -277,12 +352,15 @@ static fx_status upload(fx_ctx* ctx, const std::vector<T>& h, void** d, size_t* 
   return FX_OK;
 }
 
-void host_tables(const fx_cell* cell, const fx_kernel* kern, HostTables* h) {
+void host_tables(const fx_cell* cell, const fx_kernel* kern, HostTables* h, const PlanSet* plans) {
   const double pi = 3.14159265358979323846264338327950288;
   for (int a = 0; a < 3; ++a) {
     const int n = cell->n[a];
     AxisPlan p;
-    make_axis_plan(n, &p);
+    if (plans)
+      p = plans->ax[a];
+    else
+      make_axis_plan(n, &p);
     h->plan[a] = p;
     std::vector<int> fp;
     plan_positions(p, &fp);
@@ -303,11 +381,18 @@ void host_tables(const fx_cell* cell, const fx_kernel* kern, HostTables* h) {
       }
 }
 
-fx_status grid_tables(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* kern, int prec, const GridTables** out) {
+fx_status grid_tables(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* kern, int prec, const PlanSet* plans,
+                      const GridTables** out) {
+  PlanSet ps;
+  if (plans)
+    ps = *plans;
+  else
+    default_plans(cell, &ps);
   TableKey key;
   for (int a = 0; a < 3; ++a) {
     key.n[a] = cell->n[a];
     key.len[a] = cell->len[a];
+    for (int i = 0; i < 4; ++i) key.radix[a][i] = i < ps.ax[a].nst ? ps.ax[a].R[i] : 0;
   }
   key.kind = kern->kind;
   key.omega = kern->kind == FX_HSE ? kern->omega : 0.0;
@@ -323,7 +408,7 @@ fx_status grid_tables(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* kern, i
             "grid tables for this cell and kernel are not on the device yet and the stream is being captured; "
             "run the same call once outside capture first");
   HostTables h;
-  host_tables(cell, kern, &h);
+  host_tables(cell, kern, &h, &ps);
   GridTables t;
   for (int a = 0; a < 3; ++a) {
     if (prec == 0) {

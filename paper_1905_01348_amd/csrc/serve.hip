@@ -331,6 +331,22 @@ fx_status fx_serve(fx_server* srv, const fx_request* reqs, int32_t n_reqs, fx_st
       }
       fx_status s = launch(sl, batch);
       if (s == FX_ERR_OOM) {
+        // idle slots keep the workspaces of their last batch: hand them back
+        // (their streams have finished) and try once more
+        for (auto& other : srv->slots) {
+          if (other.busy) continue;
+          // the failed attempt may have queued copies on this slot's stream
+          if (hipStreamSynchronize(other.st) != hipSuccess) {
+            fatal = FX_ERR_DEVICE;
+            break;
+          }
+          ws_release(ctx, &other.ws);
+        }
+        if (fatal != FX_OK) break;
+        clear_error();
+        s = launch(sl, batch);
+      }
+      if (s == FX_ERR_OOM) {
         if (nbusy > 0) break;  // wait for memory to drain
         for (int i : batch) {
           status[i] = FX_ERR_OOM;

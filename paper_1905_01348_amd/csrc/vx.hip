@@ -22,6 +22,8 @@ namespace fx {
 // the current one, so the loads are in flight while the LDS stages run.
 // ---------------------------------------------------------------------------
 constexpr int kPlaneThreads = 512;
+// most threads of a generic z-pass workgroup (its launch bound)
+constexpr int kPencilThreads = 256;
 
 template <typename T, int EPT>
 __global__ void __launch_bounds__(kPlaneThreads) k_pass_a(const cpx<T>* __restrict__ psi, int64_t ld_psi,
@@ -88,7 +90,7 @@ __global__ void __launch_bounds__(kPlaneThreads) k_pass_a(const cpx<T>* __restri
 
 // Pass B: one (pair, y, x-tile) per workgroup; many small workgroups per CU.
 template <typename T, int EPT>
-__global__ void __launch_bounds__(256) k_pass_b(cpx<T>* __restrict__ work, int xt, int ntx, PassGeom g,
+__global__ void __launch_bounds__(kPencilThreads) k_pass_b(cpx<T>* __restrict__ work, int xt, int ntx, PassGeom g,
                                                 const cpx<T>* __restrict__ twz_g, const T* __restrict__ kfold,
                                                 const int* __restrict__ foldx_g, const int* __restrict__ foldy_g,
                                                 const int* __restrict__ foldz_g) {
@@ -282,20 +284,21 @@ static AxisArg to_arg(const AxisPlan& p) {
   return a;
 }
 
-PassGeom make_geom(const fx_cell* cell) {
+PassGeom make_geom(const fx_cell* cell, const PlanSet* plans = nullptr) {
   PassGeom g;
   g.nx = cell->n[0];
   g.ny = cell->n[1];
   g.nz = cell->n[2];
   // odd row stride (in elements) so consecutive rows start in different banks
   g.sx = g.nx % 2 ? g.nx : g.nx + 1;
-  AxisPlan p;
-  make_axis_plan(g.nx, &p);
-  g.ax = to_arg(p);
-  make_axis_plan(g.ny, &p);
-  g.ay = to_arg(p);
-  make_axis_plan(g.nz, &p);
-  g.az = to_arg(p);
+  PlanSet ps;
+  if (plans)
+    ps = *plans;
+  else
+    default_plans(cell, &ps);
+  g.ax = to_arg(ps.ax[0]);
+  g.ay = to_arg(ps.ax[1]);
+  g.az = to_arg(ps.ax[2]);
   g.hx = g.nx / 2 + 1;
   g.hy = g.ny / 2 + 1;
   g.hz = g.nz / 2 + 1;
@@ -401,7 +404,7 @@ static fx_status run_halved(fx_ctx* ctx, Workspace* ws, const VxArgs& a, const G
       const int tri = J == K;
       const int npairs = tri ? jb * (jb + 1) / 2 : jb * kb;
       CtBatch<T> cb{psi, ld_psi, psi, ld_psi, reinterpret_cast<cpx<T>*>(work), j0, jb, k0, kb, npairs, tw, kf,
-                    tb->fold[0], tri};
+                    tb->fold[0], tri, a.a_pipe > 0 ? 1 : 0, a.b_var == 2 ? 2 : 1, a.c_var == 2 ? 2 : 1};
       const double vol = (double)npairs * nr * sz;
       int slot;
       FX_TRY(prof_begin(ctx, st, FX_K_VX_PLANE_FWD, 3.0 * vol, &slot));
@@ -446,14 +449,23 @@ template <typename T, typename A>
 static fx_status run_batches(fx_ctx* ctx, Workspace* ws, const VxArgs& a, const GridTables* tb,
                              const cpx<T>* psi, int64_t ld_psi, const cpx<T>* phi, int64_t ld_phi, hipStream_t st,
                              VxStats* stats) {
-  const PassGeom g = make_geom(a.cell);
+  const PassGeom g = make_geom(a.cell, a.plans_set ? &a.plans : nullptr);
   const int64_t nr = (int64_t)g.nx * g.ny * g.nz;
   const int nxy = g.nx * g.ny;
   const size_t pair_bytes = (size_t)nr * sizeof(cpx<T>);
-  size_t cap = a.work_cap ? a.work_cap : work_cap_bytes(ctx);
+  size_t cap = a.work_cap ? std::min(a.work_cap, ctx->budget / 4) : work_cap_bytes(ctx);
   const int64_t pairs_cap = (int64_t)std::max<size_t>(1, cap / pair_bytes);
-  // cubic grids of the workload edges run the compile-time-specialised kernels
-  const bool use_ct = ct_supported(a.cell);
+  // cubic grids of the workload edges run the compile-time-specialised
+  // kernels unless the generic family or another radix schedule is asked for
+  bool use_ct = ct_supported(a.cell) && a.kernels != 2;
+  if (use_ct && a.plans_set) {
+    PlanSet d;
+    default_plans(a.cell, &d);
+    use_ct = same_plans(a.plans, d);
+  }
+  if (a.kernels == 1 && !use_ct)
+    FX_FAIL(FX_ERR_UNSUPPORTED, "no specialised kernels for grid %dx%dx%d with this radix schedule", g.nx, g.ny,
+            g.nz);
   if (use_ct && a.halve != 0 && psi == phi && ld_psi == ld_phi && a.n_psi == a.n_phi)
     return run_halved<T, A>(ctx, ws, a, tb, psi, ld_psi, pairs_cap, st, stats);
   // Batch shape: up to 16 orbitals per batch first (the plane-inverse pass
@@ -497,7 +509,7 @@ static fx_status run_batches(fx_ctx* ctx, Workspace* ws, const VxArgs& a, const 
   if (a.xtile > 0) xt = std::min(g.nx, a.xtile);
   const int ntx = (g.nx + xt - 1) / xt;
   int ept_b = 0, nthr_b = 0;
-  if (!pick_ept(g.nz * xt, a.nthr_b > 0 ? a.nthr_b : 256, &ept_b, &nthr_b))
+  if (!pick_ept(g.nz * xt, a.nthr_b > 0 ? std::min(a.nthr_b, kPencilThreads) : kPencilThreads, &ept_b, &nthr_b))
     FX_FAIL(FX_ERR_UNSUPPORTED, "pencil tile of %d points is too large", g.nz * xt);
   const size_t lds_plane = ((size_t)plane_lds_elems(g) + g.nx + g.ny) * sizeof(cpx<T>);
   const size_t lds_b = ((size_t)g.nz * xt + g.nz) * sizeof(cpx<T>) + (size_t)g.hz * g.hx * sizeof(T) +
@@ -518,7 +530,7 @@ static fx_status run_batches(fx_ctx* ctx, Workspace* ws, const VxArgs& a, const 
       int slot;
       if (use_ct) {
         CtBatch<T> cb{psi, ld_psi, phi, ld_phi, reinterpret_cast<cpx<T>*>(work), j0, jb, k0, kb, npairs, twx, kf,
-                      tb->fold[0], 0};
+                      tb->fold[0], 0, a.a_pipe > 0 ? 1 : 0, a.b_var == 2 ? 2 : 1, a.c_var == 2 ? 2 : 1};
         CtAcc<A> ca{acc, ld_acc, first, a.out, a.ld_out, out_c64 ? 1 : 0, last, a.pipe};
         FX_TRY(prof_begin(ctx, st, FX_K_VX_PLANE_FWD, 3.0 * vol, &slot));
         FX_TRY(ct_pass_a<T>(ctx, st, g.nx, cb));
@@ -624,12 +636,70 @@ fx_status check_vx_args(const VxArgs& a) {
   return FX_OK;
 }
 
-fx_status vx_apply(fx_ctx* ctx, Workspace* ws, const VxArgs& a, hipStream_t st, VxStats* stats) {
-  FX_TRY(check_vx_args(a));
+bool plans_from_radix(const fx_cell* cell, const int32_t radix[3][4], PlanSet* ps, bool* any) {
+  default_plans(cell, ps);
+  *any = false;
+  for (int x = 0; x < 3; ++x) {
+    if (radix[x][0] == 0) continue;
+    AxisPlan p;
+    p.n = cell->n[x];
+    p.nst = 0;
+    for (int i = 0; i < 4; ++i) p.R[i] = 1;
+    for (int i = 0; i < 4 && radix[x][i] != 0; ++i) p.R[p.nst++] = radix[x][i];
+    for (int i = p.nst; i < 4; ++i)
+      if (radix[x][i] != 0) return false;
+    if (!valid_axis_plan(p)) return false;
+    ps->ax[x] = p;
+    *any = true;
+  }
+  return true;
+}
+
+std::array<int, 5> vx_tune_key(const fx_cell* cell, fx_prec prec, bool square) {
+  return {cell->n[0], cell->n[1], cell->n[2], (int)prec, square ? 1 : 0};
+}
+
+void resolve_vx_config(fx_ctx* ctx, VxArgs* a) {
+  // environment overrides, for experiments and comparisons
+  if (const char* e = getenv("FX_VX_NJ")) a->force_nj = atoi(e);
+  if (const char* e = getenv("FX_VX_XT")) a->xtile = atoi(e);
+  if (const char* e = getenv("FX_VX_PIPE")) a->pipe = atoi(e);
+  if (const char* e = getenv("FX_VX_NTHR_B")) a->nthr_b = atoi(e);
+  if (const char* e = getenv("FX_VX_HALVE")) a->halve = atoi(e);
+  if (const char* e = getenv("FX_VX_A_PIPE")) a->a_pipe = atoi(e);
+  if (const char* e = getenv("FX_VX_B_VAR")) a->b_var = atoi(e);
+  if (const char* e = getenv("FX_VX_C_VAR")) a->c_var = atoi(e);
+  if (getenv("FX_VX_GENERIC")) a->kernels = 2;
+  if (const char* e = getenv("FX_WORK_MB")) a->work_cap = (size_t)atol(e) << 20;
+  if (!ctx) return;
+  auto it = ctx->vx_tuning.find(vx_tune_key(a->cell, a->prec, vx_square_form(*a)));
+  if (it == ctx->vx_tuning.end()) return;
+  const fx_vx_config& c = it->second;
+  if (!a->kernels) a->kernels = c.kernels;
+  if (!a->work_cap && c.work_mb > 0) a->work_cap = (size_t)c.work_mb << 20;
+  if (a->a_pipe < 0 && c.a_prefetch >= 0) a->a_pipe = c.a_prefetch;
+  if (!a->b_var) a->b_var = c.b_variant;
+  if (!a->c_var) a->c_var = c.c_variant;
+  if (!a->xtile) a->xtile = c.b_xtile;
+  if (!a->nthr_b) a->nthr_b = c.b_threads;
+  if (!a->plans_set) {
+    bool any = false;
+    PlanSet ps;
+    if (plans_from_radix(a->cell, c.radix, &ps, &any) && any) {
+      a->plans = ps;
+      a->plans_set = true;
+    }
+  }
+}
+
+fx_status vx_apply(fx_ctx* ctx, Workspace* ws, const VxArgs& a_in, hipStream_t st, VxStats* stats) {
+  FX_TRY(check_vx_args(a_in));
+  VxArgs a = a_in;
+  resolve_vx_config(ctx, &a);
   const int64_t nr = (int64_t)a.cell->n[0] * a.cell->n[1] * a.cell->n[2];
   const bool t64 = a.prec == FX_PREC_FP64;
   const GridTables* tb = nullptr;
-  FX_TRY(grid_tables(ctx, a.cell, a.kern, t64 ? 0 : 1, &tb));
+  FX_TRY(grid_tables(ctx, a.cell, a.kern, t64 ? 0 : 1, a.plans_set ? &a.plans : nullptr, &tb));
   const bool same = a.phi == a.psi && a.ld_phi == a.ld_psi;
   const bool need_conv = (a.in_dtype == FX_C128) != t64;
   const void* psi = a.psi;
@@ -700,8 +770,8 @@ fx_status vx_apply(fx_ctx* ctx, Workspace* ws, const VxArgs& a, hipStream_t st, 
 // Inputs and outputs are host arrays of N_r interleaved complex doubles.
 template <typename T>
 static void host_pair(const fx_cell* cell, const HostTables& h, const double* psi_j, const double* phi_k, double* v,
-                      int xtile) {
-  const PassGeom g = make_geom(cell);
+                      int xtile, const PlanSet* plans) {
+  const PassGeom g = make_geom(cell, plans);
   const size_t nxy = (size_t)g.nx * g.ny, nr = nxy * g.nz;
   std::vector<cpx<T>> a(nr), b(nr), vol(nr);
   for (size_t i = 0; i < nr; ++i) {
@@ -764,30 +834,47 @@ fx_status fx_apply_vx(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* kernel,
   a.out_dtype = out_dtype;
   a.prec = prec;
   a.ex_dev = ex_energy_dev;
-  if (const char* e = getenv("FX_VX_NJ")) a.force_nj = atoi(e);
-  if (const char* e = getenv("FX_VX_XT")) a.xtile = atoi(e);
-  if (const char* e = getenv("FX_VX_PIPE")) a.pipe = atoi(e);
-  if (const char* e = getenv("FX_VX_NTHR_B")) a.nthr_b = atoi(e);
-  if (const char* e = getenv("FX_VX_HALVE")) a.halve = atoi(e);
   hipStream_t st = (hipStream_t)stream;
   FX_TRY(note_capture(ctx, st));
   return vx_apply(ctx, &ctx->ws, a, st, nullptr);
 }
 
-fx_status fx_debug_host_pair(const fx_cell* cell, const fx_kernel* kernel, int prec, const double* psi_j,
-                             const double* phi_k, double* v) {
+fx_status fx_debug_host_pair_plan(const fx_cell* cell, const fx_kernel* kernel, int prec, const int32_t* radix,
+                                  const double* psi_j, const double* phi_k, double* v) {
   int xtile = cell ? cell->n[0] : 1;
   if (const char* e = getenv("FX_VX_XT")) xtile = atoi(e);
   clear_error();
   FX_TRY(check_cell(cell));
   FX_TRY(check_kernel(kernel));
   if (!psi_j || !phi_k || !v) FX_FAIL(FX_ERR_INVALID, "NULL host pointer");
+  PlanSet ps;
+  bool any = false;
+  if (radix && !plans_from_radix(cell, reinterpret_cast<const int32_t(*)[4]>(radix), &ps, &any))
+    FX_FAIL(FX_ERR_INVALID, "invalid radix schedule");
+  const PlanSet* pp = radix ? &ps : nullptr;
   HostTables h;
-  host_tables(cell, kernel, &h);
+  host_tables(cell, kernel, &h, pp);
   if (prec == 0)
-    host_pair<double>(cell, h, psi_j, phi_k, v, xtile);
+    host_pair<double>(cell, h, psi_j, phi_k, v, xtile, pp);
   else
-    host_pair<float>(cell, h, psi_j, phi_k, v, xtile);
+    host_pair<float>(cell, h, psi_j, phi_k, v, xtile, pp);
+  return FX_OK;
+}
+
+fx_status fx_debug_host_pair(const fx_cell* cell, const fx_kernel* kernel, int prec, const double* psi_j,
+                             const double* phi_k, double* v) {
+  return fx_debug_host_pair_plan(cell, kernel, prec, nullptr, psi_j, phi_k, v);
+}
+
+fx_status fx_debug_axis_plans(int32_t n, int32_t max_plans, int32_t* radix_out, int32_t* count) {
+  clear_error();
+  if (!radix_out || !count || max_plans <= 0) FX_FAIL(FX_ERR_INVALID, "bad output arguments");
+  if (!supported_edge(n)) FX_FAIL(FX_ERR_UNSUPPORTED, "edge %d is not 2^a 3^b in [2, 96]", n);
+  std::vector<AxisPlan> ps((size_t)max_plans);
+  const int k = enumerate_axis_plans(n, ps.data(), max_plans);
+  for (int i = 0; i < k; ++i)
+    for (int r = 0; r < 4; ++r) radix_out[4 * i + r] = r < ps[i].nst ? ps[i].R[r] : 0;
+  *count = k;
   return FX_OK;
 }
 

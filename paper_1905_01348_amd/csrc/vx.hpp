@@ -21,14 +21,33 @@ struct VxArgs {
   fx_dtype out_dtype = FX_C128;
   fx_prec prec = FX_PREC_FP64;
   double* ex_dev = nullptr;
-  // tuning (0 = automatic)
+  // launch configuration (0 / -1 = automatic: the context's tuned
+  // configuration for this grid and form if there is one, else defaults)
   size_t work_cap = 0;  // bytes of pair work volume per batch
   int force_nj = 0;     // orbitals per batch
-  int nthr_b = 0;  // threads of the pencil pass
-  int xtile = 0;   // x columns per pencil-pass workgroup
-  int pipe = -1;   // plane-inverse pass prefetches the next plane: 1 yes, 0 no, -1 automatic
+  int nthr_b = 0;  // generic z pass: threads per workgroup
+  int xtile = 0;   // generic z pass: x columns per workgroup
+  int pipe = -1;   // generic plane-inverse pass prefetches the next plane: 1 yes, 0 no, -1 automatic
   int halve = -1;  // phi == psi: solve each unordered pair once (1 yes, 0 no, -1 automatic)
+  int kernels = 0;  // 1 specialised (cubic workload edges only), 2 generic, 0 automatic
+  int a_pipe = -1;  // specialised plane-forward pass: 1 register prefetch, 0 two workgroups per CU
+  int b_var = 0;    // specialised z pass tile: 1 default, 2 half, 0 automatic
+  int c_var = 0;    // specialised plane-inverse threads: 1 default, 2 second count, 0 automatic
+  bool plans_set = false;  // generic kernels: radix schedules in `plans`
+  PlanSet plans;
 };
+
+// Radix rows (0-terminated, all-zero row = default) to plans; false if a row
+// is not a valid schedule of its edge.  *any: some row was given.
+bool plans_from_radix(const fx_cell* cell, const int32_t radix[3][4], PlanSet* ps, bool* any);
+std::array<int, 5> vx_tune_key(const fx_cell* cell, fx_prec prec, bool square);
+// Fill the automatic fields of `a` from the environment (FX_VX_* overrides,
+// for experiments), then from the context's tuned configuration.
+void resolve_vx_config(fx_ctx* ctx, VxArgs* a);
+// Whether a call is the phi == psi form (all targets are the orbitals).
+inline bool vx_square_form(const VxArgs& a) {
+  return a.phi == a.psi && a.ld_phi == a.ld_psi && a.n_phi == a.n_psi;
+}
 
 struct VxStats {
   int nk = 0, nj = 0;
@@ -50,6 +69,9 @@ struct CtBatch {
   const T* kfold;
   const int* fold;  // folded frequency per digit-reversed position
   int tri;          // diagonal batch of a halved apply: pairs jj <= kk only, packed
+  int a_pipe;       // plane-forward pass: register prefetch of the next plane
+  int b_var;        // z pass: 1 default x tile, 2 half tile
+  int c_var;        // plane-inverse pass: 1 default threads, 2 the second thread count
 };
 template <typename A>
 struct CtAcc {

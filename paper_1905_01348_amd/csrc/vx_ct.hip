@@ -97,12 +97,10 @@ __global__ void __launch_bounds__(CubeShape<N>::NT_P, (PassAWaves<T, PIPE>::valu
 }
 
 // ---- pass B: z convolution on an x tile ---------------------------------------
-template <typename T, int N>
-__global__ void __launch_bounds__(CubeShape<N>::NT_B) k_pass_b_ct(cpx<T>* __restrict__ work,
-                                                                  const cpx<T>* __restrict__ twg,
-                                                                  const T* __restrict__ kfold,
-                                                                  const int* __restrict__ foldg) {
-  constexpr int NT = CubeShape<N>::NT_B, XT = CubeShape<N>::XT, NTX = N / XT, NE = N * XT;
+template <typename T, int N, int XT, int NT>
+__global__ void __launch_bounds__(NT) k_pass_b_ct(cpx<T>* __restrict__ work, const cpx<T>* __restrict__ twg,
+                                                  const T* __restrict__ kfold, const int* __restrict__ foldg) {
+  constexpr int NTX = N / XT, NE = N * XT;
   constexpr int H = N / 2 + 1;
   static_assert(N % XT == 0, "x tile must divide the edge");
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -166,13 +164,13 @@ __global__ void __launch_bounds__(CubeShape<N>::NT_B) k_pass_b_ct(cpx<T>* __rest
 // runs over its k in ascending order, adding psi_{m0+kk} * conj(v_{jk}),
 // which is v_{kj} since the kernel is real and even.  On a diagonal batch
 // (tri) role 0 takes jj <= kk and role 1 kk > jj.
-template <typename T, typename A, int N, bool CONJ>
-__global__ void __launch_bounds__(CubeShape<N>::NT_P) k_pass_c_ct(const cpx<T>* __restrict__ mult, int64_t ld_mult,
+template <typename T, typename A, int N, bool CONJ, int NT>
+__global__ void __launch_bounds__(NT) k_pass_c_ct(const cpx<T>* __restrict__ mult, int64_t ld_mult,
                                                                   const cpx<T>* __restrict__ work, int nj, int nk,
                                                                   int tri, int m0, int t0, int nitems, cpx<A>* acc,
                                                                   int64_t ld_acc, int first, void* out, int64_t ld_out,
                                                                   int out_c64, int last, const cpx<T>* __restrict__ twg) {
-  constexpr int NT = CubeShape<N>::NT_P, NXY = N * N, SX = N + 1, EPT = CeilDiv<NXY, NT>::value;
+  constexpr int NXY = N * N, SX = N + 1, EPT = CeilDiv<NXY, NT>::value;
   constexpr size_t NR = (size_t)NXY * N;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* s = reinterpret_cast<cpx<T>*>(smem_raw);
@@ -242,7 +240,6 @@ __global__ void __launch_bounds__(CubeShape<N>::NT_P) k_pass_c_ct(const cpx<T>* 
 bool ct_supported(const fx_cell* cell) {
   const int n = cell->n[0];
   if (cell->n[1] != n || cell->n[2] != n) return false;
-  if (getenv("FX_VX_GENERIC")) return false;
   AxisPlan p;
   if (!make_axis_plan(n, &p) || p.nst != 2) return false;
   switch (n) {
@@ -271,8 +268,8 @@ template <typename T, int N>
 static fx_status pass_a_n(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b) {
   constexpr int NT = CubeShape<N>::NT_P;
   const size_t lds = ((size_t)N * (N + 1) + N) * sizeof(cpx<T>);
-  bool pipe = sizeof(T) == 4;
-  if (const char* e = getenv("FX_VX_A_PIPE")) pipe = pipe && atoi(e) != 0;
+  // the prefetching form exists for FP32 only (FP64 has no registers to spare)
+  const bool pipe = sizeof(T) == 4 && b.a_pipe;
   auto kern = pipe ? k_pass_a_ct<T, N, sizeof(T) == 4> : k_pass_a_ct<T, N, false>;
   const int items = b.npairs * N;
   int grid = 0;
@@ -283,11 +280,12 @@ static fx_status pass_a_n(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b) {
   return FX_OK;
 }
 
-template <typename T, int N>
-static fx_status pass_b_n(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b) {
-  constexpr int NT = CubeShape<N>::NT_B, XT = CubeShape<N>::XT, H = N / 2 + 1;
+template <typename T, int N, int XT, int NT>
+static fx_status pass_b_shape(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b) {
+  static_assert(N % XT == 0, "x tile must divide the edge");
+  constexpr int H = N / 2 + 1;
   const size_t lds = ((size_t)N * XT + N) * sizeof(cpx<T>) + (size_t)H * H * sizeof(T) + (size_t)N * sizeof(int);
-  auto kern = k_pass_b_ct<T, N>;
+  auto kern = k_pass_b_ct<T, N, XT, NT>;
   const int items = b.npairs * N * (N / XT);
   int grid = 0;
   FX_TRY(ct_prepare(ctx, kern, NT, lds, items, false, &grid));
@@ -296,12 +294,18 @@ static fx_status pass_b_n(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b) {
   return FX_OK;
 }
 
-template <typename T, typename A, int N>
-static fx_status pass_c_n(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b, const CtAcc<A>& c, int role) {
-  constexpr int NT = CubeShape<N>::NT_P;
+template <typename T, int N>
+static fx_status pass_b_n(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b) {
+  using S = CubeShape<N>;
+  if (b.b_var == 2) return pass_b_shape<T, N, S::XT2, S::NT_B2>(ctx, st, b);
+  return pass_b_shape<T, N, S::XT, S::NT_B>(ctx, st, b);
+}
+
+template <typename T, typename A, int N, int NT>
+static fx_status pass_c_shape(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b, const CtAcc<A>& c, int role) {
   const size_t lds = ((size_t)N * (N + 1) + N) * sizeof(cpx<T>);
   const int items = (role ? b.nj : b.nk) * N;
-  auto kern = role ? k_pass_c_ct<T, A, N, true> : k_pass_c_ct<T, A, N, false>;
+  auto kern = role ? k_pass_c_ct<T, A, N, true, NT> : k_pass_c_ct<T, A, N, false, NT>;
   int grid = 0;
   FX_TRY(ct_prepare(ctx, kern, NT, lds, items, true, &grid));
   if (role)
@@ -312,6 +316,13 @@ static fx_status pass_c_n(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b, cons
                        b.j0, b.k0, items, c.acc, c.ld_acc, c.first, c.out, c.ld_out, c.out_c64, c.last, b.tw);
   FX_LAUNCH_CHECK();
   return FX_OK;
+}
+
+template <typename T, typename A, int N>
+static fx_status pass_c_n(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b, const CtAcc<A>& c, int role) {
+  using S = CubeShape<N>;
+  if (b.c_var == 2) return pass_c_shape<T, A, N, S::NT_C2>(ctx, st, b, c, role);
+  return pass_c_shape<T, A, N, S::NT_P>(ctx, st, b, c, role);
 }
 
 template <typename T>

@@ -60,6 +60,29 @@ class FxServeReport(C.Structure):
                 ("n_batches", C.c_int64), ("hbm_peak_bytes", C.c_size_t)]
 
 
+class FxVxConfig(C.Structure):
+    _fields_ = [("kernels", C.c_int32), ("work_mb", C.c_int32), ("a_prefetch", C.c_int32),
+                ("b_variant", C.c_int32), ("c_variant", C.c_int32), ("b_xtile", C.c_int32), ("b_threads", C.c_int32),
+                ("radix", (C.c_int32 * 4) * 3)]
+
+
+def config_to_dict(c):
+    return {"kernels": c.kernels, "work_mb": c.work_mb, "a_prefetch": c.a_prefetch, "b_variant": c.b_variant,
+            "c_variant": c.c_variant, "b_xtile": c.b_xtile, "b_threads": c.b_threads, "radix": [list(row) for row in c.radix]}
+
+
+def config_from_dict(d):
+    c = FxVxConfig()
+    c.a_prefetch = -1
+    for k in ("kernels", "work_mb", "a_prefetch", "b_variant", "c_variant", "b_xtile", "b_threads"):
+        if k in d:
+            setattr(c, k, int(d[k]))
+    for a, row in enumerate(d.get("radix", [])):
+        for i, r in enumerate(list(row) + [0] * (4 - len(row))):
+            c.radix[a][i] = int(r)
+    return c
+
+
 # exported names and their signatures
 _SIGS = {
     "fx_init": (C.c_int, [C.c_int, C.c_size_t, C.POINTER(C.c_void_p)]),
@@ -89,6 +112,14 @@ _SIGS = {
                                C.POINTER(C.c_double)]),
     "fx_debug_host_pair": (C.c_int, [C.POINTER(FxCell), C.POINTER(FxKernel), C.c_int, C.c_void_p, C.c_void_p,
                                       C.c_void_p]),
+    "fx_debug_host_pair_plan": (C.c_int, [C.POINTER(FxCell), C.POINTER(FxKernel), C.c_int, C.c_void_p, C.c_void_p,
+                                           C.c_void_p, C.c_void_p]),
+    "fx_debug_axis_plans": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.POINTER(C.c_int32)]),
+    "fx_vx_autotune": (C.c_int, [C.c_void_p, C.POINTER(FxCell), C.POINTER(FxKernel), C.c_int32, C.c_int32, C.c_int32,
+                                 C.c_int, C.c_void_p, C.POINTER(FxVxConfig), C.POINTER(C.c_double)]),
+    "fx_vx_set_config": (C.c_int, [C.c_void_p, C.POINTER(FxCell), C.c_int, C.c_int32, C.POINTER(FxVxConfig)]),
+    "fx_vx_get_config": (C.c_int, [C.c_void_p, C.POINTER(FxCell), C.c_int, C.c_int32, C.POINTER(FxVxConfig),
+                                   C.POINTER(C.c_int32)]),
 }
 
 _lib = None
@@ -243,6 +274,35 @@ class Context:
                                   C.c_void_p(ex.data_ptr()) if ex is not None else None))
         return (out, ex) if energy else out
 
+    # -- launch configuration of the V_X path ------------------------------------
+    def vx_autotune(self, *, n, L, n_psi, n_phi, phi_is_psi=False, prec="fp32acc64", kernel="hse", omega=0.106,
+                    scale=1.0, stream=None):
+        """Tune and store the V_X launch configuration of this shape; returns (config dict, ms per 1000 pairs)."""
+        cell = make_cell(n, L)
+        kern = make_kernel(kernel, omega, scale)
+        cfg = FxVxConfig()
+        ms = C.c_double()
+        _check(load().fx_vx_autotune(self.h, C.byref(cell), C.byref(kern), int(n_psi), int(n_phi),
+                                     1 if phi_is_psi else 0, PREC[prec], _stream_ptr(stream), C.byref(cfg),
+                                     C.byref(ms)))
+        return config_to_dict(cfg), ms.value
+
+    def set_vx_config(self, cfg, *, n, L=1.0, prec="fp32acc64", phi_is_psi=False):
+        """Store a configuration (dict, fields of fx_vx_config) for (grid, prec, form); None clears it."""
+        cell = make_cell(n, L)
+        c = config_from_dict(cfg) if cfg is not None else None
+        _check(load().fx_vx_set_config(self.h, C.byref(cell), PREC[prec], 1 if phi_is_psi else 0,
+                                       C.byref(c) if c is not None else None))
+
+    def get_vx_config(self, *, n, L=1.0, prec="fp32acc64", phi_is_psi=False):
+        """(config dict, is_set) stored for (grid, prec, form)."""
+        cell = make_cell(n, L)
+        c = FxVxConfig()
+        is_set = C.c_int32()
+        _check(load().fx_vx_get_config(self.h, C.byref(cell), PREC[prec], 1 if phi_is_psi else 0, C.byref(c),
+                                       C.byref(is_set)))
+        return config_to_dict(c), bool(is_set.value)
+
     # -- ACE ------------------------------------------------------------------
     def build_ace(self, psi, *, n, L, kernel="hse", omega=0.106, scale=1.0, vx_prec="fp64",
                   ace_prec="ace_fp64", stream=None):
@@ -353,8 +413,9 @@ class Server:
             pass
 
 
-def debug_host_pair(psi_j, phi_k, *, n, L, kernel="hse", omega=0.106, scale=1.0, prec=0):
-    """Run the library's pass code on the host for one pair (prec 0: FP64, 1: FP32)."""
+def debug_host_pair(psi_j, phi_k, *, n, L, kernel="hse", omega=0.106, scale=1.0, prec=0, radix=None):
+    """Run the library's pass code on the host for one pair (prec 0: FP64, 1: FP32), optionally
+    with a radix schedule per axis (3 rows, stages in order, [] or zeros for the default)."""
     import numpy as np
 
     cell = make_cell(n, L)
@@ -362,5 +423,23 @@ def debug_host_pair(psi_j, phi_k, *, n, L, kernel="hse", omega=0.106, scale=1.0,
     a = np.ascontiguousarray(psi_j, dtype=np.complex128)
     b = np.ascontiguousarray(phi_k, dtype=np.complex128)
     v = np.empty_like(a)
-    _check(load().fx_debug_host_pair(C.byref(cell), C.byref(kern), int(prec), a.ctypes.data, b.ctypes.data, v.ctypes.data))
+    if radix is None:
+        _check(load().fx_debug_host_pair(C.byref(cell), C.byref(kern), int(prec), a.ctypes.data, b.ctypes.data,
+                                         v.ctypes.data))
+    else:
+        r = np.zeros((3, 4), dtype=np.int32)
+        for ax, row in enumerate(radix):
+            r[ax, :len(row)] = row
+        _check(load().fx_debug_host_pair_plan(C.byref(cell), C.byref(kern), int(prec), r.ctypes.data, a.ctypes.data,
+                                              b.ctypes.data, v.ctypes.data))
     return v
+
+
+def debug_axis_plans(n, max_plans=6):
+    """The radix schedules the autotuner considers for edge n (default first), as lists."""
+    import numpy as np
+
+    out = np.zeros((max_plans, 4), dtype=np.int32)
+    cnt = C.c_int32()
+    _check(load().fx_debug_axis_plans(int(n), int(max_plans), out.ctypes.data, C.byref(cnt)))
+    return [[int(r) for r in row if r] for row in out[:cnt.value]]

@@ -72,3 +72,40 @@ def test_bad_kernel_rejected():
     with pytest.raises(F.FockError) as ei:
         F.debug_host_pair(a, a, n=2, L=(1.0, 0.0, 1.0))
     assert ei.value.status == F.FX_ERR_INVALID
+
+
+def test_axis_plan_enumeration():
+    """Every schedule the autotuner may pick multiplies to its edge, uses the radix set,
+    has at most three stages, and the default (balanced two-stage where possible) comes first."""
+    rad = {2, 3, 4, 6, 8, 9, 12}
+    for n in [2, 3, 4, 6, 8, 9, 12, 16, 18, 24, 27, 32, 36, 48, 54, 64, 72, 81, 96]:
+        plans = F.debug_axis_plans(n)
+        assert plans, n
+        for p in plans:
+            assert int(np.prod(p)) == n and set(p) <= rad and 1 <= len(p) <= 3, (n, p)
+        assert len({tuple(p) for p in plans}) == len(plans)
+    assert F.debug_axis_plans(96)[0] == [12, 8] and F.debug_axis_plans(24)[0] == [6, 4]
+
+
+@pytest.mark.parametrize("n3", [(8, 12, 16), (24, 36, 9), (96, 4, 2), (2, 72, 3)])
+def test_every_radix_schedule_matches_oracle(n3):
+    """The pass code with each enumerated radix schedule (one axis varied at a time) equals the oracle."""
+    L3 = (3.0, 4.5, 5.0)
+    a = synth.random_grid_vectors(3, n3, 1)[0]
+    b = synth.random_grid_vectors(4, n3, 1)[0]
+    K = oracle.kernel_table(n3, L3, "hse", 0.3)
+    ref = -oracle.pair_potential(a, b, K) / np.prod(L3)
+    for ax in range(3):
+        for p in F.debug_axis_plans(n3[ax]):
+            radix = [[], [], []]
+            radix[ax] = p
+            got = F.debug_host_pair(a, b, n=n3, L=L3, kernel="hse", omega=0.3, radix=radix)
+            assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max(), (ax, p)
+
+
+def test_invalid_radix_schedules_rejected():
+    a = np.zeros(8 * 6 * 4, dtype=complex)
+    for bad in ([[5], [], []], [[2, 2], [], []], [[], [6, 2], []], [[8, 1], [], []], [[16], [], []]):
+        with pytest.raises(F.FockError) as ei:
+            F.debug_host_pair(a, a, n=(8, 6, 4), L=1.0, radix=bad)
+        assert ei.value.status == F.FX_ERR_INVALID, bad
