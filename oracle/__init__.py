@@ -15,10 +15,13 @@ from .fock import (  # noqa: F401
     apply_ace,
     apply_vx,
     build_ace,
+    density,
     exchange_energy,
     g2_grid,
     kernel_table,
+    orthonormalize,
     pair_potential,
+    pt_residual,
     vx_dense_matrix,
     volume,
 )

@@ -1,4 +1,5 @@
-"""Plain FP64 definitions of V_X, the exchange energy and ACE (test infrastructure).
+"""Plain FP64 definitions of V_X, the exchange energy, ACE, and the end-of-step
+operations (PT residual, Cholesky-QR re-orthonormalisation, density) (test infrastructure).
 
 Conventions (readings of the paper, each listed in the design notes):
   * An orbital is a Euclidean-normalised grid vector on an nx*ny*nz grid of a
@@ -40,6 +41,11 @@ PINS = {
     "exchange_energy": "planewave closed form of the trace",
     "build_ace": "planewave closed form of M and L; K_ACE psi_i = W_i; tr M = -||L||_F^2",
     "apply_ace": "exactness on span(Psi); annihilation of the orthogonal complement; Hermitian NSD rank <= N",
+    "pt_residual": "planewave eigenbasis (H Psi = Psi Lambda gives R = Psi - Psi_half); projections onto span(Psi) "
+                   "(zero) and onto its complement from a complete Householder QR ((i dt/2) Q_perp^H H Psi); gauge "
+                   "covariance",
+    "orthonormalize": "equals the Householder QR factor with a positive real diagonal; Q^H Q = I; span preserved",
+    "density": "planewave orbitals give the constant N/N_r; gauge invariance under unitary mixing; sum rule",
 }
 
 
@@ -187,3 +193,47 @@ def vx_dense_matrix(psi, n, L, kind="coulomb", omega=0.106, scale=1.0):
     eye = np.eye(nr, dtype=np.complex128).reshape(nr, nz, ny, nx)
     cols = apply_vx(psi, eye, n, L, kind, omega, scale)
     return cols.reshape(nr, nr).T
+
+
+def _cols(a):
+    """Orbitals (N, ...) as the columns of an N_r x N matrix."""
+    a = np.asarray(a)
+    return a.reshape(a.shape[0], -1).T
+
+
+def pt_residual(psi_f, hpsi_f, psi_half, dt):
+    """Residual R_f of the PT-CN fixed point (the residual algorithm of Sec. 3.3, for the PT equation of Sec. 2).
+
+    S = Psi_f^H (H_f Psi_f); Psi_temp = Psi_f S; R_f = Psi_f + (i dt/2)(H_f Psi_f - Psi_temp) - Psi_{n+1/2}.
+    All three inputs are orbital blocks of the same shape (N, ...); so is the result.
+    """
+    X = _cols(psi_f).astype(np.complex128)
+    HX = _cols(hpsi_f).astype(np.complex128)
+    Xh = _cols(psi_half).astype(np.complex128)
+    S = X.conj().T @ HX
+    T = X @ S
+    R = X + 0.5j * dt * (HX - T) - Xh
+    return R.T.reshape(np.shape(psi_f))
+
+
+def orthonormalize(psi):
+    """Re-orthonormalisation at the end of a time step (Sec. 3.4): overlap S = Psi^H Psi, Cholesky
+    S = L L^H (L lower, real positive diagonal), then Psi L^{-H}."""
+    X = _cols(psi).astype(np.complex128)
+    S = X.conj().T @ X
+    S = 0.5 * (S + S.conj().T)
+    L = np.linalg.cholesky(S)
+    Z = _sla.solve_triangular(L, X.conj().T, lower=True)  # L^{-1} X^H = (X L^{-H})^H
+    return Z.conj().reshape(np.shape(psi))
+
+
+def density(psi, occ=None):
+    """Electron density rho(r) = sum_i f_i |psi_i(r)|^2 (Sec. 3.4, where every f_i = 1)."""
+    a = np.asarray(psi)
+    X = a.reshape(a.shape[0], -1).astype(np.complex128)
+    f = np.ones(a.shape[0]) if occ is None else np.asarray(occ, dtype=np.float64)
+    rho = np.zeros(X.shape[1])
+    for i in range(X.shape[0]):
+        rho += f[i] * (X[i].real ** 2 + X[i].imag ** 2)
+    return rho.reshape(a.shape[1:])
+

@@ -354,6 +354,126 @@ def check_ace_identities(orc, kind="hse", seed=7):
     return float(max(errs))
 
 
+def _planewave_block(n3, L3, mvecs):
+    """Orthonormal planewave orbitals e^{i G.r}/sqrt(N_r), rows (N, nz, ny, nx); written here, not in synth."""
+    nx, ny, nz = n3
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    nr = nx * ny * nz
+    return np.array([np.exp(2j * np.pi * (m[0] * x / nx + m[1] * y / ny + m[2] * z / nz)) / np.sqrt(nr)
+                     for m in mvecs])
+
+
+def _random_hermitian(rng, n):
+    a = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    return 0.5 * (a + a.conj().T)
+
+
+def check_residual_eigenbasis(orc, n3=(6, 4, 5), L3=(4.0, 3.0, 3.5), omega=0.3, dt=0.37, seed=8):
+    """Planewaves are eigenvectors of V_X (eigenvalue from the closed form of Eq. applyVX): then
+    H Psi - Psi (Psi^H H Psi) = 0 and the residual reduces to Psi - Psi_half for any dt."""
+    mvecs = [(0, 0, 0), (1, 0, 0), (0, -1, 2), (2, 1, -1)]
+    psi = _planewave_block(n3, L3, mvecs)
+    lam = []
+    for mk in mvecs:
+        acc = 0.0
+        for mj in mvecs:
+            d = [_wrap(mk[a] - mj[a], n3[a]) for a in range(3)]
+            g2 = sum((2 * np.pi * d[a] / L3[a]) ** 2 for a in range(3))
+            acc += _kernel_formula("hse", np.array([g2]), omega)[0]
+        lam.append(-acc / np.prod(L3))
+    hpsi = np.array(lam)[:, None, None, None] * psi
+    rng = np.random.default_rng(seed)
+    half = rng.standard_normal(psi.shape) + 1j * rng.standard_normal(psi.shape)
+    r = orc.pt_residual(psi, hpsi, half, dt)
+    return float(np.abs(r - (psi - half)).max())
+
+
+def _residual_case(seed, nr=40, n=5):
+    rng = np.random.default_rng(seed)
+    x, _ = np.linalg.qr(rng.standard_normal((nr, n)) + 1j * rng.standard_normal((nr, n)))
+    h = _random_hermitian(rng, nr)
+    half = rng.standard_normal((nr, n)) + 1j * rng.standard_normal((nr, n))
+    return x, h, half
+
+
+def check_residual_projections(orc, dt=0.29, seed=9):
+    """R - Psi + Psi_half is fixed by its two projections: onto span(Psi) it vanishes (S is the
+    overlap Psi^H H Psi), onto the orthogonal complement (a basis from a complete Householder QR)
+    it equals (i dt/2) Q_perp^H (H Psi).  Sensitive to the sign and size of the i dt/2 factor."""
+    x, h, half = _residual_case(seed)
+    hx = h @ x
+    r = orc.pt_residual(x.T, hx.T, half.T, dt).T
+    d = r - x + half
+    q, _ = np.linalg.qr(x, mode="complete")
+    qp = q[:, x.shape[1]:]
+    e1 = np.abs(x.conj().T @ d).max()
+    e2 = np.abs(qp.conj().T @ d - 0.5j * dt * (qp.conj().T @ hx)).max()
+    return float(max(e1, e2) / max(1.0, np.abs(hx).max()))
+
+
+def check_residual_gauge(orc, dt=0.41, seed=10):
+    """Gauge covariance: Psi -> Psi U (U unitary, H Psi and Psi_half transformed alike) gives R U."""
+    x, h, half = _residual_case(seed)
+    rng = np.random.default_rng(seed + 1)
+    u, _ = np.linalg.qr(rng.standard_normal((x.shape[1],) * 2) + 1j * rng.standard_normal((x.shape[1],) * 2))
+    r = orc.pt_residual(x.T, (h @ x).T, half.T, dt).T
+    ru = orc.pt_residual((x @ u).T, (h @ x @ u).T, (half @ u).T, dt).T
+    return float(np.abs(ru - r @ u).max())
+
+
+def check_cholqr_vs_householder(orc, seed=11, nr=60, n=7):
+    """Cholesky-QR of a full-rank block equals its Householder QR factor Q with the phases that make
+    diag(R) real positive (both are the unique such factorisation)."""
+    rng = np.random.default_rng(seed)
+    a = rng.standard_normal((nr, n)) + 1j * rng.standard_normal((nr, n))
+    a[:, 1] += 0.5 * a[:, 0]  # not orthogonal, still well conditioned
+    q, rr = np.linalg.qr(a)
+    ph = np.diag(rr) / np.abs(np.diag(rr))
+    q = q * ph[None, :]
+    got = orc.orthonormalize(a.T).T
+    return float(np.abs(got - q).max())
+
+
+def check_cholqr_properties(orc, seed=12, n3=(4, 5, 3), n=6):
+    """Q^H Q = I and span preserved: the projector Q Q^H reproduces the input block."""
+    rng = np.random.default_rng(seed)
+    a = rng.standard_normal((n,) + n3[::-1]) + 1j * rng.standard_normal((n,) + n3[::-1])
+    q = orc.orthonormalize(a)
+    Q = q.reshape(n, -1).T
+    A = a.reshape(n, -1).T
+    e1 = np.abs(Q.conj().T @ Q - np.eye(n)).max()
+    e2 = np.abs(Q @ (Q.conj().T @ A) - A).max() / np.abs(A).max()
+    return float(max(e1, e2))
+
+
+def check_density_planewave(orc, n3=(6, 4, 5), L3=(4.0, 3.0, 3.5)):
+    """|e^{iG.r}|^2 / N_r is the same at every point: the density of N planewaves is N / N_r."""
+    mvecs = [(0, 0, 0), (1, 0, 0), (0, -1, 2), (2, 1, -1), (-3, 2, 2)]
+    psi = _planewave_block(n3, L3, mvecs)
+    rho = orc.density(psi)
+    nr = int(np.prod(n3))
+    return float(np.abs(rho - len(mvecs) / nr).max() * nr)
+
+
+def check_density_gauge_and_sum(orc, seed=13, n3=(5, 4, 6), n=4):
+    """Unit occupations: rho is invariant under unitary mixing of the orbitals and sums to N for an
+    orthonormal block; weights: each orbital counts with its occupation."""
+    rng = np.random.default_rng(seed)
+    a = rng.standard_normal((int(np.prod(n3)), n)) + 1j * rng.standard_normal((int(np.prod(n3)), n))
+    x, _ = np.linalg.qr(a)
+    u, _ = np.linalg.qr(rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n)))
+    psi = x.T.reshape((n,) + n3[::-1])
+    psiu = (x @ u).T.reshape((n,) + n3[::-1])
+    r1, r2 = orc.density(psi), orc.density(psiu)
+    e1 = np.abs(r1 - r2).max() / np.abs(r1).max()
+    e2 = abs(r1.sum() - n) / n
+    occ = np.array([2.0, 0.5, 0.0, 1.0])
+    rw = orc.density(psi, occ)
+    e3 = abs(rw.sum() - occ.sum()) / occ.sum()
+    e4 = np.abs(rw - sum(occ[i] * np.abs(psi[i]) ** 2 for i in range(n))).max() / np.abs(rw).max()
+    return float(max(e1, e2, e3, e4))
+
+
 # name -> (callable, bound)
 ALL = {
     "naive_dft": (check_naive_dft, 1e-12),
@@ -377,4 +497,11 @@ ALL = {
     "exchange_energy": (check_exchange_energy, 1e-12),
     "ace_planewave": (check_ace_planewave, 1e-12),
     "ace_identities": (check_ace_identities, 1e-10),
+    "residual_eigenbasis": (check_residual_eigenbasis, 1e-13),
+    "residual_projections": (check_residual_projections, 1e-12),
+    "residual_gauge": (check_residual_gauge, 1e-12),
+    "cholqr_vs_householder": (check_cholqr_vs_householder, 1e-12),
+    "cholqr_properties": (check_cholqr_properties, 1e-12),
+    "density_planewave": (check_density_planewave, 1e-12),
+    "density_gauge_and_sum": (check_density_gauge_and_sum, 1e-12),
 }

@@ -33,6 +33,18 @@ MUTATIONS = {
     "ace_apply_sign": ("Y = -(X @ (X.conj().T @ F))", "Y = X @ (X.conj().T @ F)"),
     "ace_apply_transpose": ("Y = -(X @ (X.conj().T @ F))", "Y = -(X @ (X.T @ F))"),
     "ace_unsymmetrised_upper": ("L = np.linalg.cholesky(-M)", "L = np.linalg.cholesky(-M).conj().T"),
+    "residual_sign_of_i": ("R = X + 0.5j * dt * (HX - T) - Xh", "R = X - 0.5j * dt * (HX - T) - Xh"),
+    "residual_full_dt": ("R = X + 0.5j * dt * (HX - T) - Xh", "R = X + 1j * dt * (HX - T) - Xh"),
+    "residual_overlap_without_conj": ("S = X.conj().T @ HX\n    T = X @ S", "S = X.T @ HX\n    T = X @ S"),
+    "residual_rotation_transposed": ("T = X @ S\n", "T = X @ S.T\n"),
+    "residual_half_added": ("R = X + 0.5j * dt * (HX - T) - Xh", "R = X + 0.5j * dt * (HX - T) + Xh"),
+    "cholqr_upper_factor": ("Z = _sla.solve_triangular(L, X.conj().T, lower=True)",
+                            "Z = _sla.solve_triangular(L.conj().T, X.conj().T, lower=False)"),
+    "cholqr_missing_conj": ("return Z.conj().reshape(np.shape(psi))", "return Z.reshape(np.shape(psi))"),
+    "density_square_not_modulus": ("rho += f[i] * (X[i].real ** 2 + X[i].imag ** 2)",
+                                   "rho += f[i] * (X[i].real ** 2 - X[i].imag ** 2)"),
+    "density_ignores_occupation": ("rho += f[i] * (X[i].real ** 2 + X[i].imag ** 2)",
+                                   "rho += (X[i].real ** 2 + X[i].imag ** 2)"),
 }
 
 
