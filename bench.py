@@ -79,7 +79,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU oracle budget (0 = skip)")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="vx leg: skip the launch-configuration autotuner (run the automatic configuration)")
-    ap.add_argument("--leg", default="vx", choices=["vx", "ace", "serve", "copy"],
+    ap.add_argument("--leg", default="vx", choices=["vx", "ace", "serve", "copy", "step"],
                     help="vx: V_X apply (default); ace: ACE build + apply at 96^3, N = R = 1024; serve: serving replay")
     ap.add_argument("--requests", type=int, default=12000, help="serve leg: measured requests")
     ap.add_argument("--warm-requests", type=int, default=1000, help="serve leg: warm-up requests")
@@ -94,6 +94,8 @@ def main():
         return bench_ace(args)
     if args.leg == "serve":
         return bench_serve(args)
+    if args.leg == "step":
+        return bench_step(args)
 
     import numpy as np
     import torch
@@ -340,6 +342,75 @@ def bench_ace(args):
     print(json.dumps(result))
 
 
+def bench_step(args):
+    """End-of-step operations at the 96^3, N = 1024 shape: PT residual (H Psi given), Cholesky-QR
+    re-orthonormalisation and density, complex64 blocks with FP64 arithmetic."""
+    import math
+
+    import torch
+
+    import synth
+    from paper_1905_01348_amd import Context, fock
+
+    w = synth.workload("cfg2")
+    n, L, N = w["n"], w["L"], w["N"]
+    nr = n ** 3
+    g = torch.Generator(device="cuda:0")
+    blocks = []
+    for seed in (7, 8, 9):  # Psi, H Psi, Psi_{n+1/2}: seeded synthetic blocks drawn on the device
+        g.manual_seed(seed)
+        blocks.append(torch.randn((N, n, n, n), dtype=torch.complex64, device="cuda:0", generator=g) / math.sqrt(nr))
+    P, H, Hf = blocks
+    R = torch.empty_like(P)
+    rho = torch.empty((n, n, n), dtype=torch.float64, device="cuda:0")
+    ctx = Context(0)
+    ops = {
+        "pt_residual": lambda: ctx.pt_residual(P, Hf, n=n, L=L, hpsi=H, dt=0.05, out=R),
+        "orthonormalize": lambda: ctx.orthonormalize(P),
+        "density": lambda: ctx.density(P, out=rho),
+    }
+    flops = {"pt_residual": 16.0 * nr * N * N, "orthonormalize": 16.0 * nr * N * N, "density": 0.0}
+    nbytes = {"density": 8.0 * nr * N + 8.0 * nr}
+    res = {}
+    for name, fn in ops.items():
+        fn()
+        torch.cuda.synchronize()
+        ctx.prof_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / args.steps
+        kern = {}
+        for kname in ("gemm_cn", "gemm_nn", "reduce", "linalg", "convert"):
+            cnt, ms, work = ctx.prof_read(fock.KERNEL_IDS[kname])
+            if cnt:
+                kern[kname] = {"launches": cnt, "avg_ms": ms / cnt, "rate_TFLOPs": work / (ms * 1e-3) / 1e12}
+        ctx.prof_enable(False)
+        e = {"ms": 1e3 * el, "kernels": kern}
+        if flops[name]:
+            e["TFLOPs"] = flops[name] / el / 1e12
+            e["roofline"] = {"bound": "mfma", "achieved": e["TFLOPs"], "peak": 78.6, "unit": "TFLOP/s",
+                             "frac": e["TFLOPs"] / 78.6}
+        else:
+            e["GBps"] = nbytes[name] / el / 1e9
+            e["roofline"] = {"bound": "hbm", "achieved": e["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": e["GBps"] / HBM_PEAK_GBS}
+        res[name] = e
+        log(f"[bench-step] {name}: {1e3 * el:.1f} ms")
+    total = sum(v["ms"] for v in res.values())
+    result = {
+        "metric": "end-of-step operations, ms per step", "value": total, "unit": "ms", "n_gpus": 1,
+        "steps": args.steps, "warmup": 1, "ms_per_step": total, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"PT residual + Cholesky-QR + density, {n}^3 grid, N = {N}, complex64 blocks, "
+                               "FP64 arithmetic"},
+        "ops": res,
+    }
+    ctx.close()
+    print(json.dumps(result))
+
+
 def bench_serve(args):
     """Serving replay: Poisson arrivals (200/s) over 12 resident trajectories of three cell sizes."""
     import numpy as np
@@ -351,7 +422,8 @@ def bench_serve(args):
 
     classes = {0: "serveA", 1: "serveB", 2: "serveC"}
     ctx = Context(0)
-    srv = Server(ctx, max_slots=8, n_streams=4, max_batch_pairs=1 << 15, hbm_budget_bytes=64 << 30)
+    srv = Server(ctx, max_slots=8, n_streams=4, max_batch_pairs=1 << 15, hbm_budget_bytes=64 << 30,
+                 autotune=args.autotune)
     by_class = {}
     t0 = time.perf_counter()
     for c, name in classes.items():
@@ -370,6 +442,7 @@ def bench_serve(args):
 
     def run(seed, nreq):
         reqs = poisson_requests(seed, nreq, 200.0, by_class, mix, block=8)
+        run.reqs = reqs
         outs = {}
         for r in reqs:
             wl = synth.workload(classes[r["traj"] // 10])
@@ -384,6 +457,16 @@ def bench_serve(args):
         run(4, args.warm_requests)
     st, lat, rep = run(5, args.requests)
     ok = sum(1 for s in st if s == 0)
+    # latency by cell class and operation (nearest-rank percentiles)
+    names = {0: "24^3 N=16", 1: "48^3 N=128", 2: "72^3 N=432"}
+    breakdown = {}
+    for c in classes:
+        for op, opn in ((0, "vx"), (1, "ace")):
+            ls = sorted(l for r, s_, l in zip(run.reqs, st, lat) if s_ == 0 and r["traj"] // 10 == c and r["op"] == op)
+            if ls:
+                pick = lambda q: ls[min(len(ls) - 1, max(0, int(np.ceil(q * len(ls))) - 1))]
+                breakdown[f"{names[c]} {opn}"] = {"n": len(ls), "p50_ms": pick(0.5), "p99_ms": pick(0.99),
+                                                  "mean_ms": float(np.mean(ls))}
     result = {
         "metric": "serving p99 latency",
         "value": rep["p99_ms"], "unit": "ms", "n_gpus": 1, "steps": args.requests, "warmup": args.warm_requests,
@@ -392,7 +475,7 @@ def bench_serve(args):
         "config": {"workload": "Poisson 200 req/s; 50/35/15% classes 24^3 N=16, 48^3 N=128, 72^3 N=432; "
                                "V_X or ACE on blocks of 8 orbitals; complex64; HSE",
                    "register_s": t_reg},
-        "report": rep, "ok": ok, "offered_load": rep["busy_frac"],
+        "report": rep, "ok": ok, "offered_load": rep["busy_frac"], "by_class": breakdown,
     }
     srv.close()
     ctx.close()

@@ -253,6 +253,37 @@ fx_status fx_ace_shape(const fx_ace* ace, int32_t* n, int64_t* n_r);
 fx_status fx_ace_free(fx_ace* ace);
 
 /*
+ * End-of-step operations of PT-CN (all arithmetic FP64; complex64 blocks are
+ * widened on input and rounded on output).
+ *
+ * fx_pt_residual: the residual of the PT-CN fixed point (the residual
+ *   algorithm of Sec. 3.3, for the parallel-transport equation of Sec. 2):
+ *     S = Psi^H (H Psi),  R = Psi + (i dt/2)(H Psi - Psi S) - Psi_half.
+ *   psi, hpsi, psi_half: device blocks of n columns, stride ld, dtype; hpsi
+ *   NULL means H = V_X[psi] (computed by the pair path with vx_prec; kernel
+ *   then required).  r_out: device, n columns, stride ld_r, dtype; must not
+ *   overlap the inputs.  s_out: nullable device n x n complex128
+ *   column-major, receives S.  The cell gives N_r (and the grid when hpsi is
+ *   NULL).  Errors: FX_ERR_INVALID, FX_ERR_UNSUPPORTED, FX_ERR_OOM,
+ *   FX_ERR_DEVICE.
+ *
+ * fx_orthonormalize: Cholesky-QR re-orthonormalisation in place (Sec. 3.4):
+ *   S = Psi^H Psi, S = L L^H, Psi <- Psi L^{-H}.  Waits on `stream` once (the
+ *   Cholesky status); FX_ERR_NOT_POSDEF if the columns are linearly dependent.
+ *
+ * fx_density: rho(r) = sum_i f_i |psi_i(r)|^2 (Sec. 3.4), summed over i in
+ *   ascending order in FP64.  occ: nullable device array of n doubles (all 1
+ *   if NULL); rho: device array of nr doubles, overwritten.
+ */
+fx_status fx_pt_residual(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* kernel, const void* psi,
+                         const void* hpsi, const void* psi_half, int32_t n, int64_t ld, fx_dtype dtype,
+                         double dt, fx_prec vx_prec, void* r_out, int64_t ld_r, void* s_out, void* stream);
+fx_status fx_orthonormalize(fx_ctx* ctx, void* psi, int32_t n, int64_t ld, int64_t nr, fx_dtype dtype,
+                            void* stream);
+fx_status fx_density(fx_ctx* ctx, const void* psi, int32_t n, int64_t ld, int64_t nr, fx_dtype dtype,
+                     const double* occ, double* rho, void* stream);
+
+/*
  * Serving: continuous batching of V_X / ACE requests over resident orbitals.
  *
  * fx_serve_create: max_slots requests may be in flight on the device at once,
@@ -275,6 +306,11 @@ typedef struct fx_serve_cfg {
   int32_t n_streams;
   int32_t max_batch_pairs;
   size_t hbm_budget_bytes;
+  int32_t autotune;   /* nonzero: fx_serve_register runs fx_vx_autotune for the trajectory's
+                         grid and V_X precision (requests of autotune_targets targets against
+                         its n orbitals) and for its ACE build (phi == psi), unless the context
+                         already holds configurations for them */
+  int32_t autotune_targets; /* targets per V_X request the tuning assumes (0 = 8) */
 } fx_serve_cfg;
 
 typedef struct fx_request {

@@ -163,6 +163,15 @@ fx_status fx_serve_register(fx_server* srv, int32_t traj, const fx_cell* cell, c
   FX_TRY(ctx_alloc(ctx, t.psi_bytes, &t.psi));
   const int64_t cb = (int64_t)dtype_size(dtype) * nr;
   fx_status s = copy_cols(psi, ld * (int64_t)dtype_size(dtype), t.psi, cb, cb, n, nullptr);
+  if (s == FX_OK && srv->cfg.autotune) {
+    // configurations for this grid's requests (blocks of targets against all
+    // n orbitals) and for the ACE build (phi == psi), unless already held
+    const int nt = std::min(n, srv->cfg.autotune_targets > 0 ? srv->cfg.autotune_targets : 8);
+    if (!ctx->vx_tuning.count(vx_tune_key(cell, vx_prec, false)))
+      s = vx_autotune_impl(ctx, cell, kernel, n, nt, false, vx_prec, nullptr, nullptr, nullptr);
+    if (s == FX_OK && !ctx->vx_tuning.count(vx_tune_key(cell, vx_prec, true)))
+      s = vx_autotune_impl(ctx, cell, kernel, n, n, true, vx_prec, nullptr, nullptr, nullptr);
+  }
   if (s == FX_OK) {
     s = ace_build_impl(ctx, &ctx->ws, cell, kernel, t.psi, n, nr, dtype, vx_prec, ace_prec, nullptr, &t.ace,
                        nullptr);

@@ -183,7 +183,7 @@ static fx_status autotune(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* ker
   cur.kernels = spec ? 1 : 2;
   cur.a_prefetch = 0;
   cur.b_variant = spec ? 1 : 0;
-  cur.c_variant = spec ? 1 : 0;
+  cur.c_variant = spec ? (cell->n[0] == 96 ? 2 : 1) : 0;
   rs = trial(cur);
   if (rs == FX_OK && best == std::numeric_limits<double>::infinity()) {
     cleanup();
@@ -209,7 +209,7 @@ static fx_status autotune(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* ker
     }
     if (rs == FX_OK) {
       fx_vx_config c = cur;
-      c.c_variant = 2;
+      c.c_variant = 3 - cur.c_variant;
       rs = trial(c);
     }
   }
@@ -257,6 +257,27 @@ static fx_status autotune(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* ker
   return FX_OK;
 }
 
+fx_status vx_autotune_impl(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* kernel, int n_psi, int n_phi,
+                           bool square, fx_prec prec, hipStream_t st, fx_vx_config* best, double* ms_per_kpair) {
+  // a stored configuration for this key must not fill in the candidates'
+  // automatic fields; it comes back if tuning fails
+  const auto key = vx_tune_key(cell, prec, square);
+  auto it = ctx->vx_tuning.find(key);
+  const bool had = it != ctx->vx_tuning.end();
+  fx_vx_config old{};
+  if (had) {
+    old = it->second;
+    ctx->vx_tuning.erase(it);
+  }
+  // probe launches are not the caller's work: keep them out of the timing
+  const bool prof = ctx->prof;
+  ctx->prof = false;
+  fx_status s = autotune(ctx, cell, kernel, n_psi, n_phi, square, prec, st, best, ms_per_kpair);
+  ctx->prof = prof;
+  if (s != FX_OK && had) ctx->vx_tuning[key] = old;
+  return s;
+}
+
 }  // namespace fx
 
 using namespace fx;
@@ -278,23 +299,7 @@ fx_status fx_vx_autotune(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* kern
   hipStream_t st = (hipStream_t)stream;
   FX_TRY(note_capture(ctx, st));
   if (ctx->capturing) FX_FAIL(FX_ERR_INVALID, "fx_vx_autotune waits on its stream and cannot be captured");
-  // a stored configuration for this key must not fill in the candidates'
-  // automatic fields; it comes back if tuning fails
-  const auto key = vx_tune_key(cell, prec, phi_is_psi != 0);
-  auto it = ctx->vx_tuning.find(key);
-  const bool had = it != ctx->vx_tuning.end();
-  fx_vx_config old{};
-  if (had) {
-    old = it->second;
-    ctx->vx_tuning.erase(it);
-  }
-  // probe launches are not the caller's work: keep them out of the timing
-  const bool prof = ctx->prof;
-  ctx->prof = false;
-  fx_status s = autotune(ctx, cell, kernel, n_psi, n_phi, phi_is_psi != 0, prec, st, best, best_ms_per_kpair);
-  ctx->prof = prof;
-  if (s != FX_OK && had) ctx->vx_tuning[key] = old;
-  return s;
+  return vx_autotune_impl(ctx, cell, kernel, n_psi, n_phi, phi_is_psi != 0, prec, st, best, best_ms_per_kpair);
 }
 
 fx_status fx_vx_set_config(fx_ctx* ctx, const fx_cell* cell, fx_prec prec, int32_t phi_is_psi,

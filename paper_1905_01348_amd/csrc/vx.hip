@@ -358,6 +358,15 @@ static bool pick_ept(int elems, int max_thr, int* ept, int* nthr) {
     default: FX_FAIL(FX_ERR_UNSUPPORTED, "no kernel for %d elements per thread", EPT_VAR); \
   }
 
+// Plane-inverse threads of the specialised kernels: the larger count (fewer
+// accumulators per thread, 12 waves per CU instead of 8) is the automatic
+// choice at 96^3, where it measured faster (3.34 vs 3.39 ms per launch of
+// 1170 pairs); elsewhere the autotuner decides.
+static int ct_c_variant(const VxArgs& a) {
+  if (a.c_var == 1 || a.c_var == 2) return a.c_var;
+  return a.cell->n[0] == 96 ? 2 : 1;
+}
+
 // Halved apply for phi == psi (all N targets): each unordered pair {j, k} is
 // solved once, as (min, max), since v_kj = conj(v_jk) for a real, even kernel.
 // Orbitals are cut into blocks of B; block pairs (J <= K) run in ascending
@@ -404,7 +413,7 @@ static fx_status run_halved(fx_ctx* ctx, Workspace* ws, const VxArgs& a, const G
       const int tri = J == K;
       const int npairs = tri ? jb * (jb + 1) / 2 : jb * kb;
       CtBatch<T> cb{psi, ld_psi, psi, ld_psi, reinterpret_cast<cpx<T>*>(work), j0, jb, k0, kb, npairs, tw, kf,
-                    tb->fold[0], tri, a.a_pipe > 0 ? 1 : 0, a.b_var == 2 ? 2 : 1, a.c_var == 2 ? 2 : 1};
+                    tb->fold[0], tri, a.a_pipe > 0 ? 1 : 0, a.b_var == 2 ? 2 : 1, ct_c_variant(a)};
       const double vol = (double)npairs * nr * sz;
       int slot;
       FX_TRY(prof_begin(ctx, st, FX_K_VX_PLANE_FWD, 3.0 * vol, &slot));
@@ -530,7 +539,7 @@ static fx_status run_batches(fx_ctx* ctx, Workspace* ws, const VxArgs& a, const 
       int slot;
       if (use_ct) {
         CtBatch<T> cb{psi, ld_psi, phi, ld_phi, reinterpret_cast<cpx<T>*>(work), j0, jb, k0, kb, npairs, twx, kf,
-                      tb->fold[0], 0, a.a_pipe > 0 ? 1 : 0, a.b_var == 2 ? 2 : 1, a.c_var == 2 ? 2 : 1};
+                      tb->fold[0], 0, a.a_pipe > 0 ? 1 : 0, a.b_var == 2 ? 2 : 1, ct_c_variant(a)};
         CtAcc<A> ca{acc, ld_acc, first, a.out, a.ld_out, out_c64 ? 1 : 0, last, a.pipe};
         FX_TRY(prof_begin(ctx, st, FX_K_VX_PLANE_FWD, 3.0 * vol, &slot));
         FX_TRY(ct_pass_a<T>(ctx, st, g.nx, cb));

@@ -44,6 +44,9 @@ std::array<int, 5> vx_tune_key(const fx_cell* cell, fx_prec prec, bool square);
 // Fill the automatic fields of `a` from the environment (FX_VX_* overrides,
 // for experiments), then from the context's tuned configuration.
 void resolve_vx_config(fx_ctx* ctx, VxArgs* a);
+// The autotuner (tune.hip): tunes and stores the configuration of one shape.
+fx_status vx_autotune_impl(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* kernel, int n_psi, int n_phi,
+                           bool square, fx_prec prec, hipStream_t st, fx_vx_config* best, double* ms_per_kpair);
 // Whether a call is the phi == psi form (all targets are the orbitals).
 inline bool vx_square_form(const VxArgs& a) {
   return a.phi == a.psi && a.ld_phi == a.ld_psi && a.n_phi == a.n_psi;

@@ -34,6 +34,43 @@ FX_HD void pair_of(int p, int nj, int tri, int* jj, int* kk) {
 
 FX_HD int plane_of(int jj, int kk, int nj, int tri) { return tri ? kk * (kk + 1) / 2 + jj : kk * nj + jj; }
 
+// Work of a persistent plane kernel: `units` (pairs, or targets) x N planes.
+// Workgroups are dispatched round-robin over the XCDs, so with a grid that is
+// a multiple of the XCD count workgroup b runs on XCD b % kXcds.  Each XCD
+// takes a contiguous chunk of the units and walks it z-major: the workgroups
+// of one XCD work on the same z at the same time and find that plane's input
+// data (orbital and target planes in pass A, orbital planes in pass C) in
+// their shared L2 instead of reading it again from HBM.
+constexpr int kXcds = 8;
+
+struct ItemMap {
+  int u_lo, u_n, first, step, total;
+  FX_HD void at(int li, int* unit, int* z) const {
+    *z = li / u_n;
+    *unit = u_lo + (li - *z * u_n);
+  }
+};
+
+template <int N>
+__device__ inline ItemMap item_map(int units) {
+  ItemMap m;
+  const int G = gridDim.x, b = blockIdx.x;
+  if (G >= kXcds && G % kXcds == 0) {
+    const int x = b % kXcds;
+    m.u_lo = (int)((int64_t)units * x / kXcds);
+    m.u_n = (int)((int64_t)units * (x + 1) / kXcds) - m.u_lo;
+    m.first = b / kXcds;
+    m.step = G / kXcds;
+  } else {
+    m.u_lo = 0;
+    m.u_n = units;
+    m.first = b;
+    m.step = G;
+  }
+  m.total = m.u_n * N;
+  return m;
+}
+
 // ---- pass A: pair product, forward FFT x and y (persistent, pipelined) ------
 // PIPE: the next plane's loads are issued into registers before the current
 // plane is transformed (one workgroup per CU at 96^2); without it the kernel
@@ -56,9 +93,11 @@ __global__ void __launch_bounds__(CubeShape<N>::NT_P, (PassAWaves<T, PIPE>::valu
   const int tid = threadIdx.x;
   for (int i = tid; i < N; i += NT) tw[i] = twg[i];
   cpx<T> va[EPT], vb[EPT];
-  auto fetch = [&](int it) __attribute__((always_inline)) {
-    if (it >= nitems) return;
-    const int z = it % N, p = it / N;
+  const ItemMap im = item_map<N>(nitems / N);
+  auto fetch = [&](int li) __attribute__((always_inline)) {
+    if (li >= im.total) return;
+    int p, z;
+    im.at(li, &p, &z);
     int jj, kk;
     pair_of(p, nj, tri, &jj, &kk);
     const cpx<T>* a = psi + (int64_t)(j0 + jj) * ld_psi + (size_t)z * NXY;
@@ -73,23 +112,24 @@ __global__ void __launch_bounds__(CubeShape<N>::NT_P, (PassAWaves<T, PIPE>::valu
     }
   };
   constexpr bool kPipe = PIPE;
-  int item = blockIdx.x;
-  if (kPipe) fetch(item);
-  for (; item < nitems; item += gridDim.x) {
-    if (!kPipe) fetch(item);
+  int li = im.first;
+  if (kPipe) fetch(li);
+  for (; li < im.total; li += im.step) {
+    if (!kPipe) fetch(li);
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
       const int e = tid + i * NT;
       if (NXY % NT == 0 || e < NXY) s[(e / N) * SX + e % N] = cconjmul(va[i], vb[i]);
     }
     __syncthreads();
-    if (kPipe) fetch(item + gridDim.x);
+    if (kPipe) fetch(li + im.step);
     ct_fft<true, T, N, N, 1, SX, NT>(s, tw, tid);
     // y: first stage in LDS, last stage straight to the work plane
     constexpr int R0 = Plan2<N>::R0, R1 = Plan2<N>::R1;
     ct_stage<R0, true, T, N, N, N, SX, 1, NT>(s, tw, tid);
     __syncthreads();
-    const int z = item % N, p = item / N;
+    int p, z;
+    im.at(li, &p, &z);
     cpx<T>* o = work + p * NR + (size_t)z * NXY;
     ct_stage_io<R1, true, T, N, R1, N, SX, 1, NT, false, true, N, 1>(s, nullptr, o, tw, tid);
     __syncthreads();
@@ -178,9 +218,10 @@ __global__ void __launch_bounds__(NT) k_pass_c_ct(const cpx<T>* __restrict__ mul
   const int tid = threadIdx.x;
   for (int i = tid; i < N; i += NT) tw[i] = twg[i];
   __syncthreads();
-  for (int item = blockIdx.x; item < nitems; item += gridDim.x) {
-    const int z = item % N;
-    const int tt = item / N;
+  const ItemMap im = item_map<N>(nitems / N);
+  for (int li = im.first; li < im.total; li += im.step) {
+    int tt, z;
+    im.at(li, &tt, &z);
     const int t = t0 + tt;
     cpx<A> a[EPT];
     cpx<T> vp[EPT];
@@ -260,7 +301,10 @@ static fx_status ct_prepare(fx_ctx* ctx, K kernel, int nthr, size_t lds, int ite
   }
   int per_cu = 0;
   FX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kernel), nthr, lds));
-  *grid = std::max(1, std::min(items, std::max(per_cu, 1) * std::max(ctx->n_cu, 1)));
+  int g = std::max(1, std::min(items, std::max(per_cu, 1) * std::max(ctx->n_cu, 1)));
+  // a multiple of the XCD count, so that each XCD walks its own chunk (item_map)
+  if (g >= kXcds) g -= g % kXcds;
+  *grid = g;
   return FX_OK;
 }
 

@@ -45,7 +45,7 @@ class FxKernel(C.Structure):
 
 class FxServeCfg(C.Structure):
     _fields_ = [("max_slots", C.c_int32), ("n_streams", C.c_int32), ("max_batch_pairs", C.c_int32),
-                ("hbm_budget_bytes", C.c_size_t)]
+                ("hbm_budget_bytes", C.c_size_t), ("autotune", C.c_int32), ("autotune_targets", C.c_int32)]
 
 
 class FxRequest(C.Structure):
@@ -115,6 +115,12 @@ _SIGS = {
     "fx_debug_host_pair_plan": (C.c_int, [C.POINTER(FxCell), C.POINTER(FxKernel), C.c_int, C.c_void_p, C.c_void_p,
                                            C.c_void_p, C.c_void_p]),
     "fx_debug_axis_plans": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.POINTER(C.c_int32)]),
+    "fx_pt_residual": (C.c_int, [C.c_void_p, C.POINTER(FxCell), C.POINTER(FxKernel), C.c_void_p, C.c_void_p,
+                                 C.c_void_p, C.c_int32, C.c_int64, C.c_int, C.c_double, C.c_int, C.c_void_p, C.c_int64,
+                                 C.c_void_p, C.c_void_p]),
+    "fx_orthonormalize": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int64, C.c_int64, C.c_int, C.c_void_p]),
+    "fx_density": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int64, C.c_int64, C.c_int, C.c_void_p,
+                             C.c_void_p, C.c_void_p]),
     "fx_vx_autotune": (C.c_int, [C.c_void_p, C.POINTER(FxCell), C.POINTER(FxKernel), C.c_int32, C.c_int32, C.c_int32,
                                  C.c_int, C.c_void_p, C.POINTER(FxVxConfig), C.POINTER(C.c_double)]),
     "fx_vx_set_config": (C.c_int, [C.c_void_p, C.POINTER(FxCell), C.c_int, C.c_int32, C.POINTER(FxVxConfig)]),
@@ -274,6 +280,62 @@ class Context:
                                   C.c_void_p(ex.data_ptr()) if ex is not None else None))
         return (out, ex) if energy else out
 
+    # -- end-of-step operations ----------------------------------------------------
+    def pt_residual(self, psi, psi_half, *, n, L, hpsi=None, dt, kernel="hse", omega=0.106, scale=1.0,
+                    vx_prec="fp32acc64", out=None, s_out=None, stream=None):
+        """R = Psi + (i dt/2)(H Psi - Psi S) - Psi_half with S = Psi^H H Psi; H = V_X if hpsi is None."""
+        import torch
+
+        cell = make_cell(n, L)
+        nr = cell.n[0] * cell.n[1] * cell.n[2]
+        kern = make_kernel(kernel, omega, scale)
+        pp, npsi, ldp = _cols(psi, nr)
+        fp, nf, ldf = _cols(psi_half, nr)
+        if nf != npsi or ldf != ldp or psi_half.dtype != psi.dtype:
+            raise ValueError("psi_half must have psi's shape, stride and dtype")
+        hp = None
+        if hpsi is not None:
+            hp, nh, ldh = _cols(hpsi, nr)
+            if nh != npsi or ldh != ldp or hpsi.dtype != psi.dtype:
+                raise ValueError("hpsi must have psi's shape, stride and dtype")
+        if out is None:
+            out = torch.empty_like(psi)
+        op, no, ldo = _cols(out, nr)
+        sp = None
+        if s_out is not None:
+            if s_out.dtype != torch.complex128 or s_out.numel() != npsi * npsi or not s_out.is_contiguous():
+                raise ValueError("s_out must be a contiguous complex128 tensor of n x n")
+            sp = C.c_void_p(s_out.data_ptr())
+        _check(load().fx_pt_residual(self.h, C.byref(cell), C.byref(kern), pp, hp, fp, npsi, ldp, _dtype_code(psi),
+                                     float(dt), PREC[vx_prec], op, ldo, sp, _stream_ptr(stream)))
+        return out
+
+    def orthonormalize(self, psi, *, stream=None):
+        """Cholesky-QR re-orthonormalisation of the columns of psi, in place; returns psi."""
+        nr = int(psi[0].numel())
+        pp, npsi, ldp = _cols(psi, nr)
+        _check(load().fx_orthonormalize(self.h, pp, npsi, ldp, nr, _dtype_code(psi), _stream_ptr(stream)))
+        return psi
+
+    def density(self, psi, *, occ=None, out=None, stream=None):
+        """rho(r) = sum_i f_i |psi_i(r)|^2 in FP64 (shape of one orbital)."""
+        import torch
+
+        nr = int(psi[0].numel())
+        pp, npsi, ldp = _cols(psi, nr)
+        if out is None:
+            out = torch.empty(tuple(psi.shape[1:]), dtype=torch.float64, device=psi.device)
+        if out.dtype != torch.float64 or out.numel() != nr or not out.is_contiguous():
+            raise ValueError("out must be a contiguous float64 tensor of N_r elements")
+        oc = None
+        if occ is not None:
+            if occ.dtype != torch.float64 or occ.numel() != npsi or not occ.is_contiguous():
+                raise ValueError("occ must be a contiguous float64 tensor of n elements")
+            oc = C.c_void_p(occ.data_ptr())
+        _check(load().fx_density(self.h, pp, npsi, ldp, nr, _dtype_code(psi), oc, C.c_void_p(out.data_ptr()),
+                                 _stream_ptr(stream)))
+        return out
+
     # -- launch configuration of the V_X path ------------------------------------
     def vx_autotune(self, *, n, L, n_psi, n_phi, phi_is_psi=False, prec="fp32acc64", kernel="hse", omega=0.106,
                     scale=1.0, stream=None):
@@ -359,10 +421,12 @@ class Ace:
 class Server:
     """Continuous-batching server over resident trajectories (fx_serve_*)."""
 
-    def __init__(self, ctx, max_slots=8, n_streams=4, max_batch_pairs=1 << 16, hbm_budget_bytes=0):
+    def __init__(self, ctx, max_slots=8, n_streams=4, max_batch_pairs=1 << 16, hbm_budget_bytes=0, autotune=False,
+                 autotune_targets=8):
         cfg = FxServeCfg()
         cfg.max_slots, cfg.n_streams, cfg.max_batch_pairs = int(max_slots), int(n_streams), int(max_batch_pairs)
         cfg.hbm_budget_bytes = int(hbm_budget_bytes)
+        cfg.autotune, cfg.autotune_targets = (1 if autotune else 0), int(autotune_targets)
         h = C.c_void_p()
         _check(load().fx_serve_create(ctx.h, C.byref(cfg), C.byref(h)))
         self.ctx, self.h = ctx, h

@@ -134,3 +134,41 @@ def test_invalid_requests_reported(setup):
             dict(traj=0, op=1, first=0, count=4, t=0.0, out=o)]
     st, lat, rep = srv.serve(reqs)
     assert st[:3] == [-1, -1, -1] and st[3] == 0
+
+
+def test_autotuned_registration(setup):
+    """With autotune on, registration stores tuned configurations for the trajectory's grid
+    (request form and ACE-build form), and served results still match the oracle."""
+    import torch
+    from paper_1905_01348_amd import Context, Server
+
+    _, _, psis = setup
+    ctx = Context(0)
+    srv = Server(ctx, max_slots=4, n_streams=2, max_batch_pairs=4096, autotune=True, autotune_targets=4)
+    for t in (2, 3):
+        n3, L, N, seed = TRAJ[t]
+        srv.register(t, dev(psis[t]), n=n3, L=L, kernel="hse", omega=0.106, vx_prec="fp32acc64", ace_prec="ace_fp32r")
+        for square in (False, True):
+            cfg, is_set = ctx.get_vx_config(n=n3, prec="fp32acc64", phi_is_psi=square)
+            say("traj", t, "square" if square else "requests", cfg)
+            assert is_set and cfg["kernels"] in (1, 2)
+    reqs = [dict(traj=t, op=op, first=4, count=4, t=0.001 * i) for i, (t, op) in
+            enumerate([(2, 0), (3, 0), (2, 1), (3, 1)])]
+    outs = _outs(reqs)
+    for r, o in zip(reqs, outs):
+        r["out"] = o
+    st, lat, rep = srv.serve(reqs)
+    torch.cuda.synchronize()
+    assert all(s == 0 for s in st)
+    for r, o in zip(reqs, outs):
+        n3, L, N, seed = TRAJ[r["traj"]]
+        psi = psis[r["traj"]].astype(np.complex128)
+        phi = psi[r["first"]:r["first"] + r["count"]]
+        if r["op"] == 0:
+            ref = oracle.apply_vx(psi, phi, n3, L, "hse", 0.106)
+        else:
+            w = oracle.apply_vx(psi, psi, n3, L, "hse", 0.106)
+            ref = oracle.apply_ace(oracle.build_ace(psi, w)["xi"], phi)
+        assert col_err(host(o), ref) <= 1e-5, r
+    srv.close()
+    ctx.close()

@@ -1,0 +1,156 @@
+"""End-of-step operations on the GPU against the FP64 oracle.
+
+Residual (given H Psi, and with H = V_X computed by the pair path), Cholesky-QR
+re-orthonormalisation and density.  Tolerances (relative, per column):
+complex128 blocks 1e-12 (pure FP64 GEMM and elementwise work; 1e-10 where
+the V_X pair path or a Cholesky factor enters), complex64 blocks 1e-6 (the
+rounding of the output), and the V_X path's own bars (1e-10 FP64, 1e-5 FP32).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from paper_1905_01348_amd import fock as F
+from tests.gpu_util import col_err, dev, host, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1905_01348_amd import Context
+
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _block(seed, n3, N):
+    return synth.random_grid_vectors(seed, n3, N)
+
+
+CASES = [((12, 12, 12), (6.0, 6.0, 6.0), 7), ((24, 18, 16), (10.0, 8.0, 7.0), 33), ((9, 8, 6), (4.0, 4.0, 3.0), 70)]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}-N{c[2]}" for c in CASES])
+def test_residual_given_hpsi(ctx, case):
+    import torch
+
+    n3, L3, N = case
+    psi = synth.make_orbitals(80, n3, L3, N, ecut=1e4)
+    hpsi = _block(81, n3, N)
+    half = _block(82, n3, N)
+    dt = 0.37
+    ref = oracle.pt_residual(psi, hpsi, half, dt)
+    S_ref = psi.reshape(N, -1).conj() @ hpsi.reshape(N, -1).T
+    for dtype, tol in ((torch.complex128, 1e-12), (torch.complex64, 1e-6)):
+        P, H, Hf = dev(psi, dtype), dev(hpsi, dtype), dev(half, dtype)
+        S = torch.zeros((N, N), dtype=torch.complex128, device="cuda")
+        R = ctx.pt_residual(P, Hf, n=n3, L=L3, hpsi=H, dt=dt, s_out=S)
+        torch.cuda.synchronize()
+        if dtype == torch.complex64:  # the oracle on the same rounded inputs
+            ref_t = oracle.pt_residual(host(P).astype(np.complex128), host(H).astype(np.complex128),
+                                       host(Hf).astype(np.complex128), dt)
+        else:
+            ref_t = ref
+        err = col_err(host(R), ref_t)
+        say("residual", n3, N, dtype, err)
+        assert err <= tol
+        # S in column-major: element (i, j) at S[j, i] of the row-major tensor
+        s_err = np.abs(host(S).T - (S_ref if dtype == torch.complex128 else
+                                    host(P).astype(np.complex128).reshape(N, -1).conj()
+                                    @ host(H).astype(np.complex128).reshape(N, -1).T)).max()
+        assert s_err <= 1e-12 * np.abs(S_ref).max()
+
+
+@pytest.mark.parametrize("vx_prec,tol", [("fp64", 1e-10), ("fp32acc64", 1e-5)])
+def test_residual_with_vx(ctx, vx_prec, tol):
+    """H = V_X: the library computes H Psi by the pair path (phi = Psi, halved on 24^3)."""
+    n3, L3, N = (24, 24, 24), (10.26,) * 3, 12
+    psi = synth.make_orbitals(83, n3, L3, N)
+    half = _block(84, n3, N)
+    dt = 0.5
+    w = oracle.apply_vx(psi, psi, n3, L3, "hse", 0.106)
+    ref = oracle.pt_residual(psi, w, half, dt)
+    R = ctx.pt_residual(dev(psi), dev(half), n=n3, L=L3, dt=dt, kernel="hse", vx_prec=vx_prec)
+    err = col_err(host(R), ref)
+    say("residual with V_X", vx_prec, err)
+    # the V_X error enters through (dt/2) H Psi, small against Psi - Psi_half
+    assert err <= tol
+
+
+def test_residual_planewave_eigenbasis(ctx):
+    """Planewaves are eigenvectors of V_X: the residual with H = V_X is Psi - Psi_half."""
+    n3, L3 = (6, 6, 6), (5.0, 5.0, 5.0)
+    psi = synth.planewave_orbitals(n3, L3, [(0, 0, 0), (1, 0, 0), (0, -1, 2), (3, 1, -1)])
+    half = _block(85, n3, 4)
+    R = host(ctx.pt_residual(dev(psi), dev(half), n=n3, L=L3, dt=0.9, kernel="hse", omega=0.3, vx_prec="fp64"))
+    assert np.abs(R - (psi - half)).max() <= 1e-13 * np.abs(psi - half).max()
+
+
+def test_residual_errors(ctx):
+    import torch
+
+    n3, L3, N = (12, 12, 12), (6.0,) * 3, 4
+    P = dev(_block(86, n3, N))
+    with pytest.raises(F.FockError) as ei:
+        ctx.pt_residual(P, P.clone(), n=n3, L=L3, hpsi=P.clone(), dt=0.1, out=P)
+    assert ei.value.status == F.FX_ERR_INVALID  # r_out overlaps psi
+    with pytest.raises(F.FockError) as ei:
+        ctx.pt_residual(P, P.clone(), n=n3, L=L3, hpsi=P.clone(), dt=float("nan"))
+    assert ei.value.status == F.FX_ERR_INVALID
+    torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}-N{c[2]}" for c in CASES])
+def test_orthonormalize(ctx, case):
+    import torch
+
+    n3, L3, N = case
+    a = _block(90, n3, N)
+    a[1] += 0.5 * a[0]  # not orthonormal, well conditioned
+    ref = oracle.orthonormalize(a)
+    for dtype, tol in ((torch.complex128, 1e-11), (torch.complex64, 1e-5)):
+        A = dev(a, dtype)
+        ref_t = ref if dtype == torch.complex128 else oracle.orthonormalize(host(A).astype(np.complex128))
+        ctx.orthonormalize(A)
+        torch.cuda.synchronize()
+        got = host(A).astype(np.complex128)
+        err = col_err(got, ref_t)
+        X = got.reshape(N, -1)
+        orth = np.abs(X.conj() @ X.T - np.eye(N)).max()
+        say("orthonormalize", n3, N, dtype, err, "orth", orth)
+        assert err <= tol and orth <= (1e-12 if dtype == torch.complex128 else 1e-5)
+
+
+def test_orthonormalize_dependent_columns(ctx):
+    import torch
+
+    n3, N = (8, 8, 8), 5
+    a = _block(91, n3, N)
+    a[3] = a[1]
+    A = dev(a)
+    before = host(A)
+    with pytest.raises(F.FockError) as ei:
+        ctx.orthonormalize(A)
+    assert ei.value.status == F.FX_ERR_NOT_POSDEF
+    torch.cuda.synchronize()
+    assert np.array_equal(host(A), before)  # left untouched
+
+
+@pytest.mark.parametrize("n3,N", [((12, 12, 12), 9), ((10, 10, 10), 130), ((96, 96, 96), 40)])
+def test_density(ctx, n3, N):
+    import torch
+
+    psi = _block(92, n3, N)
+    occ = np.linspace(2.0, 0.0, N)
+    for dtype, tol in ((torch.complex128, 1e-13), (torch.complex64, 1e-6)):
+        P = dev(psi, dtype)
+        src = host(P).astype(np.complex128)
+        for o in (None, occ):
+            ref = oracle.density(src, o)
+            got = host(ctx.density(P, occ=None if o is None else torch.from_numpy(o).cuda()))
+            err = np.abs(got - ref).max() / np.abs(ref).max()
+            assert err <= tol, (dtype, o is None, err)
+    say("density", n3, N, "ok")
