@@ -184,26 +184,27 @@ __device__ inline void ct_conv(cpx<T>* s, const cpx<T>* tw, KF kf, int tid) {
 }
 
 // Launch shapes per edge: plane passes (threads), pencil pass (x tile,
-// threads), a second pencil-pass shape with half the x tile, and a second
-// thread count for the plane-inverse pass (fewer accumulators per thread,
-// more waves per CU).
+// threads), a second pencil-pass shape with half the x tile, a second thread
+// count for the plane-inverse pass (fewer accumulators per thread, more waves
+// per CU) and one for the plane-forward pass (butterfly counts that divide
+// evenly among the threads).
 template <int N>
 struct CubeShape;
 template <>
 struct CubeShape<24> {
-  static constexpr int NT_P = 192, XT = 24, NT_B = 192, XT2 = 12, NT_B2 = 96, NT_C2 = 288;
+  static constexpr int NT_P = 192, XT = 24, NT_B = 192, XT2 = 12, NT_B2 = 96, NT_C2 = 288, NT_A2 = 288;
 };
 template <>
 struct CubeShape<48> {
-  static constexpr int NT_P = 256, XT = 48, NT_B = 256, XT2 = 24, NT_B2 = 128, NT_C2 = 384;
+  static constexpr int NT_P = 256, XT = 48, NT_B = 256, XT2 = 24, NT_B2 = 128, NT_C2 = 384, NT_A2 = 384;
 };
 template <>
 struct CubeShape<72> {
-  static constexpr int NT_P = 512, XT = 24, NT_B = 256, XT2 = 12, NT_B2 = 128, NT_C2 = 576;
+  static constexpr int NT_P = 512, XT = 24, NT_B = 256, XT2 = 12, NT_B2 = 128, NT_C2 = 576, NT_A2 = 576;
 };
 template <>
 struct CubeShape<96> {
-  static constexpr int NT_P = 512, XT = 48, NT_B = 512, XT2 = 24, NT_B2 = 256, NT_C2 = 768;
+  static constexpr int NT_P = 512, XT = 48, NT_B = 512, XT2 = 24, NT_B2 = 256, NT_C2 = 768, NT_A2 = 768;
 };
 
 }  // namespace fx

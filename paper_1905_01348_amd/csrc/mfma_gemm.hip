@@ -433,7 +433,9 @@ static fx_status apply_t(fx_ctx* ctx, Workspace* ws, fx_ace* a, AceSplit* sp, co
     // the split depends on the reduction length only, so a column's result
     // does not depend on how many right-hand sides share the launch
     (void)tiles;
-    int nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(32, ksteps / 16));
+    // (up to 128 chunks of at least 16 steps: enough workgroups for a few
+    // right-hand sides, where the output has only a handful of tiles)
+    int nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(128, ksteps / 16));
     if (const char* e = getenv("FX_ACE_NSPLIT")) nsplit = std::max(1, atoi(e));
     int64_t kchunk = (ksteps + nsplit - 1) / nsplit * BK;
     nsplit = (int)((sp->kc + kchunk - 1) / kchunk);

@@ -282,6 +282,7 @@ fx_status fx_serve(fx_server* srv, const fx_request* reqs, int32_t n_reqs, fx_st
       va.in_dtype = t.dtype;
       va.out_dtype = t.dtype;
       va.prec = t.vx_prec;
+      va.work_cap = (size_t)(srv->cfg.vx_work_mb > 0 ? srv->cfg.vx_work_mb : 1024) << 20;
       FX_TRY(vx_apply(ctx, &sl.ws, va, sl.st, nullptr));
       pairs_done += (double)t.n * total;
     } else {

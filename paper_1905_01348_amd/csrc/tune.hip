@@ -39,6 +39,7 @@ static fx_status check_config(const fx_cell* cell, const fx_vx_config& c) {
   if (c.a_prefetch < -1 || c.a_prefetch > 1) FX_FAIL(FX_ERR_INVALID, "a_prefetch = %d not in {-1, 0, 1}", c.a_prefetch);
   if (c.b_variant < 0 || c.b_variant > 2) FX_FAIL(FX_ERR_INVALID, "b_variant = %d not in {0, 1, 2}", c.b_variant);
   if (c.c_variant < 0 || c.c_variant > 2) FX_FAIL(FX_ERR_INVALID, "c_variant = %d not in {0, 1, 2}", c.c_variant);
+  if (c.a_variant < 0 || c.a_variant > 2) FX_FAIL(FX_ERR_INVALID, "a_variant = %d not in {0, 1, 2}", c.a_variant);
   if (c.b_xtile < 0 || c.b_xtile > cell->n[0]) FX_FAIL(FX_ERR_INVALID, "b_xtile = %d not in [0, n_x]", c.b_xtile);
   if (c.b_threads != 0 && (c.b_threads < 64 || c.b_threads > 256 || c.b_threads % 64))
     FX_FAIL(FX_ERR_INVALID, "b_threads = %d must be 0 or a multiple of 64 in [64, 256]", c.b_threads);
@@ -68,6 +69,7 @@ static fx_status time_candidate(fx_ctx* ctx, const VxArgs& base, const fx_vx_con
   a.a_pipe = c.a_prefetch;
   a.b_var = c.b_variant;
   a.c_var = c.c_variant;
+  a.a_var = c.a_variant;
   a.xtile = c.b_xtile;
   a.nthr_b = c.b_threads;
   bool any = false;
@@ -184,6 +186,7 @@ static fx_status autotune(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* ker
   cur.a_prefetch = 0;
   cur.b_variant = spec ? 1 : 0;
   cur.c_variant = spec ? (cell->n[0] == 96 ? 2 : 1) : 0;
+  cur.a_variant = spec ? 1 : 0;
   rs = trial(cur);
   if (rs == FX_OK && best == std::numeric_limits<double>::infinity()) {
     cleanup();
@@ -194,6 +197,7 @@ static fx_status autotune(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* ker
     c.kernels = 2;
     c.b_variant = 0;
     c.c_variant = 0;
+    c.a_variant = 0;
     rs = trial(c);
   }
   if (rs == FX_OK && cur.kernels == 1) {
@@ -210,6 +214,11 @@ static fx_status autotune(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* ker
     if (rs == FX_OK) {
       fx_vx_config c = cur;
       c.c_variant = 3 - cur.c_variant;
+      rs = trial(c);
+    }
+    if (rs == FX_OK) {
+      fx_vx_config c = cur;
+      c.a_variant = 2;
       rs = trial(c);
     }
   }

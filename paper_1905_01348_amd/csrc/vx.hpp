@@ -33,6 +33,7 @@ struct VxArgs {
   int a_pipe = -1;  // specialised plane-forward pass: 1 register prefetch, 0 two workgroups per CU
   int b_var = 0;    // specialised z pass tile: 1 default, 2 half, 0 automatic
   int c_var = 0;    // specialised plane-inverse threads: 1 default, 2 second count, 0 automatic
+  int a_var = 0;    // specialised plane-forward threads: 1 default, 2 second count, 0 automatic
   bool plans_set = false;  // generic kernels: radix schedules in `plans`
   PlanSet plans;
 };
@@ -75,6 +76,7 @@ struct CtBatch {
   int a_pipe;       // plane-forward pass: register prefetch of the next plane
   int b_var;        // z pass: 1 default x tile, 2 half tile
   int c_var;        // plane-inverse pass: 1 default threads, 2 the second thread count
+  int a_var;        // plane-forward pass: 1 default threads, 2 the second thread count
 };
 template <typename A>
 struct CtAcc {

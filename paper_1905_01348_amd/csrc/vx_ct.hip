@@ -80,12 +80,12 @@ struct PassAWaves {
   static constexpr int value = (sizeof(T) == 4 && !PIPE) ? 4 : 1;
 };
 
-template <typename T, int N, bool PIPE>
-__global__ void __launch_bounds__(CubeShape<N>::NT_P, (PassAWaves<T, PIPE>::value)) k_pass_a_ct(const cpx<T>* __restrict__ psi, int64_t ld_psi,
+template <typename T, int N, bool PIPE, int NT>
+__global__ void __launch_bounds__(NT, (PassAWaves<T, PIPE>::value)) k_pass_a_ct(const cpx<T>* __restrict__ psi, int64_t ld_psi,
                                                                   const cpx<T>* __restrict__ phi, int64_t ld_phi,
                                                                   cpx<T>* __restrict__ work, int j0, int nj, int k0,
                                                                   int tri, int nitems, const cpx<T>* __restrict__ twg) {
-  constexpr int NT = CubeShape<N>::NT_P, NXY = N * N, SX = N + 1, EPT = CeilDiv<NXY, NT>::value;
+  constexpr int NXY = N * N, SX = N + 1, EPT = CeilDiv<NXY, NT>::value;
   constexpr size_t NR = (size_t)NXY * N;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* s = reinterpret_cast<cpx<T>*>(smem_raw);
@@ -308,13 +308,12 @@ static fx_status ct_prepare(fx_ctx* ctx, K kernel, int nthr, size_t lds, int ite
   return FX_OK;
 }
 
-template <typename T, int N>
-static fx_status pass_a_n(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b) {
-  constexpr int NT = CubeShape<N>::NT_P;
+template <typename T, int N, int NT>
+static fx_status pass_a_shape(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b) {
   const size_t lds = ((size_t)N * (N + 1) + N) * sizeof(cpx<T>);
   // the prefetching form exists for FP32 only (FP64 has no registers to spare)
   const bool pipe = sizeof(T) == 4 && b.a_pipe;
-  auto kern = pipe ? k_pass_a_ct<T, N, sizeof(T) == 4> : k_pass_a_ct<T, N, false>;
+  auto kern = pipe ? k_pass_a_ct<T, N, sizeof(T) == 4, NT> : k_pass_a_ct<T, N, false, NT>;
   const int items = b.npairs * N;
   int grid = 0;
   FX_TRY(ct_prepare(ctx, kern, NT, lds, items, true, &grid));
@@ -322,6 +321,13 @@ static fx_status pass_a_n(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b) {
                      b.tri, items, b.tw);
   FX_LAUNCH_CHECK();
   return FX_OK;
+}
+
+template <typename T, int N>
+static fx_status pass_a_n(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b) {
+  using S = CubeShape<N>;
+  if (b.a_var == 2) return pass_a_shape<T, N, S::NT_A2>(ctx, st, b);
+  return pass_a_shape<T, N, S::NT_P>(ctx, st, b);
 }
 
 template <typename T, int N, int XT, int NT>

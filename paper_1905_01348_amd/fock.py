@@ -45,7 +45,8 @@ class FxKernel(C.Structure):
 
 class FxServeCfg(C.Structure):
     _fields_ = [("max_slots", C.c_int32), ("n_streams", C.c_int32), ("max_batch_pairs", C.c_int32),
-                ("hbm_budget_bytes", C.c_size_t), ("autotune", C.c_int32), ("autotune_targets", C.c_int32)]
+                ("hbm_budget_bytes", C.c_size_t), ("autotune", C.c_int32), ("autotune_targets", C.c_int32),
+                ("vx_work_mb", C.c_int32)]
 
 
 class FxRequest(C.Structure):
@@ -62,19 +63,20 @@ class FxServeReport(C.Structure):
 
 class FxVxConfig(C.Structure):
     _fields_ = [("kernels", C.c_int32), ("work_mb", C.c_int32), ("a_prefetch", C.c_int32),
-                ("b_variant", C.c_int32), ("c_variant", C.c_int32), ("b_xtile", C.c_int32), ("b_threads", C.c_int32),
+                ("b_variant", C.c_int32), ("c_variant", C.c_int32), ("a_variant", C.c_int32), ("b_xtile", C.c_int32),
+                ("b_threads", C.c_int32),
                 ("radix", (C.c_int32 * 4) * 3)]
 
 
 def config_to_dict(c):
     return {"kernels": c.kernels, "work_mb": c.work_mb, "a_prefetch": c.a_prefetch, "b_variant": c.b_variant,
-            "c_variant": c.c_variant, "b_xtile": c.b_xtile, "b_threads": c.b_threads, "radix": [list(row) for row in c.radix]}
+            "c_variant": c.c_variant, "a_variant": c.a_variant, "b_xtile": c.b_xtile, "b_threads": c.b_threads, "radix": [list(row) for row in c.radix]}
 
 
 def config_from_dict(d):
     c = FxVxConfig()
     c.a_prefetch = -1
-    for k in ("kernels", "work_mb", "a_prefetch", "b_variant", "c_variant", "b_xtile", "b_threads"):
+    for k in ("kernels", "work_mb", "a_prefetch", "b_variant", "c_variant", "a_variant", "b_xtile", "b_threads"):
         if k in d:
             setattr(c, k, int(d[k]))
     for a, row in enumerate(d.get("radix", [])):
@@ -422,11 +424,12 @@ class Server:
     """Continuous-batching server over resident trajectories (fx_serve_*)."""
 
     def __init__(self, ctx, max_slots=8, n_streams=4, max_batch_pairs=1 << 16, hbm_budget_bytes=0, autotune=False,
-                 autotune_targets=8):
+                 autotune_targets=8, vx_work_mb=0):
         cfg = FxServeCfg()
         cfg.max_slots, cfg.n_streams, cfg.max_batch_pairs = int(max_slots), int(n_streams), int(max_batch_pairs)
         cfg.hbm_budget_bytes = int(hbm_budget_bytes)
         cfg.autotune, cfg.autotune_targets = (1 if autotune else 0), int(autotune_targets)
+        cfg.vx_work_mb = int(vx_work_mb)
         h = C.c_void_p()
         _check(load().fx_serve_create(ctx.h, C.byref(cfg), C.byref(h)))
         self.ctx, self.h = ctx, h
