@@ -174,11 +174,14 @@ typedef struct fx_vx_config {
   int32_t work_mb;     /* pair work volume per batch, MiB (automatic: 8192, at most budget/4) */
   int32_t a_prefetch;  /* specialised plane-forward pass: 1 prefetch the next plane into
                           registers, 0 two workgroups per CU instead, -1 automatic (0) */
-  int32_t b_variant;   /* specialised z pass x-tile: 1 the edge's default, 2 half of it */
+  int32_t b_variant;   /* specialised z pass x-tile: 1 the edge's default, 2 half of it,
+                          3 whole x rows */
   int32_t c_variant;   /* specialised plane-inverse pass threads: 1 the edge's default,
                           2 a larger count (fewer accumulators per thread, more waves) */
   int32_t a_variant;   /* specialised plane-forward pass threads: 1 the edge's default,
                           2 a count that divides the butterflies evenly */
+  int32_t nt_hint;     /* specialised kernels: 1 read and write the pair volume with
+                          non-temporal cache hints, 0 plain accesses, -1 automatic (1) */
   int32_t b_xtile;     /* generic z pass: x columns per workgroup */
   int32_t b_threads;   /* generic z pass: most threads per workgroup (64, 128, 192 or 256) */
   int32_t radix[3][4]; /* generic: radix schedule of each axis (x, y, z), stages in
@@ -191,7 +194,8 @@ typedef struct fx_vx_config {
  * (n_psi orbitals, n_phi targets, phi_is_psi != 0 for the phi == psi form)
  * on synthetic data it allocates itself, by coordinate descent over the
  * fields above (kernel family; for the specialised kernels the prefetch form,
- * the z-pass tile and the plane-inverse and plane-forward threads; for the generic kernels the radix schedule of each
+ * the z-pass tile, the plane-inverse and plane-forward threads and the cache
+ * hints; for the generic kernels the radix schedule of each
  * axis, the z-pass tile and threads; then the batch volume), and stores the
  * fastest in the context, where every later fx_apply_vx, fx_build_ace and
  * served request of that grid, precision and form uses it.  Each candidate

@@ -69,6 +69,38 @@ FX_HD void ct_stage(cpx<T>* s, const cpx<T>* tw, int tid) {
   }
 }
 
+// Global accesses with a non-temporal hint: data read or written once (the
+// pair volume) need not displace data that is reused from the caches (the
+// orbital and target planes the workgroups of an XCD share).  At 96^3 the
+// hint took the three passes from 10.5 to 9.5 ms per launch of 1170 pairs.
+template <typename T>
+struct Vec2;
+template <>
+struct Vec2<float> {
+  typedef float type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct Vec2<double> {
+  typedef double type __attribute__((ext_vector_type(2)));
+};
+template <bool NTS, typename T>
+FX_HD cpx<T> g_load(const cpx<T>* p) {
+  if (!NTS) return *p;
+  const typename Vec2<T>::type v = __builtin_nontemporal_load(reinterpret_cast<const typename Vec2<T>::type*>(p));
+  return cpx<T>{v.x, v.y};
+}
+template <bool NTS, typename T>
+FX_HD void g_store(cpx<T>* p, cpx<T> a) {
+  if (!NTS) {
+    *p = a;
+    return;
+  }
+  typename Vec2<T>::type v;
+  v.x = a.x;
+  v.y = a.y;
+  __builtin_nontemporal_store(v, reinterpret_cast<typename Vec2<T>::type*>(p));
+}
+
 // A stage that reads its inputs from global memory (FROM_G) and/or writes its
 // outputs to global memory (TO_G) instead of LDS.  In global memory element i
 // of transform f is g[f*GFS + i*GES]; in LDS it is s[f*FS + i*ES].  With
@@ -77,7 +109,7 @@ FX_HD void ct_stage(cpx<T>* s, const cpx<T>* tw, int tid) {
 // HBM) and its last stage (results straight to HBM), saving an LDS round
 // trip and a barrier at each end.
 template <int R, bool FWD, typename T, int N, int L, int COUNT, int ES, int FS, int NTHR, bool FROM_G, bool TO_G,
-          int GES, int GFS>
+          int GES, int GFS, bool NTS = false>
 FX_HD void ct_stage_io(cpx<T>* s, const cpx<T>* gin, cpx<T>* gout, const cpx<T>* tw, int tid) {
   constexpr int SPAN = L / R, TOTAL = COUNT * (N / R), TSTEP = N / L;
   constexpr int ITERS = (TOTAL + NTHR - 1) / NTHR;
@@ -95,7 +127,7 @@ FX_HD void ct_stage_io(cpx<T>* s, const cpx<T>* gin, cpx<T>* gout, const cpx<T>*
 #pragma unroll
       for (int m = 0; m < R; ++m) {
         const int pos = pos0 + m * SPAN;
-        x[it][m] = FROM_G ? gin[f * GFS + pos * GES] : s[f * FS + pos * ES];
+        x[it][m] = FROM_G ? g_load<NTS>(gin + f * GFS + pos * GES) : s[f * FS + pos * ES];
       }
     }
   }
@@ -125,7 +157,7 @@ FX_HD void ct_stage_io(cpx<T>* s, const cpx<T>* gin, cpx<T>* gout, const cpx<T>*
       for (int m = 0; m < R; ++m) {
         const int pos = pos0 + m * SPAN;
         if (TO_G)
-          gout[f * GFS + pos * GES] = x[it][m];
+          g_store<NTS>(gout + f * GFS + pos * GES, x[it][m]);
         else
           s[f * FS + pos * ES] = x[it][m];
       }
@@ -184,7 +216,8 @@ __device__ inline void ct_conv(cpx<T>* s, const cpx<T>* tw, KF kf, int tid) {
 }
 
 // Launch shapes per edge: plane passes (threads), pencil pass (x tile,
-// threads), a second pencil-pass shape with half the x tile, a second thread
+// threads), second and third pencil-pass shapes (half the x tile; whole x
+// rows, the longest contiguous runs in HBM), a second thread
 // count for the plane-inverse pass (fewer accumulators per thread, more waves
 // per CU) and one for the plane-forward pass (butterfly counts that divide
 // evenly among the threads).
@@ -192,19 +225,19 @@ template <int N>
 struct CubeShape;
 template <>
 struct CubeShape<24> {
-  static constexpr int NT_P = 192, XT = 24, NT_B = 192, XT2 = 12, NT_B2 = 96, NT_C2 = 288, NT_A2 = 288;
+  static constexpr int NT_P = 192, XT = 24, NT_B = 192, XT2 = 12, NT_B2 = 96, NT_C2 = 288, NT_A2 = 288, XT3 = 24, NT_B3 = 192;
 };
 template <>
 struct CubeShape<48> {
-  static constexpr int NT_P = 256, XT = 48, NT_B = 256, XT2 = 24, NT_B2 = 128, NT_C2 = 384, NT_A2 = 384;
+  static constexpr int NT_P = 256, XT = 48, NT_B = 256, XT2 = 24, NT_B2 = 128, NT_C2 = 384, NT_A2 = 384, XT3 = 48, NT_B3 = 256;
 };
 template <>
 struct CubeShape<72> {
-  static constexpr int NT_P = 512, XT = 24, NT_B = 256, XT2 = 12, NT_B2 = 128, NT_C2 = 576, NT_A2 = 576;
+  static constexpr int NT_P = 512, XT = 24, NT_B = 256, XT2 = 12, NT_B2 = 128, NT_C2 = 576, NT_A2 = 576, XT3 = 72, NT_B3 = 512;
 };
 template <>
 struct CubeShape<96> {
-  static constexpr int NT_P = 512, XT = 48, NT_B = 512, XT2 = 24, NT_B2 = 256, NT_C2 = 768, NT_A2 = 768;
+  static constexpr int NT_P = 512, XT = 48, NT_B = 512, XT2 = 24, NT_B2 = 256, NT_C2 = 768, NT_A2 = 768, XT3 = 96, NT_B3 = 1024;
 };
 
 }  // namespace fx

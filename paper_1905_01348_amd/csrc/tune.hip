@@ -37,9 +37,10 @@ static fx_status check_config(const fx_cell* cell, const fx_vx_config& c) {
   if (c.kernels < 0 || c.kernels > 2) FX_FAIL(FX_ERR_INVALID, "kernels = %d not in {0, 1, 2}", c.kernels);
   if (c.work_mb < 0 || c.work_mb > (1 << 20)) FX_FAIL(FX_ERR_INVALID, "work_mb = %d out of range", c.work_mb);
   if (c.a_prefetch < -1 || c.a_prefetch > 1) FX_FAIL(FX_ERR_INVALID, "a_prefetch = %d not in {-1, 0, 1}", c.a_prefetch);
-  if (c.b_variant < 0 || c.b_variant > 2) FX_FAIL(FX_ERR_INVALID, "b_variant = %d not in {0, 1, 2}", c.b_variant);
+  if (c.b_variant < 0 || c.b_variant > 3) FX_FAIL(FX_ERR_INVALID, "b_variant = %d not in {0, 1, 2, 3}", c.b_variant);
   if (c.c_variant < 0 || c.c_variant > 2) FX_FAIL(FX_ERR_INVALID, "c_variant = %d not in {0, 1, 2}", c.c_variant);
   if (c.a_variant < 0 || c.a_variant > 2) FX_FAIL(FX_ERR_INVALID, "a_variant = %d not in {0, 1, 2}", c.a_variant);
+  if (c.nt_hint < -1 || c.nt_hint > 1) FX_FAIL(FX_ERR_INVALID, "nt_hint = %d not in {-1, 0, 1}", c.nt_hint);
   if (c.b_xtile < 0 || c.b_xtile > cell->n[0]) FX_FAIL(FX_ERR_INVALID, "b_xtile = %d not in [0, n_x]", c.b_xtile);
   if (c.b_threads != 0 && (c.b_threads < 64 || c.b_threads > 256 || c.b_threads % 64))
     FX_FAIL(FX_ERR_INVALID, "b_threads = %d must be 0 or a multiple of 64 in [64, 256]", c.b_threads);
@@ -70,6 +71,7 @@ static fx_status time_candidate(fx_ctx* ctx, const VxArgs& base, const fx_vx_con
   a.b_var = c.b_variant;
   a.c_var = c.c_variant;
   a.a_var = c.a_variant;
+  a.nt_hint = c.nt_hint;
   a.xtile = c.b_xtile;
   a.nthr_b = c.b_threads;
   bool any = false;
@@ -187,6 +189,7 @@ static fx_status autotune(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* ker
   cur.b_variant = spec ? 1 : 0;
   cur.c_variant = spec ? (cell->n[0] == 96 ? 2 : 1) : 0;
   cur.a_variant = spec ? 1 : 0;
+  cur.nt_hint = spec ? 1 : 0;
   rs = trial(cur);
   if (rs == FX_OK && best == std::numeric_limits<double>::infinity()) {
     cleanup();
@@ -206,9 +209,10 @@ static fx_status autotune(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* ker
       c.a_prefetch = 1;
       rs = trial(c);
     }
-    if (rs == FX_OK) {
+    for (int bv : {2, 3}) {
+      if (rs != FX_OK) break;
       fx_vx_config c = cur;
-      c.b_variant = 2;
+      c.b_variant = bv;
       rs = trial(c);
     }
     if (rs == FX_OK) {
@@ -219,6 +223,11 @@ static fx_status autotune(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* ker
     if (rs == FX_OK) {
       fx_vx_config c = cur;
       c.a_variant = 2;
+      rs = trial(c);
+    }
+    if (rs == FX_OK) {
+      fx_vx_config c = cur;
+      c.nt_hint = 1 - cur.nt_hint;
       rs = trial(c);
     }
   }
@@ -342,6 +351,7 @@ fx_status fx_vx_get_config(fx_ctx* ctx, const fx_cell* cell, fx_prec prec, int32
   } else {
     *cfg = fx_vx_config{};
     cfg->a_prefetch = -1;
+    cfg->nt_hint = -1;
   }
   return FX_OK;
 }

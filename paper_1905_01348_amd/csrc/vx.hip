@@ -413,7 +413,7 @@ static fx_status run_halved(fx_ctx* ctx, Workspace* ws, const VxArgs& a, const G
       const int tri = J == K;
       const int npairs = tri ? jb * (jb + 1) / 2 : jb * kb;
       CtBatch<T> cb{psi, ld_psi, psi, ld_psi, reinterpret_cast<cpx<T>*>(work), j0, jb, k0, kb, npairs, tw, kf,
-                    tb->fold[0], tri, a.a_pipe > 0 ? 1 : 0, a.b_var == 2 ? 2 : 1, ct_c_variant(a), a.a_var == 2 ? 2 : 1};
+                    tb->fold[0], tri, a.a_pipe > 0 ? 1 : 0, (a.b_var == 2 || a.b_var == 3) ? a.b_var : 1, ct_c_variant(a), a.a_var == 2 ? 2 : 1, a.nt_hint != 0 ? 1 : 0};
       const double vol = (double)npairs * nr * sz;
       int slot;
       FX_TRY(prof_begin(ctx, st, FX_K_VX_PLANE_FWD, 3.0 * vol, &slot));
@@ -539,7 +539,7 @@ static fx_status run_batches(fx_ctx* ctx, Workspace* ws, const VxArgs& a, const 
       int slot;
       if (use_ct) {
         CtBatch<T> cb{psi, ld_psi, phi, ld_phi, reinterpret_cast<cpx<T>*>(work), j0, jb, k0, kb, npairs, twx, kf,
-                      tb->fold[0], 0, a.a_pipe > 0 ? 1 : 0, a.b_var == 2 ? 2 : 1, ct_c_variant(a), a.a_var == 2 ? 2 : 1};
+                      tb->fold[0], 0, a.a_pipe > 0 ? 1 : 0, (a.b_var == 2 || a.b_var == 3) ? a.b_var : 1, ct_c_variant(a), a.a_var == 2 ? 2 : 1, a.nt_hint != 0 ? 1 : 0};
         CtAcc<A> ca{acc, ld_acc, first, a.out, a.ld_out, out_c64 ? 1 : 0, last, a.pipe};
         FX_TRY(prof_begin(ctx, st, FX_K_VX_PLANE_FWD, 3.0 * vol, &slot));
         FX_TRY(ct_pass_a<T>(ctx, st, g.nx, cb));
@@ -679,6 +679,7 @@ void resolve_vx_config(fx_ctx* ctx, VxArgs* a) {
   if (const char* e = getenv("FX_VX_B_VAR")) a->b_var = atoi(e);
   if (const char* e = getenv("FX_VX_C_VAR")) a->c_var = atoi(e);
   if (const char* e = getenv("FX_VX_A_VAR")) a->a_var = atoi(e);
+  if (const char* e = getenv("FX_VX_NT")) a->nt_hint = atoi(e);
   if (getenv("FX_VX_GENERIC")) a->kernels = 2;
   if (const char* e = getenv("FX_WORK_MB")) a->work_cap = (size_t)atol(e) << 20;
   if (!ctx) return;
@@ -691,6 +692,7 @@ void resolve_vx_config(fx_ctx* ctx, VxArgs* a) {
   if (!a->b_var) a->b_var = c.b_variant;
   if (!a->c_var) a->c_var = c.c_variant;
   if (!a->a_var) a->a_var = c.a_variant;
+  if (a->nt_hint < 0 && c.nt_hint >= 0) a->nt_hint = c.nt_hint;
   if (!a->xtile) a->xtile = c.b_xtile;
   if (!a->nthr_b) a->nthr_b = c.b_threads;
   if (!a->plans_set) {

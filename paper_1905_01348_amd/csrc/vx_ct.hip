@@ -80,7 +80,7 @@ struct PassAWaves {
   static constexpr int value = (sizeof(T) == 4 && !PIPE) ? 4 : 1;
 };
 
-template <typename T, int N, bool PIPE, int NT>
+template <typename T, int N, bool PIPE, int NT, bool NTS>
 __global__ void __launch_bounds__(NT, (PassAWaves<T, PIPE>::value)) k_pass_a_ct(const cpx<T>* __restrict__ psi, int64_t ld_psi,
                                                                   const cpx<T>* __restrict__ phi, int64_t ld_phi,
                                                                   cpx<T>* __restrict__ work, int j0, int nj, int k0,
@@ -131,13 +131,13 @@ __global__ void __launch_bounds__(NT, (PassAWaves<T, PIPE>::value)) k_pass_a_ct(
     int p, z;
     im.at(li, &p, &z);
     cpx<T>* o = work + p * NR + (size_t)z * NXY;
-    ct_stage_io<R1, true, T, N, R1, N, SX, 1, NT, false, true, N, 1>(s, nullptr, o, tw, tid);
+    ct_stage_io<R1, true, T, N, R1, N, SX, 1, NT, false, true, N, 1, NTS>(s, nullptr, o, tw, tid);
     __syncthreads();
   }
 }
 
 // ---- pass B: z convolution on an x tile ---------------------------------------
-template <typename T, int N, int XT, int NT>
+template <typename T, int N, int XT, int NT, bool NTS>
 __global__ void __launch_bounds__(NT) k_pass_b_ct(cpx<T>* __restrict__ work, const cpx<T>* __restrict__ twg,
                                                   const T* __restrict__ kfold, const int* __restrict__ foldg) {
   constexpr int NTX = N / XT, NE = N * XT;
@@ -165,7 +165,7 @@ __global__ void __launch_bounds__(NT) k_pass_b_ct(cpx<T>* __restrict__ work, con
   constexpr int R0 = Plan2<N>::R0, R1 = Plan2<N>::R1;
   // first forward stage straight from the work volume (twiddles from the
   // cached global table: the LDS copy is not yet visible)
-  ct_stage_io<R0, true, T, N, N, XT, XT, 1, NT, true, false, N * N, 1>(s, g0, nullptr, twg, tid);
+  ct_stage_io<R0, true, T, N, N, XT, XT, 1, NT, true, false, N * N, 1, NTS>(s, g0, nullptr, twg, tid);
   __syncthreads();
   // last forward stage x K x first inverse stage, in registers
   {
@@ -193,7 +193,7 @@ __global__ void __launch_bounds__(NT) k_pass_b_ct(cpx<T>* __restrict__ work, con
   }
   __syncthreads();
   // last inverse stage straight back to the work volume
-  ct_stage_io<R0, false, T, N, N, XT, XT, 1, NT, false, true, N * N, 1>(s, nullptr, g0, tw, tid);
+  ct_stage_io<R0, false, T, N, N, XT, XT, 1, NT, false, true, N * N, 1, NTS>(s, nullptr, g0, tw, tid);
 }
 
 // ---- pass C: inverse FFT y and x, times psi_j, j-sum in registers --------------
@@ -204,7 +204,7 @@ __global__ void __launch_bounds__(NT) k_pass_b_ct(cpx<T>* __restrict__ work, con
 // runs over its k in ascending order, adding psi_{m0+kk} * conj(v_{jk}),
 // which is v_{kj} since the kernel is real and even.  On a diagonal batch
 // (tri) role 0 takes jj <= kk and role 1 kk > jj.
-template <typename T, typename A, int N, bool CONJ, int NT>
+template <typename T, typename A, int N, bool CONJ, int NT, bool NTS>
 __global__ void __launch_bounds__(NT) k_pass_c_ct(const cpx<T>* __restrict__ mult, int64_t ld_mult,
                                                                   const cpx<T>* __restrict__ work, int nj, int nk,
                                                                   int tri, int m0, int t0, int nitems, cpx<A>* acc,
@@ -238,7 +238,7 @@ __global__ void __launch_bounds__(NT) k_pass_c_ct(const cpx<T>* __restrict__ mul
       const int pl = CONJ ? plane_of(tt, l, nj, tri) : plane_of(l, tt, nj, tri);
       // first inverse y stage straight from the work plane
       const cpx<T>* tp = work + (size_t)pl * NR + (size_t)z * NXY;
-      ct_stage_io<R1, false, T, N, R1, N, SX, 1, NT, true, false, N, 1>(s, tp, nullptr, tw, tid);
+      ct_stage_io<R1, false, T, N, R1, N, SX, 1, NT, true, false, N, 1, NTS>(s, tp, nullptr, tw, tid);
       __syncthreads();
       const cpx<T>* pm = mult + (int64_t)(m0 + l) * ld_mult + (size_t)z * NXY;
 #pragma unroll
@@ -313,7 +313,8 @@ static fx_status pass_a_shape(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b) 
   const size_t lds = ((size_t)N * (N + 1) + N) * sizeof(cpx<T>);
   // the prefetching form exists for FP32 only (FP64 has no registers to spare)
   const bool pipe = sizeof(T) == 4 && b.a_pipe;
-  auto kern = pipe ? k_pass_a_ct<T, N, sizeof(T) == 4, NT> : k_pass_a_ct<T, N, false, NT>;
+  auto kern = pipe ? (b.nts ? k_pass_a_ct<T, N, sizeof(T) == 4, NT, true> : k_pass_a_ct<T, N, sizeof(T) == 4, NT, false>)
+                   : (b.nts ? k_pass_a_ct<T, N, false, NT, true> : k_pass_a_ct<T, N, false, NT, false>);
   const int items = b.npairs * N;
   int grid = 0;
   FX_TRY(ct_prepare(ctx, kern, NT, lds, items, true, &grid));
@@ -330,12 +331,18 @@ static fx_status pass_a_n(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b) {
   return pass_a_shape<T, N, S::NT_P>(ctx, st, b);
 }
 
+// LDS of one z-pass workgroup with an x tile of xt columns
+template <typename T, int N>
+constexpr size_t pass_b_lds(int xt) {
+  return ((size_t)N * xt + N) * sizeof(cpx<T>) + (size_t)(N / 2 + 1) * (N / 2 + 1) * sizeof(T) + (size_t)N * sizeof(int);
+}
+constexpr size_t kLdsPerCu = 160 * 1024;
+
 template <typename T, int N, int XT, int NT>
 static fx_status pass_b_shape(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b) {
   static_assert(N % XT == 0, "x tile must divide the edge");
-  constexpr int H = N / 2 + 1;
-  const size_t lds = ((size_t)N * XT + N) * sizeof(cpx<T>) + (size_t)H * H * sizeof(T) + (size_t)N * sizeof(int);
-  auto kern = k_pass_b_ct<T, N, XT, NT>;
+  const size_t lds = pass_b_lds<T, N>(XT);
+  auto kern = b.nts ? k_pass_b_ct<T, N, XT, NT, true> : k_pass_b_ct<T, N, XT, NT, false>;
   const int items = b.npairs * N * (N / XT);
   int grid = 0;
   FX_TRY(ct_prepare(ctx, kern, NT, lds, items, false, &grid));
@@ -348,6 +355,8 @@ template <typename T, int N>
 static fx_status pass_b_n(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b) {
   using S = CubeShape<N>;
   if (b.b_var == 2) return pass_b_shape<T, N, S::XT2, S::NT_B2>(ctx, st, b);
+  // whole rows do not fit the LDS in FP64 at 96: the default tile instead
+  if (b.b_var == 3 && pass_b_lds<T, N>(S::XT3) <= kLdsPerCu) return pass_b_shape<T, N, S::XT3, S::NT_B3>(ctx, st, b);
   return pass_b_shape<T, N, S::XT, S::NT_B>(ctx, st, b);
 }
 
@@ -355,7 +364,8 @@ template <typename T, typename A, int N, int NT>
 static fx_status pass_c_shape(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b, const CtAcc<A>& c, int role) {
   const size_t lds = ((size_t)N * (N + 1) + N) * sizeof(cpx<T>);
   const int items = (role ? b.nj : b.nk) * N;
-  auto kern = role ? k_pass_c_ct<T, A, N, true, NT> : k_pass_c_ct<T, A, N, false, NT>;
+  auto kern = role ? (b.nts ? k_pass_c_ct<T, A, N, true, NT, true> : k_pass_c_ct<T, A, N, true, NT, false>)
+                   : (b.nts ? k_pass_c_ct<T, A, N, false, NT, true> : k_pass_c_ct<T, A, N, false, NT, false>);
   int grid = 0;
   FX_TRY(ct_prepare(ctx, kern, NT, lds, items, true, &grid));
   if (role)
