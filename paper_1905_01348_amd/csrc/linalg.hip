@@ -26,86 +26,111 @@ FX_HD z zfma(z acc, z a, z b) {
 }
 
 // ---------------------------------------------------------------------------
-// zgemm: 64x64 output tile per 256-thread workgroup, K steps of 8, each
-// thread owns a 4x4 block of outputs (rows tx + 16 i, cols ty + 16 j).
+// zgemm: 128x64 output tile per 256-thread workgroup, K steps of 8; each
+// thread owns an 8x4 block of outputs (rows tx + 16 i, cols ty + 16 j), so
+// one LDS read feeds 2.7 complex multiply-adds.  The next K step's tiles are
+// loaded into registers while the current one is multiplied out of the other
+// half of a double-buffered LDS, one barrier per step.
 // Split over K: blockIdx.z = batch * nsplit + split; split s covers
 // K range [s*kchunk, min(K, (s+1)*kchunk)).  With a partial buffer the raw
 // sum of split s goes to partial[(batch*nsplit + s) * M*N] (ld M); without
 // one (nsplit == 1) the result C = alpha*sum + beta*C is written directly.
 // ---------------------------------------------------------------------------
-constexpr int ZB = 64, ZK = 8;
+constexpr int ZBM = 128, ZBN = 64, ZK = 8;
 
 template <int OPA, int OPB>
 __global__ void __launch_bounds__(256) k_zgemm(int M, int N, int K, const z* __restrict__ A, int64_t lda,
                                                int64_t sA, const z* __restrict__ B, int64_t ldb, int64_t sB,
                                                z* C, int64_t ldc, int64_t sC, z alpha, z beta, int nsplit,
                                                int kchunk, z* __restrict__ partial) {
-  __shared__ z As[ZK][ZB + 1];
-  __shared__ z Bs[ZK][ZB + 1];
+  __shared__ z As[2][ZK][ZBM + 1];
+  __shared__ z Bs[2][ZK][ZBN + 1];
   const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
-  const int m0 = blockIdx.x * ZB, n0 = blockIdx.y * ZB;
+  const int m0 = blockIdx.x * ZBM, n0 = blockIdx.y * ZBN;
   const int bz = blockIdx.z, batch = bz / nsplit, split = bz % nsplit;
   A += batch * sA;
   B += batch * sB;
   const int kbeg = split * kchunk, kend = min(K, kbeg + kchunk);
-  z acc[4][4];
+  // staged loads: the A tile (128 x 8) is 4 elements per thread, the B tile
+  // (8 x 64) 2; op C reads along k (column of the stored matrix).  Element
+  // u of this thread sits at (row a_m(u), step a_k(u)) of the A tile and at
+  // (step b_k(u), column b_n(u)) of the B tile.
+  const auto a_m = [tid](int u) { return OPA == 0 ? (tid + 256 * u) % ZBM : (tid + 256 * u) / ZK; };
+  const auto a_k = [tid](int u) { return OPA == 0 ? (tid + 256 * u) / ZBM : (tid + 256 * u) % ZK; };
+  const auto b_n = [tid](int u) { return OPB == 0 ? (tid + 256 * u) / ZK : (tid + 256 * u) % ZBN; };
+  const auto b_k = [tid](int u) { return OPB == 0 ? (tid + 256 * u) % ZK : (tid + 256 * u) / ZBN; };
+  z ra0, ra1, ra2, ra3, rb0, rb1;
+#define FX_ZG_LOAD_A(u, dst)                                                                     \
+  {                                                                                              \
+    const int m = m0 + a_m(u), k = k0n + a_k(u);                                                \
+    dst = z{0.0, 0.0};                                                                           \
+    if (m < M && k < kend) dst = OPA == 0 ? A[m + (int64_t)k * lda] : zconj(A[k + (int64_t)m * lda]); \
+  }
+#define FX_ZG_LOAD_B(u, dst)                                                                     \
+  {                                                                                              \
+    const int n = n0 + b_n(u), k = k0n + b_k(u);                                                \
+    dst = z{0.0, 0.0};                                                                           \
+    if (n < N && k < kend) dst = OPB == 0 ? B[k + (int64_t)n * ldb] : zconj(B[n + (int64_t)k * ldb]); \
+  }
+#define FX_ZG_GLOAD()      \
+  FX_ZG_LOAD_A(0, ra0);    \
+  FX_ZG_LOAD_A(1, ra1);    \
+  FX_ZG_LOAD_A(2, ra2);    \
+  FX_ZG_LOAD_A(3, ra3);    \
+  FX_ZG_LOAD_B(0, rb0);    \
+  FX_ZG_LOAD_B(1, rb1);
+#define FX_ZG_SSTORE(bf)                  \
+  As[bf][a_k(0)][a_m(0)] = ra0;           \
+  As[bf][a_k(1)][a_m(1)] = ra1;           \
+  As[bf][a_k(2)][a_m(2)] = ra2;           \
+  As[bf][a_k(3)][a_m(3)] = ra3;           \
+  Bs[bf][b_k(0)][b_n(0)] = rb0;           \
+  Bs[bf][b_k(1)][b_n(1)] = rb1;
+  z acc[8][4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 8; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = z{0.0, 0.0};
-  for (int k0 = kbeg; k0 < kend; k0 += ZK) {
-    // A tile: rows m0..m0+63, k0..k0+7  (512 elements, 2 per thread)
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int t = tid + 256 * u;
-      int mm, kk;
-      if (OPA == 0) {
-        mm = t % ZB;
-        kk = t / ZB;
-      } else {
-        kk = t % ZK;
-        mm = t / ZK;
-      }
-      const int m = m0 + mm, k = k0 + kk;
-      z v = {0.0, 0.0};
-      if (m < M && k < kend) v = OPA == 0 ? A[m + (int64_t)k * lda] : zconj(A[k + (int64_t)m * lda]);
-      As[kk][mm] = v;
-    }
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const int t = tid + 256 * u;
-      int nn, kk;
-      if (OPB == 0) {
-        kk = t % ZK;
-        nn = t / ZK;
-      } else {
-        nn = t % ZB;
-        kk = t / ZB;
-      }
-      const int n = n0 + nn, k = k0 + kk;
-      z v = {0.0, 0.0};
-      if (n < N && k < kend) v = OPB == 0 ? B[k + (int64_t)n * ldb] : zconj(B[n + (int64_t)k * ldb]);
-      Bs[kk][nn] = v;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < ZK; ++kk) {
-      z a[4], b[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kk][tx + 16 * i];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][ty + 16 * j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = zfma(acc[i][j], a[i], b[j]);
-    }
-    __syncthreads();
+  if (kbeg < kend) {
+    const int k0n = kbeg;
+    FX_ZG_GLOAD();
+    FX_ZG_SSTORE(0);
   }
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = kbeg; k0 < kend; k0 += ZK) {
+    const bool more = k0 + ZK < kend;
+    if (more) {
+      const int k0n = k0 + ZK;
+      FX_ZG_GLOAD();
+    }
+#pragma unroll 2
+    for (int kk = 0; kk < ZK; ++kk) {
+      z b[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Bs[buf][kk][ty + 16 * j];
+      // one A element live at a time keeps the 8x4 accumulators in registers
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const z a = As[buf][kk][tx + 16 * i];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = zfma(acc[i][j], a, b[j]);
+      }
+    }
+    if (more) {
+      FX_ZG_SSTORE(buf ^ 1);
+    }
+    __syncthreads();
+    buf ^= 1;
+  }
+#undef FX_ZG_SSTORE
+#undef FX_ZG_GLOAD
+#undef FX_ZG_LOAD_B
+#undef FX_ZG_LOAD_A
   if (partial) {
     z* P = partial + (int64_t)bz * M * N;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 8; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int m = m0 + tx + 16 * i, n = n0 + ty + 16 * j;
@@ -115,7 +140,7 @@ __global__ void __launch_bounds__(256) k_zgemm(int M, int N, int K, const z* __r
     z* Cb = C + batch * sC;
     const bool bz0 = beta.x == 0.0 && beta.y == 0.0;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 8; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int m = m0 + tx + 16 * i, n = n0 + ty + 16 * j;
@@ -156,7 +181,7 @@ fx_status zgemm(fx_ctx* ctx, Workspace* ws, hipStream_t st, int opa, int opb, in
     FX_LAUNCH_CHECK();
     return FX_OK;
   }
-  const int tiles = ((M + ZB - 1) / ZB) * ((N + ZB - 1) / ZB) * batch;
+  const int tiles = ((M + ZBM - 1) / ZBM) * ((N + ZBN - 1) / ZBN) * batch;
   int nsplit = nsplit_hint;
   if (nsplit <= 0) {
     // enough workgroups to fill the chip, each with at least 512 K-steps
@@ -172,7 +197,7 @@ fx_status zgemm(fx_ctx* ctx, Workspace* ws, hipStream_t st, int opa, int opb, in
     FX_TRY(ws_get(ctx, ws, "zgemm_part", sizeof(z) * (size_t)M * N * nsplit * batch, &p));
     part = (z*)p;
   }
-  dim3 grid((M + ZB - 1) / ZB, (N + ZB - 1) / ZB, nsplit * batch);
+  dim3 grid((M + ZBM - 1) / ZBM, (N + ZBN - 1) / ZBN, nsplit * batch);
   int slot;
   FX_TRY(prof_begin(ctx, st, opa ? FX_K_GEMM_CN : FX_K_GEMM_NN, 8.0 * M * N * (double)K * batch, &slot));
 #define FX_ZG(a, b)                                                                                                 \

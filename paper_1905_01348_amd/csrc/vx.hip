@@ -416,7 +416,7 @@ static fx_status run_halved(fx_ctx* ctx, Workspace* ws, const VxArgs& a, const G
                     tb->fold[0], tri, a.a_pipe > 0 ? 1 : 0, (a.b_var == 2 || a.b_var == 3) ? a.b_var : 1, ct_c_variant(a), a.a_var == 2 ? 2 : 1, a.nt_hint != 0 ? 1 : 0};
       const double vol = (double)npairs * nr * sz;
       int slot;
-      FX_TRY(prof_begin(ctx, st, FX_K_VX_PLANE_FWD, 3.0 * vol, &slot));
+      FX_TRY(prof_begin(ctx, st, FX_K_VX_PLANE_FWD, 2.0 * vol, &slot));
       FX_TRY(ct_pass_a<T>(ctx, st, n, cb));
       FX_TRY(prof_end(ctx, st, slot));
       FX_TRY(prof_begin(ctx, st, FX_K_VX_PENCIL_Z, 2.0 * vol, &slot));
@@ -531,7 +531,10 @@ static fx_status run_batches(fx_ctx* ctx, Workspace* ws, const VxArgs& a, const 
       const int jb = std::min(nj, a.n_psi - j0);
       const int first = j0 == 0, last = j0 + jb >= a.n_psi;
       const int npairs = kb * jb;
-      // algorithmic bytes of each pass (see the pass descriptions)
+      // algorithmic bytes of each pass, per pair and grid point: plane-forward
+      // psi_j + T (phi_k is reused from cache across the batch's orbitals),
+      // z-pass T read + write, plane-inverse T + psi_j, plus the partial sums
+      // read and written once per batch and target
       const double vol = (double)npairs * nr * sizeof(cpx<T>);
       const double accb = (double)kb * nr *
                           ((first ? 0.0 : (double)sizeof(cpx<A>)) +
@@ -541,7 +544,7 @@ static fx_status run_batches(fx_ctx* ctx, Workspace* ws, const VxArgs& a, const 
         CtBatch<T> cb{psi, ld_psi, phi, ld_phi, reinterpret_cast<cpx<T>*>(work), j0, jb, k0, kb, npairs, twx, kf,
                       tb->fold[0], 0, a.a_pipe > 0 ? 1 : 0, (a.b_var == 2 || a.b_var == 3) ? a.b_var : 1, ct_c_variant(a), a.a_var == 2 ? 2 : 1, a.nt_hint != 0 ? 1 : 0};
         CtAcc<A> ca{acc, ld_acc, first, a.out, a.ld_out, out_c64 ? 1 : 0, last, a.pipe};
-        FX_TRY(prof_begin(ctx, st, FX_K_VX_PLANE_FWD, 3.0 * vol, &slot));
+        FX_TRY(prof_begin(ctx, st, FX_K_VX_PLANE_FWD, 2.0 * vol, &slot));
         FX_TRY(ct_pass_a<T>(ctx, st, g.nx, cb));
         FX_TRY(prof_end(ctx, st, slot));
         FX_TRY(prof_begin(ctx, st, FX_K_VX_PENCIL_Z, 2.0 * vol, &slot));
@@ -553,7 +556,7 @@ static fx_status run_batches(fx_ctx* ctx, Workspace* ws, const VxArgs& a, const 
         launches += 3;
         continue;
       }
-      FX_TRY(prof_begin(ctx, st, FX_K_VX_PLANE_FWD, 3.0 * vol, &slot));
+      FX_TRY(prof_begin(ctx, st, FX_K_VX_PLANE_FWD, 2.0 * vol, &slot));
       FX_EPT_SWITCH(ept_p, {
         auto kern = k_pass_a<T, E>;
         FX_TRY(allow_lds(kern, lds_plane));

@@ -8,9 +8,9 @@
         -> a Markdown table of calibrated DRAM bytes per dispatch for several kernels.
 
     python -m paper_1905_01348_amd.rocprof_summary counters --fetch <dir> --write <dir>
-           --copy-fetch <dir> --copy-write <dir> --kernel <substring> --prec <p> --source-hash <h>
-           [--name <library kernel id>] [--out profiles/vx_counters.json] [--command C]
-        -> HBM traffic per launch of one kernel from FETCH_SIZE and WRITE_SIZE
+           --copy-fetch <dir> --copy-write <dir> --kernels a,b --names id_a,id_b --prec <p> --source-hash <h>
+           [--out profiles/vx_counters.json] [--command C]
+        -> HBM traffic per launch of each kernel from FETCH_SIZE and WRITE_SIZE
            (KiB per dispatch), each scaled by the factor that makes a plain
            1 GiB device copy read and write exactly 1 GiB.
 
@@ -76,25 +76,27 @@ def _per_dispatch(rows):
     return acc
 
 
-def counters(fetch, write, copy_fetch, copy_write, kernel, prec, source_hash, command=None, name=None):
+def counters(fetch, write, copy_fetch, copy_write, kernels, names, prec, source_hash, command=None):
+    """Copy-calibrated DRAM bytes per launch for each kernel (name substring -> library id)."""
     one_gib_kib = float(1 << 20)
     # calibration: the largest dispatch of the copy run is the 1 GiB copy
     cf = max(_per_dispatch(_counter_rows(copy_fetch, "FETCH_SIZE")).values())
     cw = max(_per_dispatch(_counter_rows(copy_write, "WRITE_SIZE")).values())
     sf, sw = one_gib_kib / cf, one_gib_kib / cw
-    f = [v for (d, n), v in _per_dispatch(_counter_rows(fetch, "FETCH_SIZE")).items() if kernel in n]
-    w = [v for (d, n), v in _per_dispatch(_counter_rows(write, "WRITE_SIZE")).items() if kernel in n]
-    if not f or not w:
-        raise ValueError(f"kernel {kernel!r} not found in the counter runs")
-    fetch_b = sum(f) / len(f) * 1024 * sf
-    write_b = sum(w) / len(w) * 1024 * sw
-    return {
-        "kernel": kernel, "name": name, "prec": prec, "source_hash": source_hash,
-        "fetch_bytes_per_launch": fetch_b, "write_bytes_per_launch": write_b,
-        "bytes_per_launch": fetch_b + write_b,
-        "copy_scale_fetch": sf, "copy_scale_write": sw, "launches": [len(f), len(w)],
-        "command": command,
-    }
+    fr = _per_dispatch(_counter_rows(fetch, "FETCH_SIZE"))
+    wr = _per_dispatch(_counter_rows(write, "WRITE_SIZE"))
+    out = {}
+    for kernel, name in zip(kernels, names):
+        f = [v for (d, n), v in fr.items() if kernel in n]
+        w = [v for (d, n), v in wr.items() if kernel in n]
+        if not f or not w:
+            raise ValueError(f"kernel {kernel!r} not found in the counter runs")
+        fetch_b = sum(f) / len(f) * 1024 * sf
+        write_b = sum(w) / len(w) * 1024 * sw
+        out[name] = {"kernel": kernel, "fetch_bytes_per_launch": fetch_b, "write_bytes_per_launch": write_b,
+                     "bytes_per_launch": fetch_b + write_b, "launches": [len(f), len(w)]}
+    return {"prec": prec, "source_hash": source_hash, "copy_scale_fetch": sf, "copy_scale_write": sw,
+            "kernels": out, "command": command}
 
 
 def traffic_table(fetch, write, copy_fetch, copy_write, kernels, title=None, command=None, durations=None):
@@ -143,9 +145,11 @@ def main(argv=None):
     s.add_argument("--title")
     s.add_argument("--command")
     c = sub.add_parser("counters")
-    for k in ("--fetch", "--write", "--copy-fetch", "--copy-write", "--kernel", "--prec", "--source-hash"):
+    for k in ("--fetch", "--write", "--copy-fetch", "--copy-write", "--prec", "--source-hash"):
         c.add_argument(k, required=True)
-    c.add_argument("--name", help="the library's id of the kernel (fock_prof.h), e.g. vx_plane_fwd")
+    c.add_argument("--kernels", required=True, help="comma-separated kernel name substrings")
+    c.add_argument("--names", required=True,
+                   help="comma-separated library ids of the same kernels (fock_prof.h), e.g. vx_plane_fwd")
     c.add_argument("--out")
     c.add_argument("--command")
     t = sub.add_parser("traffic")
@@ -162,8 +166,8 @@ def main(argv=None):
         sys.stdout.write(traffic_table(a.fetch, a.write, a.copy_fetch, a.copy_write, a.kernels.split(","), a.title,
                                        a.command, a.durations))
     else:
-        res = counters(a.fetch, a.write, a.copy_fetch, a.copy_write, a.kernel, a.prec, a.source_hash, a.command,
-                       a.name)
+        res = counters(a.fetch, a.write, a.copy_fetch, a.copy_write, a.kernels.split(","), a.names.split(","),
+                       a.prec, a.source_hash, a.command)
         txt = json.dumps(res, indent=1)
         if a.out:
             open(a.out, "w").write(txt + "\n")
