@@ -201,7 +201,10 @@ typedef struct fx_vx_config {
  * served request of that grid, precision and form uses it.  Each candidate
  * is timed on a probe of at most ~2 full batches of pairs with HIP events on
  * `stream`; the call waits for the device.  *best (nullable) receives the
- * winner and *best_ms_per_kpair (nullable) its time per 1000 pair solves.
+ * winner and *best_ms_per_kpair (nullable) its time per 1000 logical pairs
+ * (j, k) of the probe.  The context's workspace is released at the end (the
+ * candidates grew it to the largest batch tried): graphs captured from this
+ * context before must not be replayed afterwards.
  * Errors: FX_ERR_INVALID, FX_ERR_UNSUPPORTED, FX_ERR_OOM, FX_ERR_DEVICE.
  */
 fx_status fx_vx_autotune(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* kernel, int32_t n_psi, int32_t n_phi,

@@ -140,7 +140,10 @@ static fx_status autotune(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* ker
       hipLaunchKernelGGL(k_fill_probe<float>, dim3(1024), dim3(256), 0, st, (cpx<float>*)phi, (int64_t)np_phi * nr,
                          (uint64_t)67890, (float)scale);
   }
-  FX_LAUNCH_CHECK();
+  if (hipGetLastError() != hipSuccess) {
+    ws_release(ctx, &tws);
+    FX_FAIL(FX_ERR_DEVICE, "launch of the probe filler failed");
+  }
 
   VxArgs base;
   base.cell = cell;

@@ -282,3 +282,63 @@ def test_halved_energy_and_hermitian_projection(ctx):
     assert abs(ex.item() - ex_ref) <= 1e-12 * abs(ex_ref)
     M = psi.reshape(N, -1).conj() @ got.reshape(N, -1).T
     assert np.abs(M - M.conj().T).max() <= 1e-12 * np.abs(M).max()
+
+
+@pytest.mark.parametrize("N,Nt,square", [(1, 1, True), (2, 2, True), (1, 3, False), (7, 1, False)])
+def test_degenerate_counts_on_a_workload_edge(ctx, N, Nt, square):
+    """One or two orbitals, one target: the halved path's single diagonal batch (and its empty
+    second role), and the rectangular path with a single orbital or target."""
+    n, L = 24, 10.26
+    psi = synth.make_orbitals(90 + N, n, L, N)
+    phi = psi if square else synth.random_grid_vectors(91, n, Nt)
+    ref = oracle.apply_vx(psi, phi, n, L, "hse", 0.106)
+    P = dev(psi)
+    for prec, tol in (("fp64", TOL64), ("fp32acc64", TOL32)):
+        got = host(ctx.apply_vx(P, None if square else dev(phi), n=n, L=L, kernel="hse", prec=prec))
+        assert col_err(got, ref) <= tol, (prec, N, Nt)
+
+
+@pytest.mark.parametrize("square", [True, False])
+def test_padded_leading_dimensions_on_a_workload_edge(ctx, square):
+    """FP64 blocks are read in place (no conversion copy): padded column strides on the
+    specialised kernels, halved and not; the padding of out stays untouched."""
+    import ctypes as C
+    import torch
+
+    from paper_1905_01348_amd import fock as F
+
+    n, L, N, Nt = 24, 10.26, 9, 4
+    nr = n ** 3
+    psi = synth.make_orbitals(95, n, L, N)
+    phi = psi if square else synth.random_grid_vectors(96, n, Nt)
+    nt = N if square else Nt
+    ref = oracle.apply_vx(psi, phi, n, L, "hse", 0.106).reshape(nt, nr)
+    Pp = torch.zeros((N, nr + 11), dtype=torch.complex128, device="cuda")
+    Pp[:, :nr] = dev(psi.reshape(N, nr))
+    if square:
+        Qp, ldq = Pp, nr + 11
+    else:
+        Qp = torch.zeros((Nt, nr + 5), dtype=torch.complex128, device="cuda")
+        Qp[:, :nr] = dev(phi.reshape(Nt, nr))
+        ldq = nr + 5
+    O = torch.full((nt, nr + 3), complex(5.0, 5.0), dtype=torch.complex128, device="cuda")
+    cell, kern = F.make_cell(n, L), F.make_kernel("hse", 0.106)
+    st = F.load().fx_apply_vx(ctx.h, C.byref(cell), C.byref(kern), Pp.data_ptr(), N, nr + 11, Qp.data_ptr(), nt, ldq,
+                              O.data_ptr(), nr + 3, F.FX_C128, F.FX_C128, F.PREC["fp64"],
+                              C.c_void_p(torch.cuda.current_stream().cuda_stream), None)
+    assert st == 0, F.load().fx_last_error()
+    torch.cuda.synchronize()
+    assert col_err(host(O[:, :nr]), ref) <= TOL64
+    assert np.all(host(O[:, nr:]) == complex(5.0, 5.0))
+
+
+def test_empty_blocks_rejected(ctx):
+    import torch
+    from paper_1905_01348_amd import FockError
+
+    P = torch.zeros((0, 24, 24, 24), dtype=torch.complex128, device="cuda")
+    Q = torch.zeros((2, 24, 24, 24), dtype=torch.complex128, device="cuda")
+    for a, b in ((P, Q), (Q, P)):
+        with pytest.raises(FockError) as ei:
+            ctx.apply_vx(a, b, n=24, L=10.26, prec="fp64")
+        assert ei.value.status == -1
