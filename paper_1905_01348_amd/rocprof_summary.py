@@ -14,6 +14,9 @@
            (KiB per dispatch), each scaled by the factor that makes a plain
            1 GiB device copy read and write exactly 1 GiB.
 
+    python -m paper_1905_01348_amd.rocprof_summary table <dir> [<dir> ...] --kernels a,b,c
+        -> a Markdown table of the mean of every counter per dispatch for each kernel.
+
 Input directories are rocprofv3 -d output folders written with
 --output-format csv (the counter runs produce *counter_collection.csv).
 """
@@ -137,6 +140,36 @@ def traffic_table(fetch, write, copy_fetch, copy_write, kernels, title=None, com
     return "\n".join(out) + "\n"
 
 
+def counter_table(dirs, kernels, title=None, command=None):
+    """Markdown table: mean of every counter per dispatch, for each kernel (name substring),
+    over one or more rocprofv3 --pmc output folders."""
+    vals = {}
+    for d in dirs:
+        path = _find(d, "*counter_collection.csv")
+        per = {}
+        for r in csv.DictReader(open(path)):
+            name = r.get("Kernel_Name", r.get("Kernel-Name", ""))
+            k = next((k for k in kernels if k in name), None)
+            if k is None:
+                continue
+            c = r.get("Counter_Name", r.get("Counter-Name", ""))
+            disp = r.get("Dispatch_Id", r.get("Dispatch-Id", ""))
+            per.setdefault((k, c), {}).setdefault(disp, 0.0)
+            per[(k, c)][disp] += float(r.get("Counter_Value", r.get("Counter-Value", 0)))
+        for (k, c), byd in per.items():
+            vals.setdefault(c, {})[k] = sum(byd.values()) / len(byd)
+    out = []
+    if title:
+        out.append(f"# {title}\n")
+    if command:
+        out.append(f"Commands:\n\n```\n{command}\n```\n")
+    out.append("| counter (mean per dispatch) | " + " | ".join(f"`{k}`" for k in kernels) + " |")
+    out.append("|---|" + "---|" * len(kernels))
+    for c in sorted(vals):
+        out.append(f"| {c} | " + " | ".join(f"{vals[c].get(k, float('nan')):.4g}" for k in kernels) + " |")
+    return "\n".join(out) + "\n"
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -159,7 +192,15 @@ def main(argv=None):
     t.add_argument("--durations")
     t.add_argument("--title")
     t.add_argument("--command")
+    q = sub.add_parser("table")
+    q.add_argument("dirs", nargs="+")
+    q.add_argument("--kernels", required=True, help="comma-separated name substrings")
+    q.add_argument("--title")
+    q.add_argument("--command")
     a = ap.parse_args(argv)
+    if a.cmd == "table":
+        sys.stdout.write(counter_table(a.dirs, a.kernels.split(","), a.title, a.command))
+        return
     if a.cmd == "stats":
         sys.stdout.write(stats(a.csv, a.title, a.command))
     elif a.cmd == "traffic":
