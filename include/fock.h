@@ -176,8 +176,11 @@ typedef struct fx_vx_config {
                           registers, 0 two workgroups per CU instead, -1 automatic (0) */
   int32_t b_variant;   /* specialised z pass x-tile: 1 the edge's default, 2 half of it,
                           3 whole x rows */
-  int32_t c_variant;   /* specialised plane-inverse pass threads: 1 the edge's default,
-                          2 a larger count (fewer accumulators per thread, more waves) */
+  int32_t c_variant;   /* specialised plane-inverse pass: 1 the edge's default threads,
+                          2 a larger count (fewer accumulators per thread, more waves),
+                          3 and 4: 2 and 1 with the next work plane copied into LDS
+                          while the current one is transformed (where two planes fit
+                          the LDS: not FP64 at 72 and 96, which run 2 and 1 instead) */
   int32_t a_variant;   /* specialised plane-forward pass threads: 1 the edge's default,
                           2 a count that divides the butterflies evenly */
   int32_t nt_hint;     /* specialised kernels: 1 read and write the pair volume with

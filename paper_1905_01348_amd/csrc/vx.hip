@@ -363,8 +363,20 @@ static bool pick_ept(int elems, int max_thr, int* ept, int* nthr) {
 // choice at 96^3, where it measured faster (3.34 vs 3.39 ms per launch of
 // 1170 pairs); elsewhere the autotuner decides.
 static int ct_c_variant(const VxArgs& a) {
-  if (a.c_var == 1 || a.c_var == 2) return a.c_var;
+  if (a.c_var >= 1 && a.c_var <= 4) return a.c_var;
   return a.cell->n[0] == 96 ? 2 : 1;
+}
+
+// How the XCDs share the items of the persistent plane passes (bit 0: the
+// plane-forward pass, bit 1: the plane-inverse pass; set: each XCD takes a
+// contiguous range of z planes of every unit, clear: a contiguous range of
+// units at every z).  The plane-forward pass reads each orbital and target
+// plane once per XCD with the z split instead of once per XCD per chunk of
+// pairs (3.05 -> 2.82 ms per launch of 1170 pairs at 96^3); the plane-inverse
+// pass measured slower with it (3.13 -> 3.30 ms), so it keeps the unit split.
+static int ct_zsplit() {
+  const char* e = getenv("FX_VX_ZSPLIT");
+  return e ? atoi(e) : 1;
 }
 
 // Halved apply for phi == psi (all N targets): each unordered pair {j, k} is
@@ -413,7 +425,7 @@ static fx_status run_halved(fx_ctx* ctx, Workspace* ws, const VxArgs& a, const G
       const int tri = J == K;
       const int npairs = tri ? jb * (jb + 1) / 2 : jb * kb;
       CtBatch<T> cb{psi, ld_psi, psi, ld_psi, reinterpret_cast<cpx<T>*>(work), j0, jb, k0, kb, npairs, tw, kf,
-                    tb->fold[0], tri, a.a_pipe > 0 ? 1 : 0, (a.b_var == 2 || a.b_var == 3) ? a.b_var : 1, ct_c_variant(a), a.a_var == 2 ? 2 : 1, a.nt_hint != 0 ? 1 : 0};
+                    tb->fold[0], tri, a.a_pipe > 0 ? 1 : 0, (a.b_var == 2 || a.b_var == 3) ? a.b_var : 1, ct_c_variant(a), a.a_var == 2 ? 2 : 1, a.nt_hint != 0 ? 1 : 0, ct_zsplit()};
       const double vol = (double)npairs * nr * sz;
       int slot;
       FX_TRY(prof_begin(ctx, st, FX_K_VX_PLANE_FWD, 2.0 * vol, &slot));
@@ -542,7 +554,7 @@ static fx_status run_batches(fx_ctx* ctx, Workspace* ws, const VxArgs& a, const 
       int slot;
       if (use_ct) {
         CtBatch<T> cb{psi, ld_psi, phi, ld_phi, reinterpret_cast<cpx<T>*>(work), j0, jb, k0, kb, npairs, twx, kf,
-                      tb->fold[0], 0, a.a_pipe > 0 ? 1 : 0, (a.b_var == 2 || a.b_var == 3) ? a.b_var : 1, ct_c_variant(a), a.a_var == 2 ? 2 : 1, a.nt_hint != 0 ? 1 : 0};
+                      tb->fold[0], 0, a.a_pipe > 0 ? 1 : 0, (a.b_var == 2 || a.b_var == 3) ? a.b_var : 1, ct_c_variant(a), a.a_var == 2 ? 2 : 1, a.nt_hint != 0 ? 1 : 0, ct_zsplit()};
         CtAcc<A> ca{acc, ld_acc, first, a.out, a.ld_out, out_c64 ? 1 : 0, last, a.pipe};
         FX_TRY(prof_begin(ctx, st, FX_K_VX_PLANE_FWD, 2.0 * vol, &slot));
         FX_TRY(ct_pass_a<T>(ctx, st, g.nx, cb));

@@ -32,7 +32,8 @@ struct VxArgs {
   int kernels = 0;  // 1 specialised (cubic workload edges only), 2 generic, 0 automatic
   int a_pipe = -1;  // specialised plane-forward pass: 1 register prefetch, 0 two workgroups per CU
   int b_var = 0;    // specialised z pass tile: 1 default, 2 half, 3 whole rows, 0 automatic
-  int c_var = 0;    // specialised plane-inverse threads: 1 default, 2 second count, 0 automatic
+  int c_var = 0;    // specialised plane-inverse form: 1 default, 2 second thread count, 3/4 those with the
+                    // next plane staged in LDS, 0 automatic
   int a_var = 0;    // specialised plane-forward threads: 1 default, 2 second count, 0 automatic
   int nt_hint = -1;  // specialised kernels: non-temporal hints on the pair volume (1, 0, -1 automatic = 1)
   bool plans_set = false;  // generic kernels: radix schedules in `plans`
@@ -76,9 +77,10 @@ struct CtBatch {
   int tri;          // diagonal batch of a halved apply: pairs jj <= kk only, packed
   int a_pipe;       // plane-forward pass: register prefetch of the next plane
   int b_var;        // z pass: 1 default x tile, 2 half tile, 3 whole x rows
-  int c_var;        // plane-inverse pass: 1 default threads, 2 the second thread count
+  int c_var;        // plane-inverse pass: 1 default threads, 2 the second thread count, 3/4 staged
   int a_var;        // plane-forward pass: 1 default threads, 2 the second thread count
   int nts;          // the pair volume is read and written with non-temporal hints
+  int zsplit = 0;   // plane passes split over the XCDs by z (bit 0: forward, bit 1: inverse) or by unit
 };
 template <typename A>
 struct CtAcc {

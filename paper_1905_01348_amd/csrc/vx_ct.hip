@@ -37,37 +37,46 @@ FX_HD int plane_of(int jj, int kk, int nj, int tri) { return tri ? kk * (kk + 1)
 // Work of a persistent plane kernel: `units` (pairs, or targets) x N planes.
 // Workgroups are dispatched round-robin over the XCDs, so with a grid that is
 // a multiple of the XCD count workgroup b runs on XCD b % kXcds.  Each XCD
-// takes a contiguous chunk of the units and walks it z-major: the workgroups
-// of one XCD work on the same z at the same time and find that plane's input
-// data (orbital and target planes in pass A, orbital planes in pass C) in
-// their shared L2 instead of reading it again from HBM.
+// takes either a contiguous chunk of the units (zsplit 0) or a contiguous
+// range of N / kXcds planes of every unit (zsplit 1), and walks its share
+// z-major: the workgroups of one XCD work on the same z at the same time and
+// find that plane's input data (orbital and target planes in pass A, orbital
+// planes in pass C) in their shared L2 instead of reading it again from HBM.
+// With the z split no two XCDs read the same input plane.
 constexpr int kXcds = 8;
 
 struct ItemMap {
-  int u_lo, u_n, first, step, total;
+  int u_lo, u_n, z_lo, first, step, total;
   FX_HD void at(int li, int* unit, int* z) const {
-    *z = li / u_n;
-    *unit = u_lo + (li - *z * u_n);
+    const int zz = li / u_n;
+    *z = z_lo + zz;
+    *unit = u_lo + (li - zz * u_n);
   }
 };
 
 template <int N>
-__device__ inline ItemMap item_map(int units) {
+__device__ inline ItemMap item_map(int units, int zsplit) {
   ItemMap m;
   const int G = gridDim.x, b = blockIdx.x;
+  m.u_lo = 0;
+  m.u_n = units;
+  m.z_lo = 0;
+  m.first = b;
+  m.step = G;
+  m.total = units * N;
   if (G >= kXcds && G % kXcds == 0) {
     const int x = b % kXcds;
-    m.u_lo = (int)((int64_t)units * x / kXcds);
-    m.u_n = (int)((int64_t)units * (x + 1) / kXcds) - m.u_lo;
     m.first = b / kXcds;
     m.step = G / kXcds;
-  } else {
-    m.u_lo = 0;
-    m.u_n = units;
-    m.first = b;
-    m.step = G;
+    if (zsplit && N % kXcds == 0) {
+      m.z_lo = x * (N / kXcds);
+      m.total = units * (N / kXcds);
+    } else {
+      m.u_lo = (int)((int64_t)units * x / kXcds);
+      m.u_n = (int)((int64_t)units * (x + 1) / kXcds) - m.u_lo;
+      m.total = m.u_n * N;
+    }
   }
-  m.total = m.u_n * N;
   return m;
 }
 
@@ -84,7 +93,8 @@ template <typename T, int N, bool PIPE, int NT, bool NTS>
 __global__ void __launch_bounds__(NT, (PassAWaves<T, PIPE>::value)) k_pass_a_ct(const cpx<T>* __restrict__ psi, int64_t ld_psi,
                                                                   const cpx<T>* __restrict__ phi, int64_t ld_phi,
                                                                   cpx<T>* __restrict__ work, int j0, int nj, int k0,
-                                                                  int tri, int nitems, const cpx<T>* __restrict__ twg) {
+                                                                  int tri, int nitems, const cpx<T>* __restrict__ twg,
+                                                                  int zsplit) {
   constexpr int NXY = N * N, SX = N + 1, EPT = CeilDiv<NXY, NT>::value;
   constexpr size_t NR = (size_t)NXY * N;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -93,7 +103,7 @@ __global__ void __launch_bounds__(NT, (PassAWaves<T, PIPE>::value)) k_pass_a_ct(
   const int tid = threadIdx.x;
   for (int i = tid; i < N; i += NT) tw[i] = twg[i];
   cpx<T> va[EPT], vb[EPT];
-  const ItemMap im = item_map<N>(nitems / N);
+  const ItemMap im = item_map<N>(nitems / N, zsplit);
   auto fetch = [&](int li) __attribute__((always_inline)) {
     if (li >= im.total) return;
     int p, z;
@@ -196,6 +206,34 @@ __global__ void __launch_bounds__(NT) k_pass_b_ct(cpx<T>* __restrict__ work, con
   ct_stage_io<R0, false, T, N, N, XT, XT, 1, NT, false, true, N * N, 1, NTS>(s, nullptr, g0, tw, tid);
 }
 
+// Asynchronous copy of one N x N plane from global memory into LDS, 16 bytes
+// per lane (global_load_lds_dwordx4: lane i of a wave-instruction fills bytes
+// [16 i, 16 i + 16) after the wave-uniform LDS address, so only full waves
+// take part).  No registers hold the
+// data in flight; the copy completes on the wave's vector-memory counter, so a
+// reader waits for that counter to drain and then for a barrier.
+template <typename T, int N, int NT, bool NTS>
+__device__ inline void plane_to_lds(const cpx<T>* g, cpx<T>* lds, int tid) {
+  static_assert((N * N * sizeof(cpx<T>)) % 16 == 0, "plane bytes must be a multiple of 16");
+  constexpr int CH = (int)(N * N * sizeof(cpx<T>) / 16);  // 16-byte chunks
+  // full waves share the wave-instructions (a last partial wave does none)
+  constexpr int NW = NT / 64, WI = CeilDiv<CH, 64>::value;
+  static_assert(NW >= 1, "at least one full wave");
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+  if (NT % 64 != 0 && w >= NW) return;
+  const char* gb = reinterpret_cast<const char*>(g);
+  auto lb = (__attribute__((address_space(3))) char*)(reinterpret_cast<char*>(lds));
+#pragma unroll
+  for (int i = 0; i < CeilDiv<WI, NW>::value; ++i) {
+    const int wi = i * NW + w;
+    if (WI % NW == 0 || wi < WI) {
+      const int c = wi * 64 + lane;
+      if (CH % 64 == 0 || c < CH)
+        __builtin_amdgcn_global_load_lds(gb + (size_t)c * 16, lb + wi * 1024, 16, 0, NTS ? 2 : 0);
+    }
+  }
+}
+
 // ---- pass C: inverse FFT y and x, times psi_j, j-sum in registers --------------
 // One item = (target tt of the batch, plane z).  Role 0 (CONJ false): the
 // targets are the batch's k (output column t0 + kk) and the sum runs over its
@@ -204,21 +242,38 @@ __global__ void __launch_bounds__(NT) k_pass_b_ct(cpx<T>* __restrict__ work, con
 // runs over its k in ascending order, adding psi_{m0+kk} * conj(v_{jk}),
 // which is v_{kj} since the kernel is real and even.  On a diagonal batch
 // (tri) role 0 takes jj <= kk and role 1 kk > jj.
-template <typename T, typename A, int N, bool CONJ, int NT, bool NTS>
+// STG: the next work plane (this item's next term, or the next item's first)
+// is copied into a second LDS buffer while the current one is transformed, so
+// the first inverse stage reads LDS instead of waiting on HBM with the whole
+// workgroup (one workgroup per CU at 96^2, where the registers of the
+// accumulators leave LDS to spare).
+template <typename T, typename A, int N, bool CONJ, int NT, bool NTS, bool STG>
 __global__ void __launch_bounds__(NT) k_pass_c_ct(const cpx<T>* __restrict__ mult, int64_t ld_mult,
                                                                   const cpx<T>* __restrict__ work, int nj, int nk,
                                                                   int tri, int m0, int t0, int nitems, cpx<A>* acc,
                                                                   int64_t ld_acc, int first, void* out, int64_t ld_out,
-                                                                  int out_c64, int last, const cpx<T>* __restrict__ twg) {
+                                                                  int out_c64, int last, const cpx<T>* __restrict__ twg,
+                                                                  int zsplit) {
   constexpr int NXY = N * N, SX = N + 1, EPT = CeilDiv<NXY, NT>::value;
   constexpr size_t NR = (size_t)NXY * N;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* s = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* tw = s + N * SX;
+  cpx<T>* stg = tw + N;  // STG only: N*N staged work plane, 16-byte aligned
   const int tid = threadIdx.x;
   for (int i = tid; i < N; i += NT) tw[i] = twg[i];
   __syncthreads();
-  const ItemMap im = item_map<N>(nitems / N);
+  const ItemMap im = item_map<N>(nitems / N, zsplit);
+  // terms l in [lo, hi) of target tt
+  auto range = [&](int tt_, int* lo_, int* hi_) __attribute__((always_inline)) {
+    *lo_ = CONJ ? (tri ? tt_ + 1 : 0) : 0;
+    *hi_ = CONJ ? nk : (tri ? tt_ + 1 : nj);
+  };
+  auto plane_ptr = [&](int tt_, int l_, int z_) __attribute__((always_inline)) {
+    const int pl = CONJ ? plane_of(tt_, l_, nj, tri) : plane_of(l_, tt_, nj, tri);
+    return work + (size_t)pl * NR + (size_t)z_ * NXY;
+  };
+  bool staged = false;  // STG: stg holds (or is receiving) this item's first term
   for (int li = im.first; li < im.total; li += im.step) {
     int tt, z;
     im.at(li, &tt, &z);
@@ -232,19 +287,48 @@ __global__ void __launch_bounds__(NT) k_pass_c_ct(const cpx<T>* __restrict__ mul
       if (!first && (NXY % NT == 0 || e < NXY)) a[i] = acc[t * ld_acc + (size_t)z * NXY + e];
     }
     constexpr int R0 = Plan2<N>::R0, R1 = Plan2<N>::R1;
-    const int lo = CONJ ? (tri ? tt + 1 : 0) : 0;
-    const int hi = CONJ ? nk : (tri ? tt + 1 : nj);
+    int lo, hi;
+    range(tt, &lo, &hi);
     for (int l = lo; l < hi; ++l) {
-      const int pl = CONJ ? plane_of(tt, l, nj, tri) : plane_of(l, tt, nj, tri);
-      // first inverse y stage straight from the work plane
-      const cpx<T>* tp = work + (size_t)pl * NR + (size_t)z * NXY;
-      ct_stage_io<R1, false, T, N, R1, N, SX, 1, NT, true, false, N, 1, NTS>(s, tp, nullptr, tw, tid);
-      __syncthreads();
       const cpx<T>* pm = mult + (int64_t)(m0 + l) * ld_mult + (size_t)z * NXY;
+      if (STG) {
+        if (!staged) plane_to_lds<T, N, NT, NTS>(plane_ptr(tt, l, z), stg, tid);
+        __builtin_amdgcn_s_waitcnt(0);  // this wave's part of the copy has landed
+        __syncthreads();                // ... and every other wave's
+        // first inverse y stage from the staged plane
+        ct_stage_io<R1, false, T, N, R1, N, SX, 1, NT, true, false, N, 1, false>(s, stg, nullptr, tw, tid);
+        __syncthreads();  // stg is free again
+        // orbital plane first: waiting for it must not wait for the copy below
 #pragma unroll
-      for (int i = 0; i < EPT; ++i) {
-        const int e = tid + i * NT;
-        if (NXY % NT == 0 || e < NXY) vp[i] = pm[e];
+        for (int i = 0; i < EPT; ++i) {
+          const int e = tid + i * NT;
+          if (NXY % NT == 0 || e < NXY) vp[i] = pm[e];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        // start copying the next term: this item's, else the next item's first
+        staged = false;
+        if (l + 1 < hi) {
+          plane_to_lds<T, N, NT, NTS>(plane_ptr(tt, l + 1, z), stg, tid);
+          staged = true;
+        } else if (li + im.step < im.total) {
+          int tt2, z2, lo2, hi2;
+          im.at(li + im.step, &tt2, &z2);
+          range(tt2, &lo2, &hi2);
+          if (lo2 < hi2) {
+            plane_to_lds<T, N, NT, NTS>(plane_ptr(tt2, lo2, z2), stg, tid);
+            staged = true;
+          }
+        }
+      } else {
+        // first inverse y stage straight from the work plane
+        ct_stage_io<R1, false, T, N, R1, N, SX, 1, NT, true, false, N, 1, NTS>(s, plane_ptr(tt, l, z), nullptr, tw,
+                                                                              tid);
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+          const int e = tid + i * NT;
+          if (NXY % NT == 0 || e < NXY) vp[i] = pm[e];
+        }
       }
       ct_stage<R0, false, T, N, N, N, SX, 1, NT>(s, tw, tid);
       __syncthreads();
@@ -258,7 +342,9 @@ __global__ void __launch_bounds__(NT) k_pass_c_ct(const cpx<T>* __restrict__ mul
           a[i] = cadd(a[i], cmul(cpx<A>{(A)vp[i].x, (A)vp[i].y}, va));
         }
       }
-      __syncthreads();
+      // (STG: the barrier at the top of the next term orders these reads
+      // before the next writes of s)
+      if (!STG) __syncthreads();
     }
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
@@ -319,7 +405,7 @@ static fx_status pass_a_shape(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b) 
   int grid = 0;
   FX_TRY(ct_prepare(ctx, kern, NT, lds, items, true, &grid));
   hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, st, b.psi, b.ld_psi, b.phi, b.ld_phi, b.work, b.j0, b.nj, b.k0,
-                     b.tri, items, b.tw);
+                     b.tri, items, b.tw, b.zsplit & 1);
   FX_LAUNCH_CHECK();
   return FX_OK;
 }
@@ -360,20 +446,26 @@ static fx_status pass_b_n(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b) {
   return pass_b_shape<T, N, S::XT, S::NT_B>(ctx, st, b);
 }
 
-template <typename T, typename A, int N, int NT>
+// LDS of one plane-inverse workgroup (STG: with the staged next plane)
+template <typename T, int N>
+constexpr size_t pass_c_lds(bool stg) {
+  return ((size_t)N * (N + 1) + N + (stg ? (size_t)N * N : 0)) * sizeof(cpx<T>);
+}
+
+template <typename T, typename A, int N, int NT, bool STG>
 static fx_status pass_c_shape(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b, const CtAcc<A>& c, int role) {
-  const size_t lds = ((size_t)N * (N + 1) + N) * sizeof(cpx<T>);
+  const size_t lds = pass_c_lds<T, N>(STG);
   const int items = (role ? b.nj : b.nk) * N;
-  auto kern = role ? (b.nts ? k_pass_c_ct<T, A, N, true, NT, true> : k_pass_c_ct<T, A, N, true, NT, false>)
-                   : (b.nts ? k_pass_c_ct<T, A, N, false, NT, true> : k_pass_c_ct<T, A, N, false, NT, false>);
+  auto kern = role ? (b.nts ? k_pass_c_ct<T, A, N, true, NT, true, STG> : k_pass_c_ct<T, A, N, true, NT, false, STG>)
+                   : (b.nts ? k_pass_c_ct<T, A, N, false, NT, true, STG> : k_pass_c_ct<T, A, N, false, NT, false, STG>);
   int grid = 0;
   FX_TRY(ct_prepare(ctx, kern, NT, lds, items, true, &grid));
   if (role)
     hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, st, b.phi, b.ld_phi, (const cpx<T>*)b.work, b.nj, b.nk, b.tri,
-                       b.k0, b.j0, items, c.acc, c.ld_acc, c.first, c.out, c.ld_out, c.out_c64, c.last, b.tw);
+                       b.k0, b.j0, items, c.acc, c.ld_acc, c.first, c.out, c.ld_out, c.out_c64, c.last, b.tw, (b.zsplit >> 1) & 1);
   else
     hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, st, b.psi, b.ld_psi, (const cpx<T>*)b.work, b.nj, b.nk, b.tri,
-                       b.j0, b.k0, items, c.acc, c.ld_acc, c.first, c.out, c.ld_out, c.out_c64, c.last, b.tw);
+                       b.j0, b.k0, items, c.acc, c.ld_acc, c.first, c.out, c.ld_out, c.out_c64, c.last, b.tw, (b.zsplit >> 1) & 1);
   FX_LAUNCH_CHECK();
   return FX_OK;
 }
@@ -381,8 +473,12 @@ static fx_status pass_c_shape(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b, 
 template <typename T, typename A, int N>
 static fx_status pass_c_n(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b, const CtAcc<A>& c, int role) {
   using S = CubeShape<N>;
-  if (b.c_var == 2) return pass_c_shape<T, A, N, S::NT_C2>(ctx, st, b, c, role);
-  return pass_c_shape<T, A, N, S::NT_P>(ctx, st, b, c, role);
+  // the staged forms where the second plane fits the LDS (not FP64 at 72 and 96)
+  constexpr bool kStg = pass_c_lds<T, N>(true) <= kLdsPerCu;
+  if (b.c_var == 3 && kStg) return pass_c_shape<T, A, N, S::NT_C2, kStg>(ctx, st, b, c, role);
+  if (b.c_var == 4 && kStg) return pass_c_shape<T, A, N, S::NT_P, kStg>(ctx, st, b, c, role);
+  if (b.c_var == 2 || b.c_var == 3) return pass_c_shape<T, A, N, S::NT_C2, false>(ctx, st, b, c, role);
+  return pass_c_shape<T, A, N, S::NT_P, false>(ctx, st, b, c, role);
 }
 
 template <typename T>
