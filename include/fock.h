@@ -175,7 +175,10 @@ typedef struct fx_vx_config {
   int32_t a_prefetch;  /* specialised plane-forward pass: 1 prefetch the next plane into
                           registers, 0 two workgroups per CU instead, -1 automatic (0) */
   int32_t b_variant;   /* specialised z pass x-tile: 1 the edge's default, 2 half of it,
-                          3 whole x rows */
+                          3 whole x rows, 4 a persistent kernel (one y per workgroup,
+                          the next tile's loads issued ahead) with whole x rows where
+                          they fit the LDS (else the default tile); 0 automatic (4 at
+                          edge 96, else 1) */
   int32_t c_variant;   /* specialised plane-inverse pass: 1 the edge's default threads,
                           2 a larger count (fewer accumulators per thread, more waves),
                           3 and 4: 2 and 1 with the next work plane copied into LDS

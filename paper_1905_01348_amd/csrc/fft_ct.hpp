@@ -101,68 +101,109 @@ FX_HD void g_store(cpx<T>* p, cpx<T> a) {
   __builtin_nontemporal_store(v, reinterpret_cast<typename Vec2<T>::type*>(p));
 }
 
-// A stage that reads its inputs from global memory (FROM_G) and/or writes its
-// outputs to global memory (TO_G) instead of LDS.  In global memory element i
-// of transform f is g[f*GFS + i*GES]; in LDS it is s[f*FS + i*ES].  With
-// consecutive threads on consecutive transforms f and GFS = 1, both accesses
-// are coalesced.  Used for the first stage of a pass (data straight from
-// HBM) and its last stage (results straight to HBM), saving an LDS round
-// trip and a barrier at each end.
-template <int R, bool FWD, typename T, int N, int L, int COUNT, int ES, int FS, int NTHR, bool FROM_G, bool TO_G,
-          int GES, int GFS, bool NTS = false>
-FX_HD void ct_stage_io(cpx<T>* s, const cpx<T>* gin, cpx<T>* gout, const cpx<T>* tw, int tid) {
-  constexpr int SPAN = L / R, TOTAL = COUNT * (N / R), TSTEP = N / L;
-  constexpr int ITERS = (TOTAL + NTHR - 1) / NTHR;
-  cpx<T> x[ITERS][R];
-  // loads of every butterfly of this thread first, so they are all in flight
-#pragma unroll
-  for (int it = 0; it < ITERS; ++it) {
+// A stage split into its three parts, so that a kernel can issue a stage's
+// loads early (software pipelining): butterfly it of thread tid holds
+// elements x[it][0..R) at positions pos0 + m*SPAN of transform f.  In global
+// memory element i of transform f is g[f*GFS + i*GES]; in LDS it is
+// s[f*FS + i*ES].
+template <int R, int N, int COUNT, int NTHR>
+struct StageIters {
+  static constexpr int value = (COUNT * (N / R) + NTHR - 1) / NTHR;
+};
+
+template <int R, int N, int L, int COUNT, int NTHR>
+struct Bfly {
+  static constexpr int SPAN = L / R, TOTAL = COUNT * (N / R);
+  int f, i2, pos0;
+  bool ok;
+  FX_HD Bfly(int tid, int it) {
     const int b = tid + it * NTHR;
-    if (TOTAL % NTHR == 0 || b < TOTAL) {
-      const int f = b % COUNT;
-      const int q = b / COUNT;
-      const int blk = q / SPAN;
-      const int i2 = q - blk * SPAN;
-      const int pos0 = blk * L + i2;
+    ok = TOTAL % NTHR == 0 || b < TOTAL;
+    f = b % COUNT;
+    const int q = b / COUNT;
+    const int blk = q / SPAN;
+    i2 = q - blk * SPAN;
+    pos0 = blk * L + i2;
+  }
+};
+
+template <int R, typename T, int N, int L, int COUNT, int NTHR, bool FROM_G, int GES, int GFS, int ES, int FS,
+          bool NTS, int IT>
+FX_HD void ct_bfly_load(cpx<T> (&x)[IT][R], const cpx<T>* src, int tid) {
+  using B = Bfly<R, N, L, COUNT, NTHR>;
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const B b(tid, it);
+    if (b.ok) {
 #pragma unroll
       for (int m = 0; m < R; ++m) {
-        const int pos = pos0 + m * SPAN;
-        x[it][m] = FROM_G ? g_load<NTS>(gin + f * GFS + pos * GES) : s[f * FS + pos * ES];
+        const int pos = b.pos0 + m * B::SPAN;
+        x[it][m] = FROM_G ? g_load<NTS>(src + b.f * GFS + pos * GES) : src[b.f * FS + pos * ES];
       }
     }
   }
+}
+
+template <int R, bool FWD, typename T, int N, int L, int COUNT, int NTHR, int IT>
+FX_HD void ct_bfly_run(cpx<T> (&x)[IT][R], const cpx<T>* tw, int tid) {
+  using B = Bfly<R, N, L, COUNT, NTHR>;
+  constexpr int TSTEP = N / L;
 #pragma unroll
-  for (int it = 0; it < ITERS; ++it) {
-    const int b = tid + it * NTHR;
-    if (TOTAL % NTHR == 0 || b < TOTAL) {
-      const int f = b % COUNT;
-      const int q = b / COUNT;
-      const int blk = q / SPAN;
-      const int i2 = q - blk * SPAN;
-      const int pos0 = blk * L + i2;
+  for (int it = 0; it < IT; ++it) {
+    const B b(tid, it);
+    if (b.ok) {
       if (FWD) {
         Dft<R, -1, T>::run(x[it]);
-        if (SPAN > 1) {
+        if (B::SPAN > 1) {
 #pragma unroll
-          for (int k = 1; k < R; ++k) x[it][k] = cmul(x[it][k], tw[i2 * k * TSTEP]);
+          for (int k = 1; k < R; ++k) x[it][k] = cmul(x[it][k], tw[b.i2 * k * TSTEP]);
         }
       } else {
-        if (SPAN > 1) {
+        if (B::SPAN > 1) {
 #pragma unroll
-          for (int k = 1; k < R; ++k) x[it][k] = cmulc(x[it][k], tw[i2 * k * TSTEP]);
+          for (int k = 1; k < R; ++k) x[it][k] = cmulc(x[it][k], tw[b.i2 * k * TSTEP]);
         }
         Dft<R, 1, T>::run(x[it]);
       }
+    }
+  }
+}
+
+template <int R, typename T, int N, int L, int COUNT, int NTHR, bool TO_G, int GES, int GFS, int ES, int FS, bool NTS,
+          int IT>
+FX_HD void ct_bfly_store(cpx<T> (&x)[IT][R], cpx<T>* dst, int tid) {
+  using B = Bfly<R, N, L, COUNT, NTHR>;
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const B b(tid, it);
+    if (b.ok) {
 #pragma unroll
       for (int m = 0; m < R; ++m) {
-        const int pos = pos0 + m * SPAN;
+        const int pos = b.pos0 + m * B::SPAN;
         if (TO_G)
-          g_store<NTS>(gout + f * GFS + pos * GES, x[it][m]);
+          g_store<NTS>(dst + b.f * GFS + pos * GES, x[it][m]);
         else
-          s[f * FS + pos * ES] = x[it][m];
+          dst[b.f * FS + pos * ES] = x[it][m];
       }
     }
   }
+}
+
+// A stage that reads its inputs from global memory (FROM_G) and/or writes its
+// outputs to global memory (TO_G) instead of LDS.  With consecutive threads on
+// consecutive transforms f and GFS = 1, both global accesses are coalesced.
+// Used for the first stage of a pass (data straight from HBM) and its last
+// stage (results straight to HBM), saving an LDS round trip and a barrier at
+// each end.  The loads of every butterfly of the thread are issued first, so
+// they are all in flight together.
+template <int R, bool FWD, typename T, int N, int L, int COUNT, int ES, int FS, int NTHR, bool FROM_G, bool TO_G,
+          int GES, int GFS, bool NTS = false>
+FX_HD void ct_stage_io(cpx<T>* s, const cpx<T>* gin, cpx<T>* gout, const cpx<T>* tw, int tid) {
+  constexpr int IT = StageIters<R, N, COUNT, NTHR>::value;
+  cpx<T> x[IT][R];
+  ct_bfly_load<R, T, N, L, COUNT, NTHR, FROM_G, GES, GFS, ES, FS, NTS>(x, FROM_G ? gin : s, tid);
+  ct_bfly_run<R, FWD, T, N, L, COUNT, NTHR>(x, tw, tid);
+  ct_bfly_store<R, T, N, L, COUNT, NTHR, TO_G, GES, GFS, ES, FS, NTS>(x, TO_G ? gout : s, tid);
 }
 
 // Full forward or inverse transform along one axis (two stages + barriers).
@@ -220,24 +261,25 @@ __device__ inline void ct_conv(cpx<T>* s, const cpx<T>* tw, KF kf, int tid) {
 // rows, the longest contiguous runs in HBM), a second thread
 // count for the plane-inverse pass (fewer accumulators per thread, more waves
 // per CU) and one for the plane-forward pass (butterfly counts that divide
-// evenly among the threads).
+// evenly among the threads); threads of the persistent pencil pass with whole
+// x rows.
 template <int N>
 struct CubeShape;
 template <>
 struct CubeShape<24> {
-  static constexpr int NT_P = 192, XT = 24, NT_B = 192, XT2 = 12, NT_B2 = 96, NT_C2 = 288, NT_A2 = 288, XT3 = 24, NT_B3 = 192;
+  static constexpr int NT_P = 192, XT = 24, NT_B = 192, XT2 = 12, NT_B2 = 96, NT_C2 = 288, NT_A2 = 288, XT3 = 24, NT_B3 = 192, NT_BP = 192;
 };
 template <>
 struct CubeShape<48> {
-  static constexpr int NT_P = 256, XT = 48, NT_B = 256, XT2 = 24, NT_B2 = 128, NT_C2 = 384, NT_A2 = 384, XT3 = 48, NT_B3 = 256;
+  static constexpr int NT_P = 256, XT = 48, NT_B = 256, XT2 = 24, NT_B2 = 128, NT_C2 = 384, NT_A2 = 384, XT3 = 48, NT_B3 = 256, NT_BP = 384;
 };
 template <>
 struct CubeShape<72> {
-  static constexpr int NT_P = 512, XT = 24, NT_B = 256, XT2 = 12, NT_B2 = 128, NT_C2 = 576, NT_A2 = 576, XT3 = 72, NT_B3 = 512;
+  static constexpr int NT_P = 512, XT = 24, NT_B = 256, XT2 = 12, NT_B2 = 128, NT_C2 = 576, NT_A2 = 576, XT3 = 72, NT_B3 = 512, NT_BP = 576;
 };
 template <>
 struct CubeShape<96> {
-  static constexpr int NT_P = 512, XT = 48, NT_B = 512, XT2 = 24, NT_B2 = 256, NT_C2 = 768, NT_A2 = 768, XT3 = 96, NT_B3 = 1024;
+  static constexpr int NT_P = 512, XT = 48, NT_B = 512, XT2 = 24, NT_B2 = 256, NT_C2 = 768, NT_A2 = 768, XT3 = 96, NT_B3 = 1024, NT_BP = 768;
 };
 
 }  // namespace fx

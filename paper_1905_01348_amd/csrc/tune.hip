@@ -37,7 +37,7 @@ static fx_status check_config(const fx_cell* cell, const fx_vx_config& c) {
   if (c.kernels < 0 || c.kernels > 2) FX_FAIL(FX_ERR_INVALID, "kernels = %d not in {0, 1, 2}", c.kernels);
   if (c.work_mb < 0 || c.work_mb > (1 << 20)) FX_FAIL(FX_ERR_INVALID, "work_mb = %d out of range", c.work_mb);
   if (c.a_prefetch < -1 || c.a_prefetch > 1) FX_FAIL(FX_ERR_INVALID, "a_prefetch = %d not in {-1, 0, 1}", c.a_prefetch);
-  if (c.b_variant < 0 || c.b_variant > 3) FX_FAIL(FX_ERR_INVALID, "b_variant = %d not in {0, 1, 2, 3}", c.b_variant);
+  if (c.b_variant < 0 || c.b_variant > 4) FX_FAIL(FX_ERR_INVALID, "b_variant = %d not in {0, ..., 4}", c.b_variant);
   if (c.c_variant < 0 || c.c_variant > 4) FX_FAIL(FX_ERR_INVALID, "c_variant = %d not in {0, ..., 4}", c.c_variant);
   if (c.a_variant < 0 || c.a_variant > 2) FX_FAIL(FX_ERR_INVALID, "a_variant = %d not in {0, 1, 2}", c.a_variant);
   if (c.nt_hint < -1 || c.nt_hint > 1) FX_FAIL(FX_ERR_INVALID, "nt_hint = %d not in {-1, 0, 1}", c.nt_hint);
@@ -189,7 +189,7 @@ static fx_status autotune(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* ker
   const bool spec = ct_supported(cell);
   cur.kernels = spec ? 1 : 2;
   cur.a_prefetch = 0;
-  cur.b_variant = spec ? 1 : 0;
+  cur.b_variant = spec ? (cell->n[0] == 96 ? 4 : 1) : 0;
   cur.c_variant = spec ? (cell->n[0] == 96 ? 2 : 1) : 0;
   cur.a_variant = spec ? 1 : 0;
   cur.nt_hint = spec ? 1 : 0;
@@ -212,9 +212,10 @@ static fx_status autotune(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* ker
       c.a_prefetch = 1;
       rs = trial(c);
     }
-    for (int bv : {2, 3}) {
-      if (rs != FX_OK) break;
-      fx_vx_config c = cur;
+    const fx_vx_config bstart = cur;
+    for (int bv = 1; bv <= 4 && rs == FX_OK; ++bv) {
+      if (bv == bstart.b_variant) continue;
+      fx_vx_config c = bstart;
       c.b_variant = bv;
       rs = trial(c);
     }

@@ -358,6 +358,14 @@ static bool pick_ept(int elems, int max_thr, int* ept, int* nthr) {
     default: FX_FAIL(FX_ERR_UNSUPPORTED, "no kernel for %d elements per thread", EPT_VAR); \
   }
 
+// z-pass form of the specialised kernels: the persistent kernel with whole x
+// rows is the automatic choice at 96^3, where it measured faster (3.12 vs
+// 3.38 ms per launch of 1170 pairs); elsewhere the autotuner decides.
+static int ct_b_variant(const VxArgs& a) {
+  if (a.b_var >= 1 && a.b_var <= 4) return a.b_var;
+  return a.cell->n[0] == 96 ? 4 : 1;
+}
+
 // Plane-inverse threads of the specialised kernels: the larger count (fewer
 // accumulators per thread, 12 waves per CU instead of 8) is the automatic
 // choice at 96^3, where it measured faster (3.34 vs 3.39 ms per launch of
@@ -425,7 +433,7 @@ static fx_status run_halved(fx_ctx* ctx, Workspace* ws, const VxArgs& a, const G
       const int tri = J == K;
       const int npairs = tri ? jb * (jb + 1) / 2 : jb * kb;
       CtBatch<T> cb{psi, ld_psi, psi, ld_psi, reinterpret_cast<cpx<T>*>(work), j0, jb, k0, kb, npairs, tw, kf,
-                    tb->fold[0], tri, a.a_pipe > 0 ? 1 : 0, (a.b_var == 2 || a.b_var == 3) ? a.b_var : 1, ct_c_variant(a), a.a_var == 2 ? 2 : 1, a.nt_hint != 0 ? 1 : 0, ct_zsplit()};
+                    tb->fold[0], tri, a.a_pipe > 0 ? 1 : 0, ct_b_variant(a), ct_c_variant(a), a.a_var == 2 ? 2 : 1, a.nt_hint != 0 ? 1 : 0, ct_zsplit()};
       const double vol = (double)npairs * nr * sz;
       int slot;
       FX_TRY(prof_begin(ctx, st, FX_K_VX_PLANE_FWD, 2.0 * vol, &slot));
@@ -554,7 +562,7 @@ static fx_status run_batches(fx_ctx* ctx, Workspace* ws, const VxArgs& a, const 
       int slot;
       if (use_ct) {
         CtBatch<T> cb{psi, ld_psi, phi, ld_phi, reinterpret_cast<cpx<T>*>(work), j0, jb, k0, kb, npairs, twx, kf,
-                      tb->fold[0], 0, a.a_pipe > 0 ? 1 : 0, (a.b_var == 2 || a.b_var == 3) ? a.b_var : 1, ct_c_variant(a), a.a_var == 2 ? 2 : 1, a.nt_hint != 0 ? 1 : 0, ct_zsplit()};
+                      tb->fold[0], 0, a.a_pipe > 0 ? 1 : 0, ct_b_variant(a), ct_c_variant(a), a.a_var == 2 ? 2 : 1, a.nt_hint != 0 ? 1 : 0, ct_zsplit()};
         CtAcc<A> ca{acc, ld_acc, first, a.out, a.ld_out, out_c64 ? 1 : 0, last, a.pipe};
         FX_TRY(prof_begin(ctx, st, FX_K_VX_PLANE_FWD, 2.0 * vol, &slot));
         FX_TRY(ct_pass_a<T>(ctx, st, g.nx, cb));

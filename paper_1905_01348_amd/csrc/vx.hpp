@@ -31,7 +31,7 @@ struct VxArgs {
   int halve = -1;  // phi == psi: solve each unordered pair once (1 yes, 0 no, -1 automatic)
   int kernels = 0;  // 1 specialised (cubic workload edges only), 2 generic, 0 automatic
   int a_pipe = -1;  // specialised plane-forward pass: 1 register prefetch, 0 two workgroups per CU
-  int b_var = 0;    // specialised z pass tile: 1 default, 2 half, 3 whole rows, 0 automatic
+  int b_var = 0;    // specialised z pass tile: 1 default, 2 half, 3 whole rows, 4 persistent, 0 automatic
   int c_var = 0;    // specialised plane-inverse form: 1 default, 2 second thread count, 3/4 those with the
                     // next plane staged in LDS, 0 automatic
   int a_var = 0;    // specialised plane-forward threads: 1 default, 2 second count, 0 automatic
@@ -76,7 +76,7 @@ struct CtBatch {
   const int* fold;  // folded frequency per digit-reversed position
   int tri;          // diagonal batch of a halved apply: pairs jj <= kk only, packed
   int a_pipe;       // plane-forward pass: register prefetch of the next plane
-  int b_var;        // z pass: 1 default x tile, 2 half tile, 3 whole x rows
+  int b_var;        // z pass: 1 default x tile, 2 half tile, 3 whole x rows, 4 persistent (default tile)
   int c_var;        // plane-inverse pass: 1 default threads, 2 the second thread count, 3/4 staged
   int a_var;        // plane-forward pass: 1 default threads, 2 the second thread count
   int nts;          // the pair volume is read and written with non-temporal hints

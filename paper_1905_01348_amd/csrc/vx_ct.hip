@@ -234,6 +234,85 @@ __device__ inline void plane_to_lds(const cpx<T>* g, cpx<T>* lds, int tid) {
   }
 }
 
+// ---- pass B, persistent form -----------------------------------------------------
+// The same tile transform as k_pass_b_ct, with a fixed y per workgroup (the K
+// slice of that y is loaded into LDS once) and the tiles (pair, x tile) of
+// that y walked in order by the grid / N workgroups of that y: the
+// workgroups running at one time cover every y of the same few pair volumes.
+// The first stage's loads of the next tile are issued before the current
+// tile's middle and last stages, so HBM reads stay in flight while the
+// workgroup computes.  The grid is a multiple of N.
+template <typename T, int N, int XT, int NT, bool NTS>
+__global__ void __launch_bounds__(NT) k_pass_b_pt(cpx<T>* __restrict__ work, const cpx<T>* __restrict__ twg,
+                                                  const T* __restrict__ kfold, const int* __restrict__ foldg,
+                                                  int ntiles) {
+  constexpr int NTX = N / XT, NE = N * XT;
+  constexpr int H = N / 2 + 1;
+  static_assert(N % XT == 0, "x tile must divide the edge");
+  constexpr int R0 = Plan2<N>::R0, R1 = Plan2<N>::R1;
+  constexpr int IT0 = StageIters<R0, N, XT, NT>::value;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  cpx<T>* s = reinterpret_cast<cpx<T>*>(smem_raw);
+  cpx<T>* tw = s + NE;
+  T* kl = reinterpret_cast<T*>(tw + N);
+  int* fl = reinterpret_cast<int*>(kl + H * H);
+  const int tid = threadIdx.x;
+  const int y = blockIdx.x % N;
+  const int step = gridDim.x / N;
+  const int fy = foldg[y];
+  for (int i = tid; i < N; i += NT) {
+    tw[i] = twg[i];
+    fl[i] = foldg[i];
+  }
+  for (int i = tid; i < H * H; i += NT) kl[i] = kfold[((size_t)(i / H) * H + fy) * H + i % H];
+  // tile u = (pair u / NTX, x tile u % NTX); element (xi, z) at g[xi + z*N*N]
+  auto tile = [&](int u) __attribute__((always_inline)) {
+    return work + (size_t)(u / NTX) * N * N * N + (size_t)y * N + (u % NTX) * XT;
+  };
+  cpx<T> x0[IT0][R0];
+  int u = blockIdx.x / N;
+  if (u < ntiles) ct_bfly_load<R0, T, N, N, XT, NT, true, N * N, 1, XT, 1, NTS>(x0, tile(u), tid);
+  __syncthreads();  // tables
+  for (; u < ntiles; u += step) {
+    const int x0t = (u % NTX) * XT;
+    cpx<T>* g0 = tile(u);
+    // first forward stage from the registers loaded ahead
+    ct_bfly_run<R0, true, T, N, N, XT, NT>(x0, tw, tid);
+    ct_bfly_store<R0, T, N, N, XT, NT, false, N * N, 1, XT, 1, false>(x0, s, tid);
+    __syncthreads();
+    // the next tile's first-stage loads, in flight during the rest of this one
+    if (u + step < ntiles) ct_bfly_load<R0, T, N, N, XT, NT, true, N * N, 1, XT, 1, NTS>(x0, tile(u + step), tid);
+    // last forward stage x K x first inverse stage, in registers
+    {
+      constexpr int TOTAL = XT * (N / R1);
+      constexpr int ITERS = (TOTAL + NT - 1) / NT;
+#pragma unroll
+      for (int it = 0; it < ITERS; ++it) {
+        const int b = tid + it * NT;
+        if (TOTAL % NT == 0 || b < TOTAL) {
+          const int f = b % XT;
+          const int blk = b / XT;
+          const int base = f + blk * R1 * XT;
+          const int kx = fl[x0t + f];
+          cpx<T> xv[R1];
+#pragma unroll
+          for (int m = 0; m < R1; ++m) xv[m] = s[base + m * XT];
+          Dft<R1, -1, T>::run(xv);
+#pragma unroll
+          for (int k = 0; k < R1; ++k) xv[k] = cscale(xv[k], kl[fl[blk * R1 + k] * H + kx]);
+          Dft<R1, 1, T>::run(xv);
+#pragma unroll
+          for (int m = 0; m < R1; ++m) s[base + m * XT] = xv[m];
+        }
+      }
+    }
+    __syncthreads();
+    // last inverse stage straight back to the work volume
+    ct_stage_io<R0, false, T, N, N, XT, XT, 1, NT, false, true, N * N, 1, NTS>(s, nullptr, g0, tw, tid);
+    __syncthreads();  // before the next tile's first stage writes s
+  }
+}
+
 // ---- pass C: inverse FFT y and x, times psi_j, j-sum in registers --------------
 // One item = (target tt of the batch, plane z).  Role 0 (CONJ false): the
 // targets are the batch's k (output column t0 + kk) and the sum runs over its
@@ -437,9 +516,34 @@ static fx_status pass_b_shape(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b) 
   return FX_OK;
 }
 
+template <typename T, int N, int XT, int NT>
+static fx_status pass_b_pt_shape(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b) {
+  static_assert(N % XT == 0, "x tile must divide the edge");
+  const size_t lds = pass_b_lds<T, N>(XT);
+  auto kern = b.nts ? k_pass_b_pt<T, N, XT, NT, true> : k_pass_b_pt<T, N, XT, NT, false>;
+  const int ntiles = b.npairs * (N / XT);
+  FX_TRY(allow_dynamic_lds(reinterpret_cast<const void*>(kern), lds));
+  int per_cu = 0;
+  FX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kern), NT, lds));
+  // a whole number of workgroups per y that all run at once, no more than the
+  // tiles of a y (at 96^3 with whole rows: 2 per y, 192 of the 256 CUs, which
+  // measured faster than 256 workgroups over all CUs: the z pass runs at the
+  // HBM limit and gains more from the locality of a fixed y than from CUs)
+  int per_y = std::max(1, std::max(per_cu, 1) * std::max(ctx->n_cu, 1) / N);
+  per_y = std::min(per_y, ntiles);
+  hipLaunchKernelGGL(kern, dim3(per_y * N), dim3(NT), lds, st, b.work, b.tw, b.kfold, b.fold, ntiles);
+  FX_LAUNCH_CHECK();
+  return FX_OK;
+}
+
 template <typename T, int N>
 static fx_status pass_b_n(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b) {
   using S = CubeShape<N>;
+  // persistent form: whole x rows where they fit the LDS (not FP64 at 96), else the default tile
+  if (b.b_var == 4) {
+    if constexpr (pass_b_lds<T, N>(S::XT3) <= kLdsPerCu) return pass_b_pt_shape<T, N, S::XT3, S::NT_BP>(ctx, st, b);
+    return pass_b_pt_shape<T, N, S::XT, S::NT_B>(ctx, st, b);
+  }
   if (b.b_var == 2) return pass_b_shape<T, N, S::XT2, S::NT_B2>(ctx, st, b);
   // whole rows do not fit the LDS in FP64 at 96: the default tile instead
   if (b.b_var == 3 && pass_b_lds<T, N>(S::XT3) <= kLdsPerCu) return pass_b_shape<T, N, S::XT3, S::NT_B3>(ctx, st, b);
