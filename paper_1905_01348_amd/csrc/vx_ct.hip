@@ -84,13 +84,13 @@ __device__ inline ItemMap item_map(int units, int zsplit) {
 // PIPE: the next plane's loads are issued into registers before the current
 // plane is transformed (one workgroup per CU at 96^2); without it the kernel
 // is held to 128 VGPRs so that two workgroups share a CU instead.
-template <typename T, bool PIPE>
+template <typename T, bool PIPE, int NT>
 struct PassAWaves {
-  static constexpr int value = (sizeof(T) == 4 && !PIPE) ? 4 : 1;
+  static constexpr int value = (sizeof(T) == 4 && !PIPE) ? (NT > 512 ? 6 : 4) : 1;
 };
 
 template <typename T, int N, bool PIPE, int NT, bool NTS>
-__global__ void __launch_bounds__(NT, (PassAWaves<T, PIPE>::value)) k_pass_a_ct(const cpx<T>* __restrict__ psi, int64_t ld_psi,
+__global__ void __launch_bounds__(NT, (PassAWaves<T, PIPE, NT>::value)) k_pass_a_ct(const cpx<T>* __restrict__ psi, int64_t ld_psi,
                                                                   const cpx<T>* __restrict__ phi, int64_t ld_phi,
                                                                   cpx<T>* __restrict__ work, int j0, int nj, int k0,
                                                                   int tri, int nitems, const cpx<T>* __restrict__ twg,
