@@ -87,8 +87,16 @@ __device__ inline uint4 times_minus_i(uint4 v, int elem_bytes) {
 // ---------------------------------------------------------------------------
 constexpr int TBM = 128, TBN = 128;
 
+// BF16: held to two waves per SIMD (accumulators in the unified register
+// file), so two workgroups share a CU; FP32 keeps its registers (the
+// 32x32x2 FP32 matrix instruction is long enough to hide one wave's latency).
+template <typename S>
+struct MfmaWaves {
+  static constexpr int value = sizeof(S) == 2 ? 2 : 1;
+};
+
 template <typename S, bool REFINE, bool BDOUBLE, int MODE>
-__global__ void __launch_bounds__(256) k_tn_mfma(int M, int N, int K, int kchunk, const S* __restrict__ Ap,
+__global__ void __launch_bounds__(256, (MfmaWaves<S>::value)) k_tn_mfma(int M, int N, int K, int kchunk, const S* __restrict__ Ap,
                                                  const S* __restrict__ Ar, int64_t lda, const S* __restrict__ Bp,
                                                  const S* __restrict__ Br, int64_t ldb, double* __restrict__ partial,
                                                  void* __restrict__ out, int64_t ldo, int out_c64, double alpha,
