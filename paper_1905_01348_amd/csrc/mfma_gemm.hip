@@ -87,6 +87,15 @@ __device__ inline uint4 times_minus_i(uint4 v, int elem_bytes) {
 // ---------------------------------------------------------------------------
 constexpr int TBM = 128, TBN = 128;
 
+// Order of a wave's own LDS accesses across lanes: the wave's LDS
+// instructions execute in issue order, so only the compiler has to be kept
+// from moving accesses across this point.
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // BF16: held to two waves per SIMD (accumulators in the unified register
 // file), so two workgroups share a CU; FP32 keeps its registers (the
 // 32x32x2 FP32 matrix instruction is long enough to hide one wave's latency).
@@ -259,26 +268,52 @@ __global__ void __launch_bounds__(256, (MfmaWaves<S>::value)) k_tn_mfma(int M, i
   }
 
   // epilogue: D tile element e of (i, j): row = i*32 + 8*(e/4) + 4*(lane/32) + e%4, col = j*32 + lane%32
+  if (MODE == 0) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int n = n0 + wn * 64 + j * 32 + (lane & 31);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const int m = m0 + wm * 64 + i * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+          if (m >= M || n >= N) continue;
+          partial[((int64_t)split * M + m) * N + n] = (double)acc[i][j][e] + (REFINE ? (double)cor[i][j][e] : 0.0);
+        }
+      }
+    return;
+  }
+  // MODE 1: the output runs along m (r) for each target, the tile along n:
+  // each wave turns its 32x32 tiles around in its own slice of the (now idle)
+  // LDS, then writes 32 consecutive r of one target per half-wave.
+  constexpr int SL = 33;  // padded row of the staged tile (doubles)
+  double* stg = reinterpret_cast<double*>(smem_raw) + wave * 32 * SL;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      const int n = n0 + wn * 64 + j * 32 + (lane & 31);
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
-        const int m = m0 + wm * 64 + i * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
-        if (m >= M || n >= N) continue;
-        const double v = (double)acc[i][j][e] + (REFINE ? (double)cor[i][j][e] : 0.0);
-        if (MODE == 0) {
-          partial[((int64_t)split * M + m) * N + n] = v;
-        } else {
-          const int64_t idx = ((int64_t)(n >> 1) * ldo + m) * 2 + (n & 1);
+        const int ml = 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+        stg[ml * SL + (lane & 31)] = (double)acc[i][j][e] + (REFINE ? (double)cor[i][j][e] : 0.0);
+      }
+      wave_lds_sync();
+      const int ml = lane & 31;
+      const int m = m0 + wm * 64 + i * 32 + ml;
+#pragma unroll
+      for (int it = 0; it < 8; ++it) {
+        const int tl = (lane >> 5) + 2 * it;  // target within the tile's 16
+        const int n = n0 + wn * 64 + j * 32 + 2 * tl;
+        const double re = stg[ml * SL + 2 * tl], im = stg[ml * SL + 2 * tl + 1];
+        if (m < M && n < N) {
+          const int64_t idx = (int64_t)(n >> 1) * ldo + m;
           if (out_c64)
-            reinterpret_cast<float*>(out)[idx] = (float)(-alpha * v);
+            reinterpret_cast<float2*>(out)[idx] = make_float2((float)(-alpha * re), (float)(-alpha * im));
           else
-            reinterpret_cast<double*>(out)[idx] = -alpha * v;
+            reinterpret_cast<double2*>(out)[idx] = make_double2(-alpha * re, -alpha * im);
         }
       }
+      wave_lds_sync();
     }
 }
 
@@ -471,9 +506,11 @@ static fx_status apply_t(fx_ctx* ctx, Workspace* ws, fx_ace* a, AceSplit* sp, co
     // y = -xi C: M = nr, N = 2R, K = kn
     const int tm2 = (int)((nr + TBM - 1) / TBM), tn2 = (2 * R + TBN - 1) / TBN;
     auto kern2 = k_tn_mfma<S, REFINE, false, 1>;
-    FX_TRY(allow_lds_mfma(kern2, lds));
+    // the epilogue turns each wave's 32x32 tiles around in 32 x 33 doubles of LDS
+    const size_t lds2 = std::max(lds, (size_t)4 * 32 * 33 * sizeof(double));
+    FX_TRY(allow_lds_mfma(kern2, lds2));
     FX_TRY(prof_begin(ctx, st, FX_K_GEMM_NN, (REFINE ? 3.0 : 1.0) * 2.0 * (double)nr * 2.0 * R * (double)sp->kn, &slot));
-    hipLaunchKernelGGL(kern2, dim3((unsigned)(tm2 * tn2)), dim3(256), lds, st, (int)nr, 2 * R, (int)sp->kn,
+    hipLaunchKernelGGL(kern2, dim3((unsigned)(tm2 * tn2)), dim3(256), lds2, st, (int)nr, 2 * R, (int)sp->kn,
                        (int)sp->kn, (const S*)sp->row_p, (const S*)sp->row_r, sp->kn, (const S*)bp, (const S*)br,
                        sp->kn, (double*)nullptr, out, ld_out, out_dtype == FX_C64 ? 1 : 0, 1.0, tm2, tn2);
     FX_LAUNCH_CHECK();
