@@ -54,7 +54,7 @@ def cpu_baseline(psi_h, w, seconds):
     J, K, el = 4, 1, 0.0
     while True:
         t0 = time.perf_counter()
-        oracle.apply_vx(psi_h[:J], psi_h[:K].astype(np.complex128), w["n"], w["L"], "hse", 0.106, workers=cores)
+        oracle.apply_vx(psi_h[:J], psi_h[:K].astype(np.complex128), w["n"], w["L"], w.get("kernel", "hse"), 0.106, workers=cores)
         el = time.perf_counter() - t0
         if el >= seconds or (J >= N and K >= min(N, 32)):
             break
@@ -65,7 +65,7 @@ def cpu_baseline(psi_h, w, seconds):
             K = min(N, 32, max(K + 1, int(np.ceil(K * grow))))
     return {"value": J * K / el, "unit": "pairs/s", "cores": cores, "kind": "oracle",
             "sample": f"oracle.apply_vx on targets phi_0..phi_{K - 1} against psi_0..psi_{J - 1} "
-                      f"({J * K} pairs of the same 96^3 workload, scipy.fft workers={cores}), {el:.1f} s"}
+                      f"({J * K} pairs of the same {w['n']}^3 workload, scipy.fft workers={cores}), {el:.1f} s"}
 
 
 def main():
@@ -73,7 +73,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="cfg2", choices=["cfg1", "cfg2"])
+    ap.add_argument("--workload", default="cfg2", choices=["cfg0", "cfg1", "cfg2"],
+                    help="vx leg: cfg2 (96^3 share, the headline), or the phi = Psi workloads cfg0 (24^3, Coulomb) "
+                         "and cfg1 (48^3, HSE), which also time the ACE build and E_X")
     ap.add_argument("--prec", default="fp32acc64", choices=["fp32acc64", "fp32", "fp64"])
     ap.add_argument("--fp64-steps", type=int, default=2, help="timed FP64 steps for the comparison (0 = skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU oracle budget (0 = skip)")
@@ -116,7 +118,12 @@ def main():
     phi = P[:Nt]
     out = torch.empty((Nt, n, n, n), dtype=torch.complex128 if args.prec != "fp32" else torch.complex64, device=dev)
     ctx = Context(0)
-    kw = dict(n=n, L=L, kernel="hse", omega=0.106, prec=args.prec, out=out)
+    kname = w.get("kernel", "hse")
+    kw = dict(n=n, L=L, kernel=kname, omega=0.106, prec=args.prec, out=out)
+    # phi = Psi on a workload edge: the library solves each unordered pair once
+    # (halving is on by default for the specialised grids; FX_VX_HALVE=0 turns it off)
+    halved = Nt == N and n in (24, 48, 72, 96) and os.environ.get("FX_VX_HALVE", "1") != "0"
+    solves = N * (N + 1) // 2 if halved else N * Nt
     tune = None
     if args.autotune:
         t0 = time.perf_counter()
@@ -175,7 +182,10 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": (f"{args.workload}: V_X apply, {n}^3 grid, L={L:.2f} bohr, {N} orbitals x {Nt} targets "
-                         f"= {pairs} pair Poisson solves, HSE w=0.106"),
+                         f"= {pairs} pair Poisson solves, "
+                         + ("HSE w=0.106" if kname == "hse" else "Coulomb")
+                         + (" (phi = Psi: each unordered pair solved once)" if halved else "")),
+            "poisson_solves_per_step": solves,
             "prec": args.prec,
             "accumulation": "f64" if args.prec in ("fp64", "fp32acc64") else "f32",
             "pairs_per_step": pairs,
@@ -195,12 +205,14 @@ def main():
         },
         "kernels": kern,
     }
+    if solves != pairs:
+        result["poisson_solves_per_s"] = solves * args.steps / el
     # whole path: algorithmic bytes of every kernel per step / step time
     result["path_algorithmic_GBps"] = path_bytes / (ms_per_step * 1e-3) / 1e9
     result["path_bytes_per_pair_pt"] = path_bytes / (pairs * nr)
 
     if args.fp64_steps > 0 and args.prec != "fp64":
-        del out
+        # the same inputs (the rounded complex64 orbitals, widened exactly) in FP64 throughout
         P64 = P.to(torch.complex128)
         out64 = torch.empty((Nt, n, n, n), dtype=torch.complex128, device=dev)
         kw64 = dict(kw, prec="fp64", out=out64)
@@ -212,10 +224,26 @@ def main():
         torch.cuda.synchronize()
         el64 = time.perf_counter() - t0
         v64 = pairs * args.fp64_steps / el64
+        ref = out64.reshape(Nt, -1)
+        err = (torch.linalg.vector_norm(out.reshape(Nt, -1).to(torch.complex128) - ref, dim=1)
+               / torch.linalg.vector_norm(ref, dim=1)).max().item()
         result["fp64_same_gpu"] = {"value": v64, "unit": "pairs/s", "ms_per_step": 1e3 * el64 / args.fp64_steps,
-                                   "speedup_of_value": value / v64}
-        log(f"[bench] fp64 {v64:.0f} pairs/s")
+                                   "speedup_of_value": value / v64, "max_col_rel_err_of_value_vs_fp64": err}
+        log(f"[bench] fp64 {v64:.0f} pairs/s; {args.prec} vs fp64: max column relative error {err:.2e}")
         del P64, out64
+    del out
+
+    if Nt == N and args.workload != "cfg2":
+        # phi = Psi workloads: the ACE build (W = V_X Psi halved, FP64 GEMMs and Cholesky) and E_X
+        ace_vx = "fp64" if args.prec == "fp64" else "fp32acc64"
+        ctx.build_ace(P, n=n, L=L, kernel=kname, omega=0.106, vx_prec=ace_vx, ace_prec="ace_fp64")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ace = ctx.build_ace(P, n=n, L=L, kernel=kname, omega=0.106, vx_prec=ace_vx, ace_prec="ace_fp64")
+        torch.cuda.synchronize()
+        result["ace_build"] = {"ms": 1e3 * (time.perf_counter() - t0), "vx_prec": ace_vx, "E_X": ace.ex}
+        log(f"[bench] ACE build {result['ace_build']['ms']:.1f} ms, E_X {ace.ex:.8f}")
+        del ace
 
     if args.cpu_seconds > 0:
         log("[bench] CPU oracle baseline ...")
