@@ -353,6 +353,10 @@ __global__ void __launch_bounds__(NT) k_pass_c_ct(const cpx<T>* __restrict__ mul
     return work + (size_t)pl * NR + (size_t)z_ * NXY;
   };
   bool staged = false;  // STG: stg holds (or is receiving) this item's first term
+  // FP64: the orbital plane is loaded only before the last x stage, so that
+  // its registers are not live through the y stages beside the accumulators
+  // (loaded early it spills at 96^2)
+  constexpr bool kLateOrbital = sizeof(T) == 8;
   for (int li = im.first; li < im.total; li += im.step) {
     int tt, z;
     im.at(li, &tt, &z);
@@ -403,15 +407,29 @@ __global__ void __launch_bounds__(NT) k_pass_c_ct(const cpx<T>* __restrict__ mul
         ct_stage_io<R1, false, T, N, R1, N, SX, 1, NT, true, false, N, 1, NTS>(s, plane_ptr(tt, l, z), nullptr, tw,
                                                                               tid);
         __syncthreads();
+        if (!kLateOrbital) {
+#pragma unroll
+          for (int i = 0; i < EPT; ++i) {
+            const int e = tid + i * NT;
+            if (NXY % NT == 0 || e < NXY) vp[i] = pm[e];
+          }
+        }
+      }
+      ct_stage<R0, false, T, N, N, N, SX, 1, NT>(s, tw, tid);
+      __syncthreads();
+      // inverse x: its two stages (ct_fft's), the orbital plane loaded between
+      // them in FP64
+      ct_stage<R1, false, T, N, R1, N, 1, SX, NT>(s, tw, tid);
+      __syncthreads();
+      if (!STG && kLateOrbital) {
 #pragma unroll
         for (int i = 0; i < EPT; ++i) {
           const int e = tid + i * NT;
           if (NXY % NT == 0 || e < NXY) vp[i] = pm[e];
         }
       }
-      ct_stage<R0, false, T, N, N, N, SX, 1, NT>(s, tw, tid);
+      ct_stage<R0, false, T, N, N, N, 1, SX, NT>(s, tw, tid);
       __syncthreads();
-      ct_fft<false, T, N, N, 1, SX, NT>(s, tw, tid);
 #pragma unroll
       for (int i = 0; i < EPT; ++i) {
         const int e = tid + i * NT;

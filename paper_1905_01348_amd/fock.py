@@ -141,7 +141,7 @@ def load():
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise RuntimeError(f"libfock.so not built ({LIB_PATH}); run __graft_entry__.build()")
+        raise RuntimeError(f"libfock.so not built ({LIB_PATH}); run python -m paper_1905_01348_amd.build")
     lib = C.CDLL(LIB_PATH)
     for name, (res, args) in _SIGS.items():
         fn = getattr(lib, name)
