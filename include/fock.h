@@ -301,8 +301,10 @@ fx_status fx_density(fx_ctx* ctx, const void* psi, int32_t n, int64_t ld, int64_
 /*
  * Serving: continuous batching of V_X / ACE requests over resident orbitals.
  *
- * fx_serve_create: max_slots requests may be in flight on the device at once,
- *   spread over n_streams streams; same-grid requests that are waiting are
+ * fx_serve_create: batches run on n_streams streams, at most one per stream at
+ *   a time (a batch waits in the host queue rather than behind another
+ *   stream's batch); max_slots bounds the workspaces kept for them (slot i
+ *   uses stream i mod n_streams); same-grid requests that are waiting are
  *   merged into one launch of up to max_batch_pairs pairs; admission keeps the
  *   memory of resident trajectories plus in-flight requests within
  *   hbm_budget_bytes (0 = the context budget).

@@ -321,10 +321,17 @@ fx_status fx_serve(fx_server* srv, const fx_request* reqs, int32_t n_reqs, fx_st
       }
     }
     if (fatal != FX_OK) break;
-    // dispatch
+    // dispatch, only onto streams with nothing running: a batch queued on a
+    // busy stream would wait behind all of that stream's batch (a 72^3 V_X
+    // block is ~15 ms), while waiting in the host queue it takes the first
+    // stream to come free
     bool progressed = false;
     for (auto& sl : srv->slots) {
       if (sl.busy || waiting.empty()) continue;
+      bool stream_busy = false;
+      for (const auto& other : srv->slots)
+        if (other.busy && other.st == sl.st) stream_busy = true;
+      if (stream_busy) continue;
       // merge: oldest request first, then same trajectory and op in arrival order
       const int head = waiting.front();
       const fx_request& rh = reqs[head];
