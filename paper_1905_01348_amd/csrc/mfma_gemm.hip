@@ -216,29 +216,36 @@ __global__ void __launch_bounds__(256, (MfmaWaves<S>::value)) k_tn_mfma(int M, i
     const int ar = wm * 64 + (lane & 31);
     const int br = wn * 64 + (lane & 31);
     if constexpr (sizeof(S) == 4) {
+      // MFMA u of group q takes k = 4q + u (lanes 0-31) and BK/2 + 4q + u
+      // (lanes 32-63): any order of the step's k terms gives the same sum up
+      // to rounding, and this one lets each lane fetch the operands of four
+      // MFMAs with one 16-byte LDS read (rows 36 floats apart fill the 32
+      // banks in each group of 8 lanes; 4-byte reads of 32 rows did not)
 #pragma unroll
-      for (int kk = 0; kk < BK / 2; ++kk) {
-        const int kc = kk * 2 + (lane >> 5);
-        float a[2], b[2], a2[2], b2[2];
+      for (int q = 0; q < BK / 8; ++q) {
+        const int kc = (lane >> 5) * (BK / 2) + 4 * q;
+        float4 a[2], b[2], a2[2], b2[2];
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
-          a[t] = reinterpret_cast<const float*>(sAp)[(ar + 32 * t) * LDK + kc];
-          b[t] = reinterpret_cast<const float*>(sBp)[(br + 32 * t) * LDK + kc];
+          a[t] = *reinterpret_cast<const float4*>(reinterpret_cast<const float*>(sAp) + (ar + 32 * t) * LDK + kc);
+          b[t] = *reinterpret_cast<const float4*>(reinterpret_cast<const float*>(sBp) + (br + 32 * t) * LDK + kc);
           if (REFINE) {
-            a2[t] = reinterpret_cast<const float*>(sAr)[(ar + 32 * t) * LDK + kc];
-            b2[t] = reinterpret_cast<const float*>(sBr)[(br + 32 * t) * LDK + kc];
+            a2[t] = *reinterpret_cast<const float4*>(reinterpret_cast<const float*>(sAr) + (ar + 32 * t) * LDK + kc);
+            b2[t] = *reinterpret_cast<const float4*>(reinterpret_cast<const float*>(sBr) + (br + 32 * t) * LDK + kc);
           }
         }
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int u = 0; u < 4; ++u)
 #pragma unroll
-          for (int j = 0; j < 2; ++j) {
-            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b[j], acc[i][j], 0, 0, 0);
-            if (REFINE) {
-              cor[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i], b2[j], cor[i][j], 0, 0, 0);
-              cor[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a2[i], b[j], cor[i][j], 0, 0, 0);
+          for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i][u], b[j][u], acc[i][j], 0, 0, 0);
+              if (REFINE) {
+                cor[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[i][u], b2[j][u], cor[i][j], 0, 0, 0);
+                cor[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a2[i][u], b[j][u], cor[i][j], 0, 0, 0);
+              }
             }
-          }
       }
     } else {
 #pragma unroll
