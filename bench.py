@@ -160,11 +160,18 @@ def main():
     achieved = kern[dom]["algorithmic_GBps"]
     bytes_per_launch = kern[dom]["bytes_per_launch"]
     traffic = None
+    path_dram = None
     cpath = os.path.join(ROOT, "profiles", "vx_counters.json")
     if os.path.exists(cpath):
         c = json.load(open(cpath))
         if c.get("source_hash") == kernel_source_hash() and c.get("prec") == args.prec and dom in c.get("kernels", {}):
             traffic = c["kernels"][dom]["bytes_per_launch"]
+            # measured DRAM bytes of every pass (copy-calibrated counters, same kernels and launch
+            # shapes) over their event-timed durations
+            if args.workload == "cfg2" and all(k in c["kernels"] for k in kern if k.startswith("vx_")):
+                b = sum(c["kernels"][k]["bytes_per_launch"] * kern[k]["launches"] for k in kern if k.startswith("vx_"))
+                t = sum(kern[k]["total_ms"] for k in kern if k.startswith("vx_")) * 1e-3
+                path_dram = b / t / 1e9
     path_bytes = sum(kern[k]["bytes_per_launch"] * kern[k]["launches"] for k in kern) / args.steps
 
     result = {
@@ -210,6 +217,10 @@ def main():
     # whole path: algorithmic bytes of every kernel per step / step time
     result["path_algorithmic_GBps"] = path_bytes / (ms_per_step * 1e-3) / 1e9
     result["path_bytes_per_pair_pt"] = path_bytes / (pairs * nr)
+    if path_dram is not None:
+        # DRAM bytes measured by FETCH_SIZE/WRITE_SIZE for these kernels / their summed durations
+        result["path_dram_GBps"] = path_dram
+        result["path_dram_frac_of_peak"] = path_dram / HBM_PEAK_GBS
 
     if args.fp64_steps > 0 and args.prec != "fp64":
         # the same inputs (the rounded complex64 orbitals, widened exactly) in FP64 throughout

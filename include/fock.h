@@ -120,7 +120,10 @@ typedef struct fx_server fx_server;
  * the handle.  Errors: FX_ERR_INVALID (ctx NULL), FX_ERR_DEVICE. */
 fx_status fx_init(int device, size_t hbm_budget_bytes, fx_ctx** ctx);
 
-/* Wait for the context's work, free everything it owns, destroy it. */
+/* Wait for the context's work, free everything it owns, destroy it.  ACE
+ * handles and servers created on the context and still alive give their device
+ * memory back here; afterwards fx_ace_free / fx_serve_destroy on them only
+ * delete the handle, and every other call on them fails with FX_ERR_INVALID. */
 fx_status fx_finalize(fx_ctx* ctx);
 
 /* Text of the last error raised on the calling thread ("" if none). */
@@ -264,7 +267,8 @@ fx_status fx_ace_export(const fx_ace* ace, void* xi, void* L, void* M);
 /* Number of orbitals and grid points of a handle. */
 fx_status fx_ace_shape(const fx_ace* ace, int32_t* n, int64_t* n_r);
 
-/* Free an ACE handle (waits for its work first). */
+/* Free an ACE handle (waits for its work first).  Valid before or after
+ * fx_finalize of its context (after it, only the handle is left to delete). */
 fx_status fx_ace_free(fx_ace* ace);
 
 /*
@@ -355,6 +359,9 @@ fx_status fx_serve_register(fx_server* srv, int32_t traj, const fx_cell* cell, c
                             fx_prec vx_prec, fx_prec ace_prec);
 fx_status fx_serve(fx_server* srv, const fx_request* reqs, int32_t n_reqs,
                    fx_status* per_req_status, double* per_req_latency_ms, fx_serve_report* report);
+/* Release a server: its resident orbitals, ACE factors, workspaces and streams
+ * (after waiting for the device), and the context budget it capped.  Valid
+ * before or after fx_finalize of its context. */
 fx_status fx_serve_destroy(fx_server* srv);
 
 #ifdef __cplusplus

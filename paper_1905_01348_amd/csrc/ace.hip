@@ -21,6 +21,14 @@ static void ace_release(fx_ace* a) {
   ws_release(ctx, &a->ws);
 }
 
+void ace_detach_all(fx_ctx* ctx) {
+  for (fx_ace* a : ctx->aces) {
+    ace_release(a);
+    a->ctx = nullptr;
+  }
+  ctx->aces.clear();
+}
+
 fx_status ace_alloc(fx_ace* a, size_t bytes, void** out) {
   FX_TRY(ctx_alloc(a->ctx, bytes, out));
   a->owned.push_back({*out, bytes});
@@ -212,8 +220,10 @@ fx_status fx_build_ace(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* kernel
   FX_HIP(hipSetDevice(ctx->device));
   FX_TRY(note_capture(ctx, (hipStream_t)stream));
   if (ctx->capturing) FX_FAIL(FX_ERR_INVALID, "fx_build_ace waits on its stream and cannot be captured");
-  return ace_build_impl(ctx, &ctx->ws, cell, kernel, psi, n_psi, ld_psi, in_dtype, vx_prec, ace_prec,
-                        (hipStream_t)stream, ace, ex_energy);
+  FX_TRY(ace_build_impl(ctx, &ctx->ws, cell, kernel, psi, n_psi, ld_psi, in_dtype, vx_prec, ace_prec,
+                        (hipStream_t)stream, ace, ex_energy));
+  ctx->aces.insert(*ace);
+  return FX_OK;
 }
 
 fx_status fx_apply_ace(fx_ctx* ctx, const fx_ace* ace, const void* phi, int32_t n_phi, int64_t ld_phi, void* out,
@@ -221,6 +231,7 @@ fx_status fx_apply_ace(fx_ctx* ctx, const fx_ace* ace, const void* phi, int32_t 
   clear_error();
   if (!ctx) FX_FAIL(FX_ERR_INVALID, "ctx is NULL");
   if (!ace) FX_FAIL(FX_ERR_INVALID, "ace is NULL");
+  if (!ace->ctx) FX_FAIL(FX_ERR_INVALID, "the context of this ACE handle was finalized");
   if (ace->ctx != ctx) FX_FAIL(FX_ERR_INVALID, "ace was built on another context");
   std::lock_guard<std::recursive_mutex> lk(ctx->mu);
   FX_HIP(hipSetDevice(ctx->device));
@@ -232,6 +243,7 @@ fx_status fx_apply_ace(fx_ctx* ctx, const fx_ace* ace, const void* phi, int32_t 
 fx_status fx_ace_export(const fx_ace* ace, void* xi, void* L, void* M) {
   clear_error();
   if (!ace) FX_FAIL(FX_ERR_INVALID, "ace is NULL");
+  if (!ace->ctx) FX_FAIL(FX_ERR_INVALID, "the context of this ACE handle was finalized");
   const size_t nn = (size_t)ace->n * ace->n * 16;
   FX_HIP(hipDeviceSynchronize());
   if (xi) FX_HIP(hipMemcpy(xi, ace->xi, (size_t)ace->nr * ace->n * 16, hipMemcpyDeviceToDevice));
@@ -251,10 +263,14 @@ fx_status fx_ace_shape(const fx_ace* ace, int32_t* n, int64_t* n_r) {
 fx_status fx_ace_free(fx_ace* ace) {
   clear_error();
   if (!ace) FX_FAIL(FX_ERR_INVALID, "ace is NULL");
-  fx_ctx* ctx = ace->ctx;
-  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
-  FX_HIP(hipDeviceSynchronize());
-  ace_release(ace);
+  // a handle whose context was finalized holds no device memory any more
+  if (fx_ctx* ctx = ace->ctx) {
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    FX_HIP(hipSetDevice(ctx->device));
+    FX_HIP(hipDeviceSynchronize());
+    ace_release(ace);
+    ctx->aces.erase(ace);
+  }
   delete ace;
   return FX_OK;
 }

@@ -10,6 +10,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -122,9 +123,19 @@ struct fx_ctx {
   int64_t prof_launches[FX_K_COUNT] = {0};
   double prof_ms[FX_K_COUNT] = {0};
   double prof_work[FX_K_COUNT] = {0};
+  // live handles created on this context: fx_finalize releases their device
+  // memory and detaches them (afterwards only fx_ace_free / fx_serve_destroy
+  // may be called on them, and those just delete the handle)
+  std::set<fx_ace*> aces;
+  std::set<fx_server*> servers;
 };
 
 namespace fx {
+
+// Release the device memory of every live ACE handle / server of the context
+// and detach them from it (fx_finalize).
+void ace_detach_all(fx_ctx* ctx);
+void serve_detach_all(fx_ctx* ctx);
 
 // Allocation charged to the context budget.  Returns FX_ERR_OOM when the
 // budget would be exceeded or hipMalloc fails.

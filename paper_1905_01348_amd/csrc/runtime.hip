@@ -474,6 +474,10 @@ fx_status fx_finalize(fx_ctx* ctx) {
   if (!ctx) FX_FAIL(FX_ERR_INVALID, "ctx is NULL");
   FX_HIP(hipSetDevice(ctx->device));
   FX_HIP(hipDeviceSynchronize());
+  // servers and ACE handles still alive give their device memory back here;
+  // they stay valid for fx_serve_destroy / fx_ace_free only
+  serve_detach_all(ctx);
+  ace_detach_all(ctx);
   ws_release(ctx, &ctx->ws);
   for (auto& kv : ctx->tables) {
     GridTables& t = kv.second;

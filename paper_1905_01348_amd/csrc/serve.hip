@@ -100,6 +100,44 @@ static double percentile(std::vector<double> v, double q) {
   return v[k - 1];
 }
 
+// Device resources of a server: resident orbitals and ACE factors of its
+// trajectories, slot workspaces, events and streams; the context budget it
+// capped is restored.  The device has been synchronised by the caller.
+static void serve_release(fx_server* srv) {
+  fx_ctx* ctx = srv->ctx;
+  for (auto& kv : srv->trajs) {
+    Traj& t = kv.second;
+    if (t.ace) {
+      for (auto& b : t.ace->owned) ctx_free(ctx, b.first, b.second);
+      ws_release(ctx, &t.ace->ws);
+      delete t.ace;
+      t.ace = nullptr;
+    }
+    ctx_free(ctx, t.psi, t.psi_bytes);
+  }
+  srv->trajs.clear();
+  std::vector<hipStream_t> streams;
+  for (auto& sl : srv->slots) {
+    ws_release(ctx, &sl.ws);
+    if (sl.done) (void)hipEventDestroy(sl.done);
+    sl.done = nullptr;
+    if (std::find(streams.begin(), streams.end(), sl.st) == streams.end()) streams.push_back(sl.st);
+  }
+  srv->slots.clear();
+  for (auto st : streams) (void)hipStreamDestroy(st);
+  ctx->budget = srv->saved_budget;
+}
+
+namespace fx {
+void serve_detach_all(fx_ctx* ctx) {
+  for (fx_server* srv : ctx->servers) {
+    serve_release(srv);
+    srv->ctx = nullptr;
+  }
+  ctx->servers.clear();
+}
+}  // namespace fx
+
 extern "C" {
 
 fx_status fx_serve_create(fx_ctx* ctx, const fx_serve_cfg* cfg, fx_server** srv) {
@@ -117,20 +155,30 @@ fx_status fx_serve_create(fx_ctx* ctx, const fx_serve_cfg* cfg, fx_server** srv)
   s->saved_budget = ctx->budget;
   if (cfg->hbm_budget_bytes && cfg->hbm_budget_bytes < ctx->budget) ctx->budget = cfg->hbm_budget_bytes;
   s->slots.resize(cfg->max_slots);
-  std::vector<hipStream_t> streams(cfg->n_streams);
-  for (auto& st : streams) {
+  std::vector<hipStream_t> streams;
+  auto undo = [&]() {
+    for (auto& sl : s->slots)
+      if (sl.done) (void)hipEventDestroy(sl.done);
+    for (auto st : streams) (void)hipStreamDestroy(st);
+    ctx->budget = s->saved_budget;
+    delete s;
+  };
+  for (int i = 0; i < cfg->n_streams; ++i) {
+    hipStream_t st = nullptr;
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
-      delete s;
+      undo();
       FX_FAIL(FX_ERR_DEVICE, "stream creation failed");
     }
+    streams.push_back(st);
   }
   for (int i = 0; i < cfg->max_slots; ++i) {
     s->slots[i].st = streams[i % cfg->n_streams];
     if (hipEventCreateWithFlags(&s->slots[i].done, hipEventDisableTiming) != hipSuccess) {
-      delete s;
+      undo();
       FX_FAIL(FX_ERR_DEVICE, "event creation failed");
     }
   }
+  ctx->servers.insert(s);
   *srv = s;
   return FX_OK;
 }
@@ -140,6 +188,7 @@ fx_status fx_serve_register(fx_server* srv, int32_t traj, const fx_cell* cell, c
                             fx_prec ace_prec) {
   clear_error();
   if (!srv) FX_FAIL(FX_ERR_INVALID, "srv is NULL");
+  if (!srv->ctx) FX_FAIL(FX_ERR_INVALID, "the context of this server was finalized");
   fx_ctx* ctx = srv->ctx;
   std::lock_guard<std::recursive_mutex> lk(ctx->mu);
   ctx->capturing = false;  // the serving loop runs on its own, uncaptured streams
@@ -192,6 +241,7 @@ fx_status fx_serve(fx_server* srv, const fx_request* reqs, int32_t n_reqs, fx_st
   clear_error();
   if (!srv) FX_FAIL(FX_ERR_INVALID, "srv is NULL");
   if (n_reqs < 0 || (n_reqs > 0 && !reqs)) FX_FAIL(FX_ERR_INVALID, "bad request array");
+  if (!srv->ctx) FX_FAIL(FX_ERR_INVALID, "the context of this server was finalized");
   fx_ctx* ctx = srv->ctx;
   std::lock_guard<std::recursive_mutex> lk(ctx->mu);
   ctx->capturing = false;  // the serving loop runs on its own, uncaptured streams
@@ -436,27 +486,14 @@ fx_status fx_serve(fx_server* srv, const fx_request* reqs, int32_t n_reqs, fx_st
 fx_status fx_serve_destroy(fx_server* srv) {
   clear_error();
   if (!srv) FX_FAIL(FX_ERR_INVALID, "srv is NULL");
-  fx_ctx* ctx = srv->ctx;
-  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
-  FX_HIP(hipSetDevice(ctx->device));
-  FX_HIP(hipDeviceSynchronize());
-  for (auto& kv : srv->trajs) {
-    Traj& t = kv.second;
-    if (t.ace) {
-      for (auto& b : t.ace->owned) ctx_free(ctx, b.first, b.second);
-      ws_release(ctx, &t.ace->ws);
-      delete t.ace;
-    }
-    ctx_free(ctx, t.psi, t.psi_bytes);
+  // a server whose context was finalized holds no device resources any more
+  if (fx_ctx* ctx = srv->ctx) {
+    std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+    FX_HIP(hipSetDevice(ctx->device));
+    FX_HIP(hipDeviceSynchronize());
+    serve_release(srv);
+    ctx->servers.erase(srv);
   }
-  std::vector<hipStream_t> streams;
-  for (auto& sl : srv->slots) {
-    ws_release(ctx, &sl.ws);
-    if (sl.done) (void)hipEventDestroy(sl.done);
-    if (std::find(streams.begin(), streams.end(), sl.st) == streams.end()) streams.push_back(sl.st);
-  }
-  for (auto st : streams) (void)hipStreamDestroy(st);
-  ctx->budget = srv->saved_budget;
   delete srv;
   return FX_OK;
 }

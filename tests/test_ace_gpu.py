@@ -131,3 +131,36 @@ def test_ace_errors(ctx):
     assert ei.value.status == -2
     ace.free()
     torch.cuda.synchronize()
+
+
+def test_handles_outlive_their_context():
+    """An ACE handle and a server (with a registered trajectory) still alive when
+    their context is finalized: the context takes their device memory back, a
+    later free only deletes the handle, and any other use is refused."""
+    import torch
+    from paper_1905_01348_amd import Context, FockError, Server
+
+    c = Context(0)
+    n3, L3 = (6, 6, 6), (4.0, 4.0, 4.0)
+    P = dev(synth.make_orbitals(3, n3, L3, 4, ecut=1e4))
+    ace = c.build_ace(P, n=n3, L=L3, kernel="hse", vx_prec="fp64")
+    srv = Server(c, max_slots=2, n_streams=1)
+    srv.register(0, P.to(torch.complex64), n=n3, L=L3)
+    c.close()
+    with pytest.raises(FockError) as ei:
+        ace.export()
+    assert ei.value.status == -1
+    with pytest.raises(FockError) as ei:
+        srv.register(1, P.to(torch.complex64), n=n3, L=L3)
+    assert ei.value.status == -1
+    ace.free()
+    srv.close()
+    torch.cuda.synchronize()
+    # a fresh context on the same device works as usual
+    c2 = Context(0)
+    ace2 = c2.build_ace(P, n=n3, L=L3, kernel="hse", vx_prec="fp64")
+    y = ace2.apply(P, prec="ace_fp64")
+    torch.cuda.synchronize()
+    assert torch.isfinite(torch.view_as_real(y)).all()
+    ace2.free()
+    c2.close()
