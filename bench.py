@@ -79,6 +79,9 @@ def main():
     ap.add_argument("--prec", default="fp32acc64", choices=["fp32acc64", "fp32", "fp64"])
     ap.add_argument("--fp64-steps", type=int, default=2, help="timed FP64 steps for the comparison (0 = skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU oracle budget (0 = skip)")
+    ap.add_argument("--graph", action="store_true",
+                    help="vx leg: also time the apply captured once into a HIP graph and replayed "
+                         "(launch overhead; every replay checked bitwise against the eager result)")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="vx leg: skip the launch-configuration autotuner (run the automatic configuration)")
     ap.add_argument("--leg", default="vx", choices=["vx", "ace", "serve", "copy", "step"],
@@ -222,6 +225,15 @@ def main():
         result["path_dram_GBps"] = path_dram
         result["path_dram_frac_of_peak"] = path_dram / HBM_PEAK_GBS
 
+    if args.graph:
+        try:
+            result["graph_replay"] = graph_replay(ctx, P, phi, kw, out, pairs, max(args.steps, 20))
+            log(f"[bench] graph replay {result['graph_replay']['value']:.0f} pairs/s "
+                f"({result['graph_replay']['ms_per_step']:.4f} ms per apply, eager {ms_per_step:.4f})")
+        except (RuntimeError, fock.FockError) as e:
+            result["graph_replay"] = {"error": str(e)}
+            log(f"[bench] graph replay failed: {e}")
+
     if args.fp64_steps > 0 and args.prec != "fp64":
         # the same inputs (the rounded complex64 orbitals, widened exactly) in FP64 throughout
         P64 = P.to(torch.complex128)
@@ -261,6 +273,40 @@ def main():
         result["cpu_baseline"] = cpu_baseline(psi_h, w, args.cpu_seconds)
     ctx.close()
     print(json.dumps(result))
+
+
+def graph_replay(ctx, P, phi, kw, out, pairs, steps):
+    """The apply captured once (after the eager runs above, so its workspace and
+    tables exist) into a HIP graph on a side stream and replayed `steps` times
+    back to back; each replay's output must equal the eager one bitwise."""
+    import torch
+
+    ref = out.clone()
+    s = torch.cuda.Stream()
+    out_g = torch.empty_like(out)
+    kwg = dict(kw, out=out_g)
+    ctx.prof_enable(False)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        ctx.apply_vx(P, phi, **kwg)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        out_g.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        if not torch.equal(torch.view_as_real(out_g), torch.view_as_real(ref)):
+            raise RuntimeError("graph replay differs from the eager result")
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.replay()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    if not torch.equal(torch.view_as_real(out_g), torch.view_as_real(ref)):
+        raise RuntimeError("graph replay differs from the eager result")
+    del g
+    return {"value": pairs * steps / el, "unit": "pairs/s", "steps": steps, "ms_per_step": 1e3 * el / steps}
 
 
 def bench_copy(args):
