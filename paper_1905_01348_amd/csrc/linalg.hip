@@ -19,9 +19,14 @@ namespace fx {
 using z = cpx<double>;
 
 FX_HD z zconj(z a) { return {a.x, -a.y}; }
+// acc + a*b as four fused multiply-adds (written as `acc += a.x*b.x - a.y*b.y`
+// the compiler emits a multiply, a fused multiply-add and an add per
+// component: six FP64 instructions instead of four)
 FX_HD z zfma(z acc, z a, z b) {
-  acc.x += a.x * b.x - a.y * b.y;
-  acc.y += a.x * b.y + a.y * b.x;
+  acc.x = __builtin_fma(a.x, b.x, acc.x);
+  acc.x = __builtin_fma(-a.y, b.y, acc.x);
+  acc.y = __builtin_fma(a.x, b.y, acc.y);
+  acc.y = __builtin_fma(a.y, b.x, acc.y);
   return acc;
 }
 
@@ -39,7 +44,7 @@ FX_HD z zfma(z acc, z a, z b) {
 constexpr int ZBM = 128, ZBN = 64, ZK = 8;
 
 template <int OPA, int OPB>
-__global__ void __launch_bounds__(256) k_zgemm(int M, int N, int K, const z* __restrict__ A, int64_t lda,
+__global__ void __launch_bounds__(256, 2) k_zgemm(int M, int N, int K, const z* __restrict__ A, int64_t lda,
                                                int64_t sA, const z* __restrict__ B, int64_t ldb, int64_t sB,
                                                z* C, int64_t ldc, int64_t sC, z alpha, z beta, int nsplit,
                                                int kchunk, z* __restrict__ partial) {
