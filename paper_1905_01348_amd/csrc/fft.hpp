@@ -32,6 +32,18 @@ template <typename T>
 FX_HD cpx<T> csub(cpx<T> a, cpx<T> b) { return {a.x - b.x, a.y - b.y}; }
 template <typename T>
 FX_HD cpx<T> cmul(cpx<T> a, cpx<T> b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+FX_HD float fmadd(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+FX_HD double fmadd(double a, double b, double c) { return __builtin_fma(a, b, c); }
+// acc + a*b as four fused multiply-adds (written as cadd(acc, cmul(a, b)) the
+// compiler emits a multiply, a fused multiply-add and an add per component)
+template <typename T>
+FX_HD cpx<T> cfma(cpx<T> acc, cpx<T> a, cpx<T> b) {
+  acc.x = fmadd(a.x, b.x, acc.x);
+  acc.x = fmadd(-a.y, b.y, acc.x);
+  acc.y = fmadd(a.x, b.y, acc.y);
+  acc.y = fmadd(a.y, b.x, acc.y);
+  return acc;
+}
 // a * conj(b)
 template <typename T>
 FX_HD cpx<T> cmulc(cpx<T> a, cpx<T> b) { return {a.x * b.x + a.y * b.y, a.y * b.x - a.x * b.y}; }

@@ -210,7 +210,12 @@ __global__ void __launch_bounds__(kPlaneThreads) k_pass_c(const cpx<T>* __restri
         if (e < nxy) {
           const int y = e / g.nx, x = e - y * g.nx;
           const cpx<T> v = s[y * g.sx + x];
-          a[i] = cadd(a[i], cmul(cpx<A>{(A)vp[i].x, (A)vp[i].y}, cpx<A>{(A)v.x, (A)v.y}));
+          // FP32 transforms: four FMAs per term; FP64: product then sum (the
+          // FMA chain costs the FP64 kernels registers they do not have)
+          if constexpr (sizeof(T) == 4)
+            a[i] = cfma(a[i], cpx<A>{(A)vp[i].x, (A)vp[i].y}, cpx<A>{(A)v.x, (A)v.y});
+          else
+            a[i] = cadd(a[i], cmul(cpx<A>{(A)vp[i].x, (A)vp[i].y}, cpx<A>{(A)v.x, (A)v.y}));
         }
       }
       __syncthreads();

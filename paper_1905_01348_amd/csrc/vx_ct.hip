@@ -436,7 +436,12 @@ __global__ void __launch_bounds__(NT) k_pass_c_ct(const cpx<T>* __restrict__ mul
         if (NXY % NT == 0 || e < NXY) {
           const cpx<T> v = s[(e / N) * SX + e % N];
           const cpx<A> va{(A)v.x, CONJ ? -(A)v.y : (A)v.y};
-          a[i] = cadd(a[i], cmul(cpx<A>{(A)vp[i].x, (A)vp[i].y}, va));
+          // FP32 transforms: four FMAs per term; FP64: product then sum (the
+          // FMA chain costs the FP64 kernel registers it does not have)
+          if constexpr (sizeof(T) == 4)
+            a[i] = cfma(a[i], cpx<A>{(A)vp[i].x, (A)vp[i].y}, va);
+          else
+            a[i] = cadd(a[i], cmul(cpx<A>{(A)vp[i].x, (A)vp[i].y}, va));
         }
       }
       // (STG: the barrier at the top of the next term orders these reads
