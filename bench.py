@@ -30,11 +30,36 @@ KSRC = ["paper_1905_01348_amd/csrc/vx.hip", "paper_1905_01348_amd/csrc/vx_passes
         "paper_1905_01348_amd/csrc/fft_ct.hpp"]
 
 
+def _code_tokens(text):
+    """The source without its comments and with whitespace runs collapsed: a change to
+    comments alone leaves the kernels, and so their stored counters, as they were."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        elif c in "\"'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def kernel_source_hash():
     h = hashlib.sha256()
     for p in KSRC:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, p), encoding="utf-8") as f:
+            h.update(_code_tokens(f.read()).encode())
     return h.hexdigest()[:16]
 
 
