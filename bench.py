@@ -98,9 +98,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="cfg2", choices=["cfg0", "cfg1", "cfg2"],
-                    help="vx leg: cfg2 (96^3 share, the headline), or the phi = Psi workloads cfg0 (24^3, Coulomb) "
-                         "and cfg1 (48^3, HSE), which also time the ACE build and E_X")
+    ap.add_argument("--workload", default="96cube_1024x32", choices=["24cube_16", "48cube_128", "96cube_1024x32"],
+                    help="vx leg: 96cube_1024x32 (96^3, 1024 orbitals x 32 targets, the headline), or the phi = Psi "
+                         "workloads 24cube_16 (24^3, 16 orbitals, Coulomb) and 48cube_128 (48^3, 128 orbitals, HSE), "
+                         "which also time the ACE build and E_X")
     ap.add_argument("--prec", default="fp32acc64", choices=["fp32acc64", "fp32", "fp64"])
     ap.add_argument("--fp64-steps", type=int, default=2, help="timed FP64 steps for the comparison (0 = skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU oracle budget (0 = skip)")
@@ -196,7 +197,7 @@ def main():
             traffic = c["kernels"][dom]["bytes_per_launch"]
             # measured DRAM bytes of every pass (copy-calibrated counters, same kernels and launch
             # shapes) over their event-timed durations
-            if args.workload == "cfg2" and all(k in c["kernels"] for k in kern if k.startswith("vx_")):
+            if args.workload == "96cube_1024x32" and all(k in c["kernels"] for k in kern if k.startswith("vx_")):
                 b = sum(c["kernels"][k]["bytes_per_launch"] * kern[k]["launches"] for k in kern if k.startswith("vx_"))
                 t = sum(kern[k]["total_ms"] for k in kern if k.startswith("vx_")) * 1e-3
                 path_dram = b / t / 1e9
@@ -281,7 +282,7 @@ def main():
         del P64, out64
     del out
 
-    if Nt == N and args.workload != "cfg2":
+    if Nt == N and args.workload != "96cube_1024x32":
         # phi = Psi workloads: the ACE build (W = V_X Psi halved, FP64 GEMMs and Cholesky) and E_X
         ace_vx = "fp64" if args.prec == "fp64" else "fp32acc64"
         ctx.build_ace(P, n=n, L=L, kernel=kname, omega=0.106, vx_prec=ace_vx, ace_prec="ace_fp64")
@@ -371,7 +372,7 @@ def bench_ace(args):
     import synth
     from paper_1905_01348_amd import Context, fock
 
-    w = synth.workload("cfg2")
+    w = synth.workload("96cube_1024x32")
     n, L, N = w["n"], w["L"], w["N"]
     nr = n ** 3
     R = N
@@ -467,7 +468,7 @@ def bench_step(args):
     import synth
     from paper_1905_01348_amd import Context, fock
 
-    w = synth.workload("cfg2")
+    w = synth.workload("96cube_1024x32")
     n, L, N = w["n"], w["L"], w["N"]
     nr = n ** 3
     g = torch.Generator(device="cuda:0")

@@ -36,11 +36,11 @@ HSE_OMEGA = 0.106
 # Workloads: name -> parameters.  Only shapes, seeds and kernels live here.
 WORKLOADS = {
     # 8-Si-atom cubic cell, 24^3, 16 orbitals, Coulomb, phi = psi
-    "cfg0": dict(n=24, L=A_SI_BOHR, N=16, n_targets=16, kernel="coulomb", seed=0),
+    "24cube_16": dict(n=24, L=A_SI_BOHR, N=16, n_targets=16, kernel="coulomb", seed=0),
     # 64-Si-atom cell, 48^3, 128 orbitals, screened HSE, phi = psi
-    "cfg1": dict(n=48, L=2 * A_SI_BOHR, N=128, n_targets=128, kernel="hse", seed=1),
+    "48cube_128": dict(n=48, L=2 * A_SI_BOHR, N=128, n_targets=128, kernel="hse", seed=1),
     # one GPU's band-index share of a 512-atom cell: 96^3, 1024 psi, 32 targets
-    "cfg2": dict(n=96, L=4 * A_SI_BOHR, N=1024, n_targets=32, kernel="hse", seed=2),
+    "96cube_1024x32": dict(n=96, L=4 * A_SI_BOHR, N=1024, n_targets=32, kernel="hse", seed=2),
     # serving classes
     "serveA": dict(n=24, L=A_SI_BOHR, N=16, n_targets=8, kernel="hse", seed=4000),
     "serveB": dict(n=48, L=2 * A_SI_BOHR, N=128, n_targets=8, kernel="hse", seed=4100),

@@ -22,13 +22,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 def small_case():
     """24^3 cell of 10.26 bohr, 16 orbitals, Coulomb: the 8-Si-atom workload."""
-    w = synth.workload("cfg0")
+    w = synth.workload("24cube_16")
     psi = synth.make_orbitals(w["seed"], w["n"], w["L"], w["N"])
     out = oracle.apply_vx(psi, psi, w["n"], w["L"], "coulomb")
     ace = oracle.build_ace(psi, out)
     probes = [(0, 0, 0, 0), (3, 5, 7, 11), (15, 23, 1, 9), (8, 12, 12, 12)]
     return {
-        "workload": "cfg0",
+        "workload": "24cube_16",
         "ex": oracle.exchange_energy(psi, out),
         "trace_M": float(np.trace(ace["M"]).real),
         "col_norms": [float(np.linalg.norm(out[k])) for k in range(out.shape[0])],
@@ -40,6 +40,6 @@ def small_case():
 
 if __name__ == "__main__":
     data = small_case()
-    with open(os.path.join(HERE, "cfg0_oracle.json"), "w") as f:
+    with open(os.path.join(HERE, "24cube_16_oracle.json"), "w") as f:
         json.dump(data, f, indent=1)
-    print("wrote cfg0_oracle.json")
+    print("wrote 24cube_16_oracle.json")

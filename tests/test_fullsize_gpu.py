@@ -20,7 +20,7 @@ pytestmark = pytest.mark.gpu
 def share():
     import torch
 
-    w = synth.workload("cfg2")
+    w = synth.workload("96cube_1024x32")
     say("generating the 96^3 share (1024 orbitals)")
     psi = synth.make_orbitals(w["seed"], w["n"], w["L"], w["N"], dtype=np.complex64)
     P = torch.from_numpy(psi).to("cuda:0")

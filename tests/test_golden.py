@@ -10,9 +10,9 @@ import synth
 HERE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
-def test_cfg0_oracle_frozen():
-    g = json.load(open(os.path.join(HERE, "cfg0_oracle.json")))
-    w = synth.workload("cfg0")
+def test_24cube_oracle_frozen():
+    g = json.load(open(os.path.join(HERE, "24cube_16_oracle.json")))
+    w = synth.workload("24cube_16")
     psi = synth.make_orbitals(w["seed"], w["n"], w["L"], w["N"])
     out = oracle.apply_vx(psi, psi, w["n"], w["L"], "coulomb")
     assert abs(oracle.exchange_energy(psi, out) - g["ex"]) <= 1e-11 * abs(g["ex"])

@@ -27,18 +27,18 @@ def ctx():
 
 
 @pytest.fixture(scope="module")
-def cfg0():
-    w = synth.workload("cfg0")
+def w24():
+    w = synth.workload("24cube_16")
     psi = synth.make_orbitals(w["seed"], w["n"], w["L"], w["N"])
     ref = oracle.apply_vx(psi, psi, w["n"], w["L"], "coulomb")
     return w, psi, ref
 
 
-def test_cfg0_fp64_parity_and_energy(ctx, cfg0):
+def test_24cube_fp64_parity_and_energy(ctx, w24):
     import torch
 
-    w, psi, ref = cfg0
-    say("cfg0 fp64", psi.shape)
+    w, psi, ref = w24
+    say("24^3 fp64", psi.shape)
     out, ex = ctx.apply_vx(dev(psi), n=w["n"], L=w["L"], kernel="coulomb", prec="fp64", energy=True)
     torch.cuda.synchronize()
     assert col_err(host(out), ref) <= TOL64
@@ -47,11 +47,11 @@ def test_cfg0_fp64_parity_and_energy(ctx, cfg0):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp32acc64"])
-def test_cfg0_fp32_paths(ctx, cfg0, prec):
+def test_24cube_fp32_paths(ctx, w24, prec):
     import torch
 
-    w, psi, ref = cfg0
-    say("cfg0", prec)
+    w, psi, ref = w24
+    say("24cube_16", prec)
     for in_dtype in (torch.complex128, torch.complex64):
         out = ctx.apply_vx(dev(psi, in_dtype), n=w["n"], L=w["L"], kernel="coulomb", prec=prec)
         err = col_err(host(out), ref)
@@ -126,9 +126,9 @@ def test_planewave_closed_form_on_gpu(ctx):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32acc64", "fp32"])
-def test_batching_invariance_and_repeatability_bitwise(ctx, cfg0, prec):
+def test_batching_invariance_and_repeatability_bitwise(ctx, w24, prec):
     """The j-sum order is fixed: results are bitwise identical for any batch size and across runs."""
-    w, psi, _ = cfg0
+    w, psi, _ = w24
     P = dev(psi)
     outs = []
     for nj in ("", "1", "3", "16"):
@@ -146,16 +146,16 @@ def test_batching_invariance_and_repeatability_bitwise(ctx, cfg0, prec):
                               outs[0].view(np.float64 if o.dtype == np.complex128 else np.float32))
 
 
-def test_cfg1_sampled_columns(ctx):
+def test_48cube_sampled_columns(ctx):
     """48^3, 128 orbitals, HSE: every precision on all 128 targets, oracle on 3 sampled targets."""
     import torch
 
-    w = synth.workload("cfg1")
-    say("cfg1 generating")
+    w = synth.workload("48cube_128")
+    say("48^3 generating")
     psi = synth.make_orbitals(w["seed"], w["n"], w["L"], w["N"])
     P = dev(psi)
     ks = [0, 77, 127]
-    say("cfg1 oracle on", ks)
+    say("48^3 oracle on", ks)
     ref = oracle.apply_vx(psi, psi, w["n"], w["L"], "hse", targets=ks, workers=workers())
     outs = {}
     for prec, tol in (("fp64", TOL64), ("fp32acc64", TOL32), ("fp32", TOL32)):
@@ -163,7 +163,7 @@ def test_cfg1_sampled_columns(ctx):
         torch.cuda.synchronize()
         outs[prec] = out
         err = col_err(host(out[ks]), ref)
-        say("cfg1", prec, err)
+        say("48cube_128", prec, err)
         assert err <= tol
     # FP32 forms against the GPU FP64 form on every column
     r64 = host(outs["fp64"])
@@ -171,11 +171,11 @@ def test_cfg1_sampled_columns(ctx):
     assert col_err(host(outs["fp32"]), r64) <= TOL32
 
 
-def test_error_paths(ctx, cfg0):
+def test_error_paths(ctx, w24):
     import torch
     from paper_1905_01348_amd import FockError
 
-    w, psi, _ = cfg0
+    w, psi, _ = w24
     P = dev(psi)
     with pytest.raises(FockError) as ei:  # out aliases psi
         ctx.apply_vx(P, n=w["n"], L=w["L"], out=P, prec="fp64")
