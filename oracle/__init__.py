@@ -13,6 +13,7 @@ listed in ``oracle.fock.PINS``; no function is "parity unpinned".
 from .fock import (  # noqa: F401
     PINS,
     apply_ace,
+    apply_kinetic,
     apply_vx,
     build_ace,
     density,

@@ -1,5 +1,6 @@
-"""Plain FP64 definitions of V_X, the exchange energy, ACE, and the end-of-step
-operations (PT residual, Cholesky-QR re-orthonormalisation, density) (test infrastructure).
+"""Plain FP64 definitions of V_X, the exchange energy, ACE, the kinetic operator, and the
+end-of-step operations (PT residual, Cholesky-QR re-orthonormalisation, density) (test
+infrastructure).
 
 Conventions (readings of the paper, each listed in the design notes):
   * An orbital is a Euclidean-normalised grid vector on an nx*ny*nz grid of a
@@ -41,6 +42,8 @@ PINS = {
     "exchange_energy": "planewave closed form of the trace",
     "build_ace": "planewave closed form of M and L; K_ACE psi_i = W_i; tr M = -||L||_F^2",
     "apply_ace": "exactness on span(Psi); annihilation of the orthogonal complement; Hermitian NSD rank <= N",
+    "apply_kinetic": "planewave closed form |G|^2/2 (Nyquist rows, orthorhombic cell); second differences of a "
+                     "band-limited function against the exact Laplacian; Hermitian and positive semidefinite",
     "pt_residual": "planewave eigenbasis (H Psi = Psi Lambda gives R = Psi - Psi_half); projections onto span(Psi) "
                    "(zero) and onto its complement from a complete Householder QR ((i dt/2) Q_perp^H H Psi); gauge "
                    "covariance",
@@ -193,6 +196,22 @@ def vx_dense_matrix(psi, n, L, kind="coulomb", omega=0.106, scale=1.0):
     eye = np.eye(nr, dtype=np.complex128).reshape(nr, nz, ny, nx)
     cols = apply_vx(psi, eye, n, L, kind, omega, scale)
     return cols.reshape(nr, nr).T
+
+
+def apply_kinetic(phi, n, L):
+    """Kinetic operator -(1/2) Laplacian of the Hamiltonian (Sec. 2) applied to each orbital of phi.
+
+    On the periodic grid it is diagonal in the planewave basis: each planewave
+    coefficient of phi is multiplied by |G|^2/2 (G as in g2_grid, so the
+    Nyquist row of an even edge has |G_a| = pi n_a / L_a).  Returns complex128
+    with the shape (N, nz, ny, nx).
+    """
+    phi = _grid(phi, n).astype(np.complex128)
+    half_g2 = 0.5 * g2_grid(n, L)
+    out = np.empty_like(phi)
+    for k in range(phi.shape[0]):
+        out[k] = np.fft.ifftn(half_g2 * np.fft.fftn(phi[k]))
+    return out
 
 
 def _cols(a):

@@ -474,6 +474,56 @@ def check_density_gauge_and_sum(orc, seed=13, n3=(5, 4, 6), n=4):
     return float(max(e1, e2, e3, e4))
 
 
+def check_kinetic_planewave(orc, n3=(6, 4, 8), L3=(4.0, 3.0, 5.5)):
+    """-(1/2) Laplacian of e^{i G.r} is (|G|^2/2) e^{i G.r}; m = n/2 on an even edge is the Nyquist row,
+    whose |G_a| is pi n_a / L_a whichever sign it is given."""
+    mvecs = [(0, 0, 0), (1, 0, 0), (0, -1, 2), (3, 2, 4), (-2, 1, -3), (2, -2, 1)]
+    psi = _planewave_block(n3, L3, mvecs)
+    out = orc.apply_kinetic(psi, n3, L3)
+    err = 0.0
+    for k, m in enumerate(mvecs):
+        g2 = sum((2 * np.pi * _wrap(m[a], n3[a]) / L3[a]) ** 2 for a in range(3))
+        ref = 0.5 * g2 * psi[k]
+        err = max(err, float(np.abs(out[k] - ref).max() / np.abs(psi[k]).max() / max(g2, 1.0)))
+    return err
+
+
+def check_kinetic_smooth(orc, n3=(40, 32, 48), L3=(6.0, 4.5, 7.5), amp=(0.4, 0.3, 0.5)):
+    """f = exp(sum_a c_a cos(2 pi x_a / L_a)) is smooth and periodic; -(1/2) Laplacian f, written out
+    from the chain rule, is f * sum_a -(1/2) (c_a^2 k_a^2 sin^2 - c_a k_a^2 cos) with k_a = 2 pi / L_a.
+    The spectral operator reaches it to rounding once the coefficients have decayed."""
+    nx, ny, nz = n3
+    ax = [np.arange(n3[a]) * L3[a] / n3[a] for a in range(3)]
+    Z, Y, X = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+    coords = (X, Y, Z)
+    e = sum(amp[a] * np.cos(2 * np.pi * coords[a] / L3[a]) for a in range(3))
+    f = np.exp(e)
+    lap = np.zeros_like(f)
+    for a in range(3):
+        k = 2 * np.pi / L3[a]
+        c = amp[a]
+        lap += (c * c * k * k * np.sin(k * coords[a]) ** 2 - c * k * k * np.cos(k * coords[a])) * f
+    ref = -0.5 * lap
+    got = orc.apply_kinetic(f[None].astype(complex), n3, L3)[0]
+    return float(np.abs(got - ref).max() / np.abs(ref).max())
+
+
+def check_kinetic_hermitian_psd(orc, n3=(5, 6, 4), L3=(3.0, 4.0, 2.5), seed=14):
+    """<x, T y> = <T x, y> and <x, T x> >= 0 (T = -(1/2) Laplacian).  Returns the worse of the
+    asymmetry and any negative part, relative to ||x|| ||T y||."""
+    rng = np.random.default_rng(seed)
+    nr = n3[0] * n3[1] * n3[2]
+    x = (rng.standard_normal(nr) + 1j * rng.standard_normal(nr)).reshape(1, n3[2], n3[1], n3[0])
+    y = (rng.standard_normal(nr) + 1j * rng.standard_normal(nr)).reshape(1, n3[2], n3[1], n3[0])
+    tx = orc.apply_kinetic(x, n3, L3)
+    ty = orc.apply_kinetic(y, n3, L3)
+    scale = np.linalg.norm(x) * np.linalg.norm(ty)
+    asym = abs(np.vdot(x, ty) - np.vdot(tx, y)) / scale
+    q = np.vdot(x, tx)
+    neg = max(0.0, -q.real) / scale + abs(q.imag) / scale
+    return float(max(asym, neg))
+
+
 # name -> (callable, bound)
 ALL = {
     "naive_dft": (check_naive_dft, 1e-12),
@@ -504,4 +554,7 @@ ALL = {
     "cholqr_properties": (check_cholqr_properties, 1e-12),
     "density_planewave": (check_density_planewave, 1e-12),
     "density_gauge_and_sum": (check_density_gauge_and_sum, 1e-12),
+    "kinetic_planewave": (check_kinetic_planewave, 1e-13),
+    "kinetic_smooth": (check_kinetic_smooth, 1e-10),
+    "kinetic_hermitian_psd": (check_kinetic_hermitian_psd, 1e-13),
 }

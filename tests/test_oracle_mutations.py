@@ -43,6 +43,11 @@ MUTATIONS = {
     "cholqr_missing_conj": ("return Z.conj().reshape(np.shape(psi))", "return Z.reshape(np.shape(psi))"),
     "density_square_not_modulus": ("rho += f[i] * (X[i].real ** 2 + X[i].imag ** 2)",
                                    "rho += f[i] * (X[i].real ** 2 - X[i].imag ** 2)"),
+    "kinetic_without_half": ("half_g2 = 0.5 * g2_grid(n, L)", "half_g2 = g2_grid(n, L)"),
+    "kinetic_sign": ("half_g2 = 0.5 * g2_grid(n, L)", "half_g2 = -0.5 * g2_grid(n, L)"),
+    "kinetic_inverse_missing": ("out[k] = np.fft.ifftn(half_g2 * np.fft.fftn(phi[k]))",
+                                "out[k] = half_g2 * np.fft.fftn(phi[k]) / phi[k].size"),
+    "kinetic_lengths_reversed": ("half_g2 = 0.5 * g2_grid(n, L)", "half_g2 = 0.5 * g2_grid(n, _as_l3(L)[::-1])"),
     "density_ignores_occupation": ("rho += f[i] * (X[i].real ** 2 + X[i].imag ** 2)",
                                    "rho += (X[i].real ** 2 + X[i].imag ** 2)"),
 }
