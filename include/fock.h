@@ -276,15 +276,28 @@ fx_status fx_ace_free(fx_ace* ace);
  * End-of-step operations of PT-CN (all arithmetic FP64; complex64 blocks are
  * widened on input and rounded on output).
  *
+ * fx_apply_kinetic: out = T phi with T = -(1/2) Laplacian, the kinetic term of
+ *   the Hamiltonian (Sec. 2), on the periodic grid of the cell: each planewave
+ *   coefficient of phi_k is multiplied by |G|^2/2, G_a = 2 pi m_a / len_a with
+ *   m_a in FFT order (on an even edge the row m_a = n_a/2 has |G_a| =
+ *   pi n_a / len_a).  phi: device, n_phi columns of N_r, stride ld_phi,
+ *   in_dtype; out: device, n_phi columns, stride ld_out, out_dtype,
+ *   overwritten, must not overlap phi.  Computed by the V_X pair path (FP64)
+ *   with the constant orbital 1 and the kernel |G|^2/(2 N_r); the first call
+ *   on a grid allocates its tables and workspace.  Errors: FX_ERR_INVALID,
+ *   FX_ERR_UNSUPPORTED, FX_ERR_OOM, FX_ERR_DEVICE.
+ *
  * fx_pt_residual: the residual of the PT-CN fixed point (the residual
  *   algorithm of Sec. 3.3, for the parallel-transport equation of Sec. 2):
  *     S = Psi^H (H Psi),  R = Psi + (i dt/2)(H Psi - Psi S) - Psi_half.
  *   psi, hpsi, psi_half: device blocks of n columns, stride ld, dtype; hpsi
  *   NULL means H = V_X[psi] (computed by the pair path with vx_prec; kernel
- *   then required).  r_out: device, n columns, stride ld_r, dtype; must not
- *   overlap the inputs.  s_out: nullable device n x n complex128
- *   column-major, receives S.  The cell gives N_r (and the grid when hpsi is
- *   NULL).  Errors: FX_ERR_INVALID, FX_ERR_UNSUPPORTED, FX_ERR_OOM,
+ *   then required).  kinetic nonzero adds the kinetic term: H Psi becomes
+ *   hpsi + T psi (or V_X[psi] psi + T psi), T as in fx_apply_kinetic.
+ *   r_out: device, n columns, stride ld_r, dtype; must not overlap the
+ *   inputs.  s_out: nullable device n x n complex128 column-major, receives
+ *   S.  The cell gives N_r (and the grid and lengths when hpsi is NULL or
+ *   kinetic is set).  Errors: FX_ERR_INVALID, FX_ERR_UNSUPPORTED, FX_ERR_OOM,
  *   FX_ERR_DEVICE.
  *
  * fx_orthonormalize: Cholesky-QR re-orthonormalisation in place (Sec. 3.4):
@@ -295,9 +308,12 @@ fx_status fx_ace_free(fx_ace* ace);
  *   ascending order in FP64.  occ: nullable device array of n doubles (all 1
  *   if NULL); rho: device array of nr doubles, overwritten.
  */
+fx_status fx_apply_kinetic(fx_ctx* ctx, const fx_cell* cell, const void* phi, int32_t n_phi, int64_t ld_phi,
+                           void* out, int64_t ld_out, fx_dtype in_dtype, fx_dtype out_dtype, void* stream);
 fx_status fx_pt_residual(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* kernel, const void* psi,
                          const void* hpsi, const void* psi_half, int32_t n, int64_t ld, fx_dtype dtype,
-                         double dt, fx_prec vx_prec, void* r_out, int64_t ld_r, void* s_out, void* stream);
+                         double dt, fx_prec vx_prec, int32_t kinetic, void* r_out, int64_t ld_r, void* s_out,
+                         void* stream);
 fx_status fx_orthonormalize(fx_ctx* ctx, void* psi, int32_t n, int64_t ld, int64_t nr, fx_dtype dtype,
                             void* stream);
 fx_status fx_density(fx_ctx* ctx, const void* psi, int32_t n, int64_t ld, int64_t nr, fx_dtype dtype,

@@ -196,7 +196,11 @@ void host_tables(const fx_cell* cell, const fx_kernel* kern, HostTables* h, cons
 
 bool supported_edge(int n);
 fx_status check_cell(const fx_cell* cell);
-fx_status check_kernel(const fx_kernel* k);
+// Kernel kind used inside the library only: the symbol |G|^2/(2 N_r) of the
+// kinetic operator, so that the pair path with the constant orbital 1 applies
+// -(1/2) Laplacian.  Public calls reject it.
+constexpr int kKineticKind = 100;
+fx_status check_kernel(const fx_kernel* k, bool allow_internal = false);
 
 // Bracket a launch with events when timing is on (no-ops otherwise).
 fx_status prof_begin(fx_ctx* ctx, hipStream_t st, int id, double work, int* slot);

@@ -326,9 +326,10 @@ fx_status check_cell(const fx_cell* cell) {
   return FX_OK;
 }
 
-fx_status check_kernel(const fx_kernel* k) {
+fx_status check_kernel(const fx_kernel* k, bool allow_internal) {
   if (!k) FX_FAIL(FX_ERR_INVALID, "kernel is NULL");
-  if (k->kind != FX_COULOMB && k->kind != FX_HSE) FX_FAIL(FX_ERR_UNSUPPORTED, "unknown kernel kind %d", k->kind);
+  if (k->kind != FX_COULOMB && k->kind != FX_HSE && !(allow_internal && k->kind == kKineticKind))
+    FX_FAIL(FX_ERR_UNSUPPORTED, "unknown kernel kind %d", k->kind);
   if (k->kind == FX_HSE && !(k->omega > 0.0)) FX_FAIL(FX_ERR_INVALID, "HSE omega = %g must be positive", k->omega);
   if (!std::isfinite(k->scale)) FX_FAIL(FX_ERR_INVALID, "kernel scale is not finite");
   return FX_OK;
@@ -371,13 +372,16 @@ void host_tables(const fx_cell* cell, const fx_kernel* kern, HostTables* h, cons
   }
   const int hx = cell->n[0] / 2 + 1, hy = cell->n[1] / 2 + 1, hz = cell->n[2] / 2 + 1;
   const double vol = cell->len[0] * cell->len[1] * cell->len[2];
+  const double nr = (double)cell->n[0] * cell->n[1] * cell->n[2];
   h->kfold.assign((size_t)hx * hy * hz, 0.0);
   for (int z = 0; z < hz; ++z)
     for (int y = 0; y < hy; ++y)
       for (int x = 0; x < hx; ++x) {
         const double gx = 2 * pi * x / cell->len[0], gy = 2 * pi * y / cell->len[1], gz = 2 * pi * z / cell->len[2];
         const double g2 = gx * gx + gy * gy + gz * gz;
-        h->kfold[((size_t)z * hy + y) * hx + x] = -kern->scale / vol * kernel_value(kern->kind, kern->omega, g2);
+        h->kfold[((size_t)z * hy + y) * hx + x] = kern->kind == kKineticKind
+                                                      ? 0.5 * g2 / nr
+                                                      : -kern->scale / vol * kernel_value(kern->kind, kern->omega, g2);
       }
 }
 

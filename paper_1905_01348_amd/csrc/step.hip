@@ -1,8 +1,9 @@
 // The operations at the end of a PT-CN step: the residual of the fixed-point
 // equation (the residual algorithm of Sec. 3.3), the Cholesky-QR
-// re-orthonormalisation of the orbitals and the electron density (Sec. 3.4).
-// All arithmetic is FP64; complex64 blocks are widened on the way in and
-// rounded on the way out.
+// re-orthonormalisation of the orbitals and the electron density (Sec. 3.4);
+// and the kinetic operator -(1/2) Laplacian of the Hamiltonian (Sec. 2),
+// which a residual may add to H.  All arithmetic is FP64; complex64 blocks
+// are widened on the way in and rounded on the way out.
 #include <algorithm>
 
 #include "common.hpp"
@@ -23,6 +24,24 @@ __global__ void __launch_bounds__(256) k_residual_init(const cpx<double>* __rest
     const cpx<double> p = psi[c * ldp + e], h = hpsi[c * ldh + e], f = half[c * ldf + e];
     r[c * ldr + e] = cpx<double>{p.x - f.x - hdt * h.y, p.y - f.y + hdt * h.x};
   }
+}
+
+// dst += src, n columns of nr FP64 complex values.
+__global__ void __launch_bounds__(256) k_add_cols(cpx<double>* __restrict__ dst, int64_t ldd,
+                                                  const cpx<double>* __restrict__ src, int64_t lds, int64_t nr, int n) {
+  const int64_t total = nr * n;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = i / nr, e = i - c * nr;
+    const cpx<double> a = dst[c * ldd + e], b = src[c * lds + e];
+    dst[c * ldd + e] = cpx<double>{a.x + b.x, a.y + b.y};
+  }
+}
+
+// the constant 1 at nr points
+template <typename T>
+__global__ void __launch_bounds__(256) k_fill_one(cpx<T>* __restrict__ p, int64_t nr) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < nr; e += (int64_t)gridDim.x * blockDim.x)
+    p[e] = cpx<T>{(T)1, (T)0};
 }
 
 // rho[e] = sum_c f_c |psi_c[e]|^2 over c ascending, FP64 (f = 1 if occ is null).
@@ -74,9 +93,44 @@ static bool overlaps(const void* a, int n, int64_t lda, const void* b, int m, in
   return a0 < b1 && b0 < a1;
 }
 
+// out = -(1/2) Laplacian phi on the periodic grid: each planewave coefficient
+// times |G|^2/2 (Sec. 2).  It is the pair path with the constant orbital 1 as
+// its only psi and |G|^2/(2 N_r) as its kernel, in FP64: conj(1) phi = phi,
+// the FFT, the symbol, the inverse FFT, times 1.
+static fx_status apply_kinetic(fx_ctx* ctx, Workspace* ws, const fx_cell* cell, const void* phi, int n,
+                               int64_t ld, fx_dtype din, void* out, int64_t ld_out, fx_dtype dout, hipStream_t st) {
+  FX_TRY(check_cell(cell));
+  if (din != FX_C128 && din != FX_C64) FX_FAIL(FX_ERR_UNSUPPORTED, "unknown in_dtype %d", din);
+  const int64_t nr = (int64_t)cell->n[0] * cell->n[1] * cell->n[2];
+  void* ones = nullptr;
+  FX_TRY(ws_get(ctx, ws, "kin_ones", dtype_size(din) * (size_t)nr, &ones));
+  if (din == FX_C128)
+    hipLaunchKernelGGL(k_fill_one<double>, dim3(grid_for(nr)), dim3(256), 0, st, (cpx<double>*)ones, nr);
+  else
+    hipLaunchKernelGGL(k_fill_one<float>, dim3(grid_for(nr)), dim3(256), 0, st, (cpx<float>*)ones, nr);
+  FX_LAUNCH_CHECK();
+  const fx_kernel kk{kKineticKind, 0.0, 1.0};
+  VxArgs va;
+  va.cell = cell;
+  va.kern = &kk;
+  va.internal_kernel = true;
+  va.psi = ones;
+  va.n_psi = 1;
+  va.ld_psi = nr;
+  va.phi = phi;
+  va.n_phi = n;
+  va.ld_phi = ld;
+  va.out = out;
+  va.ld_out = ld_out;
+  va.in_dtype = din;
+  va.out_dtype = dout;
+  va.prec = FX_PREC_FP64;
+  return vx_apply(ctx, ws, va, st, nullptr);
+}
+
 static fx_status pt_residual(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* kern, const void* psi,
                              const void* hpsi, const void* half, int n, int64_t ld, fx_dtype dt, double dtime,
-                             fx_prec vx_prec, void* r, int64_t ldr, void* s_out, hipStream_t st) {
+                             fx_prec vx_prec, int kinetic, void* r, int64_t ldr, void* s_out, hipStream_t st) {
   FX_TRY(check_cell(cell));
   const int64_t nr = (int64_t)cell->n[0] * cell->n[1] * cell->n[2];
   FX_TRY(check_block(psi, n, ld, nr, dt, "psi"));
@@ -115,6 +169,17 @@ static fx_status pt_residual(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* 
     va.prec = vx_prec;
     FX_TRY(vx_apply(ctx, ws, va, st, nullptr));
     h64 = w;
+    ldh = nr;
+  }
+  if (kinetic) {
+    // H Psi + T Psi in a buffer of the library's (hpsi may be the caller's)
+    void* kin = nullptr;
+    FX_TRY(ws_get(ctx, ws, "pt_kin", (size_t)16 * nr * n, &kin));
+    FX_TRY(apply_kinetic(ctx, ws, cell, psi, n, ld, dt, kin, nr, FX_C128, st));
+    hipLaunchKernelGGL(k_add_cols, dim3(grid_for(nr * n)), dim3(256), 0, st, (cpx<double>*)kin, nr,
+                       (const cpx<double>*)h64, ldh, nr, n);
+    FX_LAUNCH_CHECK();
+    h64 = kin;
     ldh = nr;
   }
   // S = Psi^H (H Psi), N x N, FP64 (split over N_r with a fixed-order reduction)
@@ -196,16 +261,28 @@ using namespace fx;
 
 extern "C" {
 
-fx_status fx_pt_residual(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* kernel, const void* psi, const void* hpsi,
-                         const void* psi_half, int32_t n, int64_t ld, fx_dtype dtype, double dt, fx_prec vx_prec,
-                         void* r_out, int64_t ld_r, void* s_out, void* stream) {
+fx_status fx_apply_kinetic(fx_ctx* ctx, const fx_cell* cell, const void* phi, int32_t n_phi, int64_t ld_phi,
+                           void* out, int64_t ld_out, fx_dtype in_dtype, fx_dtype out_dtype, void* stream) {
   clear_error();
   if (!ctx) FX_FAIL(FX_ERR_INVALID, "ctx is NULL");
   std::lock_guard<std::recursive_mutex> lk(ctx->mu);
   FX_HIP(hipSetDevice(ctx->device));
   hipStream_t st = (hipStream_t)stream;
   FX_TRY(note_capture(ctx, st));
-  return pt_residual(ctx, cell, kernel, psi, hpsi, psi_half, n, ld, dtype, dt, vx_prec, r_out, ld_r, s_out, st);
+  return apply_kinetic(ctx, &ctx->ws, cell, phi, n_phi, ld_phi, in_dtype, out, ld_out, out_dtype, st);
+}
+
+fx_status fx_pt_residual(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* kernel, const void* psi, const void* hpsi,
+                         const void* psi_half, int32_t n, int64_t ld, fx_dtype dtype, double dt, fx_prec vx_prec,
+                         int32_t kinetic, void* r_out, int64_t ld_r, void* s_out, void* stream) {
+  clear_error();
+  if (!ctx) FX_FAIL(FX_ERR_INVALID, "ctx is NULL");
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  FX_HIP(hipSetDevice(ctx->device));
+  hipStream_t st = (hipStream_t)stream;
+  FX_TRY(note_capture(ctx, st));
+  return pt_residual(ctx, cell, kernel, psi, hpsi, psi_half, n, ld, dtype, dt, vx_prec, kinetic, r_out, ld_r, s_out,
+                     st);
 }
 
 fx_status fx_orthonormalize(fx_ctx* ctx, void* psi, int32_t n, int64_t ld, int64_t nr, fx_dtype dtype, void* stream) {

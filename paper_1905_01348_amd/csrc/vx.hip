@@ -649,7 +649,7 @@ fx_status convert_cols(const void* in, fx_dtype din, int64_t ld_in, void* out, f
 
 fx_status check_vx_args(const VxArgs& a) {
   FX_TRY(check_cell(a.cell));
-  FX_TRY(check_kernel(a.kern));
+  FX_TRY(check_kernel(a.kern, a.internal_kernel));
   const int64_t nr = (int64_t)a.cell->n[0] * a.cell->n[1] * a.cell->n[2];
   if (!a.psi || !a.phi || !a.out) FX_FAIL(FX_ERR_INVALID, "psi, phi and out must be non-NULL device pointers");
   if (a.n_psi <= 0 || a.n_phi <= 0) FX_FAIL(FX_ERR_INVALID, "n_psi = %d and n_phi = %d must be positive", a.n_psi, a.n_phi);

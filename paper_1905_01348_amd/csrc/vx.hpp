@@ -21,6 +21,7 @@ struct VxArgs {
   fx_dtype out_dtype = FX_C128;
   fx_prec prec = FX_PREC_FP64;
   double* ex_dev = nullptr;
+  bool internal_kernel = false;  // kern may be the library's own kinetic kind
   // launch configuration (0 / -1 = automatic: the context's tuned
   // configuration for this grid and form if there is one, else defaults)
   size_t work_cap = 0;  // bytes of pair work volume per batch

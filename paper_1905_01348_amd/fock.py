@@ -119,9 +119,11 @@ _SIGS = {
     "fx_debug_host_pair_plan": (C.c_int, [C.POINTER(FxCell), C.POINTER(FxKernel), C.c_int, C.c_void_p, C.c_void_p,
                                            C.c_void_p, C.c_void_p]),
     "fx_debug_axis_plans": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.POINTER(C.c_int32)]),
+    "fx_apply_kinetic": (C.c_int, [C.c_void_p, C.POINTER(FxCell), C.c_void_p, C.c_int32, C.c_int64, C.c_void_p,
+                                   C.c_int64, C.c_int, C.c_int, C.c_void_p]),
     "fx_pt_residual": (C.c_int, [C.c_void_p, C.POINTER(FxCell), C.POINTER(FxKernel), C.c_void_p, C.c_void_p,
-                                 C.c_void_p, C.c_int32, C.c_int64, C.c_int, C.c_double, C.c_int, C.c_void_p, C.c_int64,
-                                 C.c_void_p, C.c_void_p]),
+                                 C.c_void_p, C.c_int32, C.c_int64, C.c_int, C.c_double, C.c_int, C.c_int32, C.c_void_p,
+                                 C.c_int64, C.c_void_p, C.c_void_p]),
     "fx_orthonormalize": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int64, C.c_int64, C.c_int, C.c_void_p]),
     "fx_density": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int64, C.c_int64, C.c_int, C.c_void_p,
                              C.c_void_p, C.c_void_p]),
@@ -285,9 +287,26 @@ class Context:
         return (out, ex) if energy else out
 
     # -- end-of-step operations ----------------------------------------------------
+    def apply_kinetic(self, phi, *, n, L, out=None, out_dtype=None, stream=None):
+        """out = -(1/2) Laplacian phi on the periodic grid (|G|^2/2 on each planewave), FP64."""
+        import torch
+
+        cell = make_cell(n, L)
+        nr = cell.n[0] * cell.n[1] * cell.n[2]
+        fp, nphi, ldf = _cols(phi, nr)
+        if out is None:
+            out = torch.empty((nphi,) + tuple(phi.shape[1:]), dtype=out_dtype or phi.dtype, device=phi.device)
+        op, nout, ldo = _cols(out, nr)
+        if nout != nphi:
+            raise ValueError("out must have as many columns as phi")
+        _check(load().fx_apply_kinetic(self.h, C.byref(cell), fp, nphi, ldf, op, ldo, _dtype_code(phi),
+                                       _dtype_code(out), _stream_ptr(stream)))
+        return out
+
     def pt_residual(self, psi, psi_half, *, n, L, hpsi=None, dt, kernel="hse", omega=0.106, scale=1.0,
-                    vx_prec="fp32acc64", out=None, s_out=None, stream=None):
-        """R = Psi + (i dt/2)(H Psi - Psi S) - Psi_half with S = Psi^H H Psi; H = V_X if hpsi is None."""
+                    vx_prec="fp32acc64", kinetic=False, out=None, s_out=None, stream=None):
+        """R = Psi + (i dt/2)(H Psi - Psi S) - Psi_half with S = Psi^H H Psi; H = V_X if hpsi is None,
+        plus -(1/2) Laplacian if kinetic."""
         import torch
 
         cell = make_cell(n, L)
@@ -311,7 +330,8 @@ class Context:
                 raise ValueError("s_out must be a contiguous complex128 tensor of n x n")
             sp = C.c_void_p(s_out.data_ptr())
         _check(load().fx_pt_residual(self.h, C.byref(cell), C.byref(kern), pp, hp, fp, npsi, ldp, _dtype_code(psi),
-                                     float(dt), PREC[vx_prec], op, ldo, sp, _stream_ptr(stream)))
+                                     float(dt), PREC[vx_prec], 1 if kinetic else 0, op, ldo, sp,
+                                     _stream_ptr(stream)))
         return out
 
     def orthonormalize(self, psi, *, stream=None):

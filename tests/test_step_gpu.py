@@ -1,6 +1,7 @@
 """End-of-step operations on the GPU against the FP64 oracle.
 
-Residual (given H Psi, and with H = V_X computed by the pair path), Cholesky-QR
+Residual (given H Psi, and with H = V_X computed by the pair path, each with
+or without the kinetic term), the kinetic operator, Cholesky-QR
 re-orthonormalisation and density.  Tolerances (relative, per column):
 complex128 blocks 1e-12 (pure FP64 GEMM and elementwise work; 1e-10 where
 the V_X pair path or a Cholesky factor enters), complex64 blocks 1e-6 (the
@@ -78,6 +79,86 @@ def test_residual_with_vx(ctx, vx_prec, tol):
     say("residual with V_X", vx_prec, err)
     # the V_X error enters through (dt/2) H Psi, small against Psi - Psi_half
     assert err <= tol
+
+
+KIN_CASES = [((24, 24, 24), (10.26,) * 3, 5), ((24, 18, 16), (10.0, 8.0, 7.0), 6), ((9, 8, 6), (4.0, 4.0, 3.0), 3),
+             ((96, 96, 96), (41.04,) * 3, 2)]
+
+
+@pytest.mark.parametrize("case", KIN_CASES, ids=[f"{c[0]}-N{c[2]}" for c in KIN_CASES])
+def test_kinetic(ctx, case):
+    """-(1/2) Laplacian against the oracle: complex128 at the FP64 bar (1e-10), complex64 in and out at
+    the rounding of the output (1e-6, the oracle on the same rounded inputs)."""
+    import torch
+
+    n3, L3, N = case
+    phi = _block(95, n3, N)
+    ref = oracle.apply_kinetic(phi, n3, L3)
+    for dtype, tol in ((torch.complex128, 1e-10), (torch.complex64, 1e-6)):
+        Q = dev(phi, dtype)
+        ref_t = ref if dtype == torch.complex128 else oracle.apply_kinetic(host(Q).astype(np.complex128), n3, L3)
+        got = ctx.apply_kinetic(Q, n=n3, L=L3)
+        assert got.dtype == dtype
+        err = col_err(host(got), ref_t)
+        say("kinetic", n3, N, dtype, err)
+        assert err <= tol
+
+
+def test_kinetic_planewaves(ctx):
+    """e^{i G.r} is an eigenvector with eigenvalue |G|^2/2, written out here (Nyquist rows included)."""
+    n3, L3 = (12, 8, 6), (5.0, 4.0, 3.0)
+    mvecs = [(0, 0, 0), (1, 0, 0), (6, 0, 0), (0, 4, 0), (-2, 3, 3), (5, -1, 2)]
+    psi = synth.planewave_orbitals(n3, L3, mvecs)
+    got = host(ctx.apply_kinetic(dev(psi), n=n3, L=L3))
+    for k, m in enumerate(mvecs):
+        w = [((m[a] + n3[a] // 2) % n3[a]) - n3[a] // 2 for a in range(3)]
+        lam = 0.5 * sum((2 * np.pi * w[a] / L3[a]) ** 2 for a in range(3))
+        assert np.abs(got[k] - lam * psi[k]).max() <= 1e-13 * max(lam, 1.0) * np.abs(psi[k]).max(), m
+
+
+@pytest.mark.parametrize("given", [False, True], ids=["vx", "given-hpsi"])
+@pytest.mark.parametrize("vx_prec,tol", [("fp64", 1e-10), ("fp32acc64", 1e-5)])
+def test_residual_with_kinetic(ctx, given, vx_prec, tol):
+    """H = (V_X or a given H) + T: the library adds -(1/2) Laplacian psi to H Psi."""
+    n3, L3, N = (24, 24, 24), (10.26,) * 3, 7
+    psi = synth.make_orbitals(87, n3, L3, N)
+    half = _block(88, n3, N)
+    dt = 0.3
+    tpsi = oracle.apply_kinetic(psi, n3, L3)
+    if given:
+        h = _block(89, n3, N)
+        ref = oracle.pt_residual(psi, h + tpsi, half, dt)
+        R = ctx.pt_residual(dev(psi), dev(half), n=n3, L=L3, hpsi=dev(h), dt=dt, kinetic=True)
+        tol = 1e-10
+    else:
+        w = oracle.apply_vx(psi, psi, n3, L3, "hse", 0.106)
+        ref = oracle.pt_residual(psi, w + tpsi, half, dt)
+        R = ctx.pt_residual(dev(psi), dev(half), n=n3, L=L3, dt=dt, kernel="hse", vx_prec=vx_prec, kinetic=True)
+    err = col_err(host(R), ref)
+    say("residual with kinetic", "given" if given else "V_X", vx_prec, err)
+    assert err <= tol
+
+
+def test_residual_planewave_eigenbasis_kinetic(ctx):
+    """Planewaves are eigenvectors of V_X + T: the residual is Psi - Psi_half."""
+    n3, L3 = (6, 6, 6), (5.0, 5.0, 5.0)
+    psi = synth.planewave_orbitals(n3, L3, [(0, 0, 0), (1, 0, 0), (0, -1, 2), (3, 1, -1)])
+    half = _block(90, n3, 4)
+    R = host(ctx.pt_residual(dev(psi), dev(half), n=n3, L=L3, dt=0.9, kernel="hse", omega=0.3, vx_prec="fp64",
+                             kinetic=True))
+    assert np.abs(R - (psi - half)).max() <= 1e-13 * np.abs(psi - half).max()
+
+
+def test_internal_kernel_kind_is_rejected(ctx):
+    """The library's own kinetic kernel kind is not accepted by the public V_X call."""
+    import torch
+
+    n3, L3 = (8, 8, 8), (4.0,) * 3
+    P = dev(_block(96, n3, 2))
+    with pytest.raises(F.FockError) as ei:
+        ctx.apply_vx(P, n=n3, L=L3, kernel=100, prec="fp64")
+    assert ei.value.status == F.FX_ERR_UNSUPPORTED
+    torch.cuda.synchronize()
 
 
 def test_residual_planewave_eigenbasis(ctx):
