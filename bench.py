@@ -478,15 +478,19 @@ def bench_step(args):
         blocks.append(torch.randn((N, n, n, n), dtype=torch.complex64, device="cuda:0", generator=g) / math.sqrt(nr))
     P, H, Hf = blocks
     R = torch.empty_like(P)
+    TP = torch.empty_like(P)
     rho = torch.empty((n, n, n), dtype=torch.float64, device="cuda:0")
     ctx = Context(0)
     ops = {
+        "kinetic": lambda: ctx.apply_kinetic(P, n=n, L=L, out=TP),
         "pt_residual": lambda: ctx.pt_residual(P, Hf, n=n, L=L, hpsi=H, dt=0.05, out=R),
         "orthonormalize": lambda: ctx.orthonormalize(P),
         "density": lambda: ctx.density(P, out=rho),
     }
-    flops = {"pt_residual": 16.0 * nr * N * N, "orthonormalize": 16.0 * nr * N * N, "density": 0.0}
-    nbytes = {"density": 8.0 * nr * N + 8.0 * nr}
+    flops = {"kinetic": 0.0, "pt_residual": 16.0 * nr * N * N, "orthonormalize": 16.0 * nr * N * N, "density": 0.0}
+    # kinetic: the FP64 pair path with one constant orbital, 96 B per point per orbital (plane, pencil and
+    # plane passes over a 16-byte pair volume, the orbital read and the result written once)
+    nbytes = {"kinetic": 96.0 * nr * N, "density": 8.0 * nr * N + 8.0 * nr}
     res = {}
     for name, fn in ops.items():
         fn()
@@ -498,10 +502,14 @@ def bench_step(args):
         torch.cuda.synchronize()
         el = (time.perf_counter() - t0) / args.steps
         kern = {}
-        for kname in ("gemm_cn", "gemm_nn", "reduce", "linalg", "convert"):
+        for kname in ("gemm_cn", "gemm_nn", "reduce", "linalg", "convert", "vx_plane_fwd", "vx_pencil_z",
+                      "vx_plane_inv"):
             cnt, ms, work = ctx.prof_read(fock.KERNEL_IDS[kname])
             if cnt:
-                kern[kname] = {"launches": cnt, "avg_ms": ms / cnt, "rate_TFLOPs": work / (ms * 1e-3) / 1e12}
+                # work: flops of the GEMM and factorisation kernels, model bytes of the others
+                rate = ("rate_TFLOPs", work / (ms * 1e-3) / 1e12) if kname in ("gemm_cn", "gemm_nn", "linalg") \
+                    else ("model_GBps", work / (ms * 1e-3) / 1e9)
+                kern[kname] = {"launches": cnt, "avg_ms": ms / cnt, rate[0]: rate[1]}
         ctx.prof_enable(False)
         e = {"ms": 1e3 * el, "kernels": kern}
         if flops[name]:
@@ -519,8 +527,8 @@ def bench_step(args):
         "metric": "end-of-step operations, ms per step", "value": total, "unit": "ms", "n_gpus": 1,
         "steps": args.steps, "warmup": 1, "ms_per_step": total, "higher_is_better": False, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"PT residual + Cholesky-QR + density, {n}^3 grid, N = {N}, complex64 blocks, "
-                               "FP64 arithmetic"},
+        "config": {"workload": f"kinetic operator + PT residual + Cholesky-QR + density, {n}^3 grid, N = {N}, "
+                               "complex64 blocks, FP64 arithmetic"},
         "ops": res,
     }
     ctx.close()
