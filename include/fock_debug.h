@@ -1,6 +1,7 @@
 /*
  * libfock debug extension: host execution of the device pass code, for
- * checking FFT plans, digit-reversed spectra and kernel tables without a GPU.
+ * checking FFT plans, digit-reversed spectra and kernel tables without a GPU;
+ * and forced allocation failures, for tests of the error paths.
  */
 #ifndef LIBFOCK_FOCK_DEBUG_H
 #define LIBFOCK_FOCK_DEBUG_H
@@ -32,6 +33,14 @@ fx_status fx_debug_host_pair_plan(const fx_cell* cell, const fx_kernel* kernel, 
  * max_plans rows of 4 int32 written to radix_out (0-terminated), their
  * number to *count.  Errors: FX_ERR_INVALID, FX_ERR_UNSUPPORTED. */
 fx_status fx_debug_axis_plans(int32_t n, int32_t max_plans, int32_t* radix_out, int32_t* count);
+
+/* Make the k-th device allocation of the library after this call (k >= 1,
+ * counted over all contexts of the process) fail once with FX_ERR_OOM, as if
+ * the HBM budget were exhausted; k = 0 cancels a pending failure.  A call that
+ * meets the failure returns FX_ERR_OOM and leaves its context usable.  The
+ * environment variable FX_FAULT_INJECT=k does the same for the k-th
+ * allocation of the process.  Errors: FX_ERR_INVALID (k < 0). */
+fx_status fx_debug_fail_alloc(int64_t k);
 
 #ifdef __cplusplus
 }

@@ -41,8 +41,10 @@ bool TableKey::operator<(const TableKey& o) const {
 }
 
 // Optional fault injection for error-path tests: FX_FAULT_INJECT=<k> makes the
-// k-th allocation of the process (1-based) fail with FX_ERR_OOM.
+// k-th allocation of the process (1-based) fail with FX_ERR_OOM, and
+// fx_debug_fail_alloc(k) the k-th allocation after that call (once).
 static long g_alloc_count = 0;
+static long g_fail_at = 0;  // allocation count that fails (0: none)
 
 fx_status ctx_alloc(fx_ctx* ctx, size_t bytes, void** out) {
   *out = nullptr;
@@ -50,6 +52,9 @@ fx_status ctx_alloc(fx_ctx* ctx, size_t bytes, void** out) {
   const char* fi = getenv("FX_FAULT_INJECT");
   long n = __atomic_add_fetch(&g_alloc_count, 1, __ATOMIC_SEQ_CST);
   if (fi && atol(fi) == n) FX_FAIL(FX_ERR_OOM, "injected allocation failure (FX_FAULT_INJECT=%s)", fi);
+  long at = n;
+  if (__atomic_compare_exchange_n(&g_fail_at, &at, 0L, false, __ATOMIC_SEQ_CST, __ATOMIC_SEQ_CST))
+    FX_FAIL(FX_ERR_OOM, "injected allocation failure (allocation %ld)", n);
   if (ctx->capturing)
     FX_FAIL(FX_ERR_INVALID,
             "%zu bytes must be allocated while the stream is being captured; run the same call once outside "
@@ -444,6 +449,14 @@ using namespace fx;
 extern "C" {
 
 const char* fx_last_error(void) { return g_err; }
+
+fx_status fx_debug_fail_alloc(int64_t k) {
+  clear_error();
+  if (k < 0) FX_FAIL(FX_ERR_INVALID, "k = %lld must be >= 0", (long long)k);
+  const long base = __atomic_load_n(&g_alloc_count, __ATOMIC_SEQ_CST);
+  __atomic_store_n(&g_fail_at, k ? base + (long)k : 0L, __ATOMIC_SEQ_CST);
+  return FX_OK;
+}
 
 const char* fx_version(void) { return "libfock 0.1 (gfx950)"; }
 

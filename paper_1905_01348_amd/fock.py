@@ -119,6 +119,7 @@ _SIGS = {
     "fx_debug_host_pair_plan": (C.c_int, [C.POINTER(FxCell), C.POINTER(FxKernel), C.c_int, C.c_void_p, C.c_void_p,
                                            C.c_void_p, C.c_void_p]),
     "fx_debug_axis_plans": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.POINTER(C.c_int32)]),
+    "fx_debug_fail_alloc": (C.c_int, [C.c_int64]),
     "fx_apply_kinetic": (C.c_int, [C.c_void_p, C.POINTER(FxCell), C.c_void_p, C.c_int32, C.c_int64, C.c_void_p,
                                    C.c_int64, C.c_int, C.c_int, C.c_void_p]),
     "fx_pt_residual": (C.c_int, [C.c_void_p, C.POINTER(FxCell), C.POINTER(FxKernel), C.c_void_p, C.c_void_p,
@@ -522,6 +523,11 @@ def debug_host_pair(psi_j, phi_k, *, n, L, kernel="hse", omega=0.106, scale=1.0,
         _check(load().fx_debug_host_pair_plan(C.byref(cell), C.byref(kern), int(prec), r.ctypes.data, a.ctypes.data,
                                               b.ctypes.data, v.ctypes.data))
     return v
+
+
+def debug_fail_alloc(k):
+    """Make the k-th device allocation of the library from now fail once with FX_ERR_OOM (0 cancels)."""
+    _check(load().fx_debug_fail_alloc(int(k)))
 
 
 def debug_axis_plans(n, max_plans=6):
