@@ -1,5 +1,5 @@
 // fx_serve: continuous batching of V_X and K_ACE requests over orbitals kept
-// resident on the device.
+// resident on the device (the host scheduling is in serve_sched.hpp).
 //
 // One host loop replays the arrivals.  Waiting requests of the same
 // trajectory and operation are merged into one launch (their target orbitals
@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "ace.hpp"
+#include "serve_sched.hpp"
 #include "vx.hpp"
 
 using namespace fx;
@@ -41,9 +42,6 @@ struct Slot {
   hipStream_t st = nullptr;
   hipEvent_t done = nullptr;
   Workspace ws;
-  bool busy = false;
-  std::vector<int> reqs;
-  double t_launch = 0;
 };
 
 // gather columns [first, first+count) of each request's trajectory into a
@@ -90,16 +88,6 @@ static double now_s() {
   return duration<double>(steady_clock::now().time_since_epoch()).count();
 }
 
-static double percentile(std::vector<double> v, double q) {
-  if (v.empty()) return 0.0;
-  std::sort(v.begin(), v.end());
-  // nearest-rank
-  size_t k = (size_t)std::ceil(q * v.size());
-  if (k < 1) k = 1;
-  if (k > v.size()) k = v.size();
-  return v[k - 1];
-}
-
 // Device resources of a server: resident orbitals and ACE factors of its
 // trajectories, slot workspaces, events and streams; the context budget it
 // capped is restored.  The device has been synchronised by the caller.
@@ -137,6 +125,110 @@ void serve_detach_all(fx_ctx* ctx) {
   ctx->servers.clear();
 }
 }  // namespace fx
+
+// The device side of the serving loop: slot streams, events and workspaces.
+namespace {
+struct HipExec final : ServeExecutor {
+  fx_server* srv;
+  fx_ctx* ctx;
+  const fx_request* reqs;
+  std::vector<int> stream_id;
+  HipExec(fx_server* s, const fx_request* r) : srv(s), ctx(s->ctx), reqs(r) {
+    const int ns = (int)srv->slots.size();
+    stream_id.resize(ns);
+    for (int i = 0; i < ns; ++i) {
+      stream_id[i] = i;
+      for (int j = 0; j < i; ++j)
+        if (srv->slots[j].st == srv->slots[i].st) {
+          stream_id[i] = stream_id[j];
+          break;
+        }
+    }
+  }
+  int n_slots() const override { return (int)srv->slots.size(); }
+  int stream_of(int slot) const override { return stream_id[slot]; }
+  int orbitals(int traj) const override { return srv->trajs.at(traj).n; }
+  fx_status launch(int slot, const std::vector<int>& batch) override {
+    Slot& sl = srv->slots[slot];
+    const fx_request& r0 = reqs[batch[0]];
+    Traj& t = srv->trajs[r0.traj];
+    const size_t esz = dtype_size(t.dtype);
+    const int64_t cb = (int64_t)esz * t.nr;
+    int total = 0;
+    for (int i : batch) total += reqs[i].count;
+    const void* phi = nullptr;
+    void* out = nullptr;
+    const bool single = batch.size() == 1;
+    if (single) {
+      phi = (const char*)t.psi + (int64_t)r0.first * cb;
+      out = r0.out;
+    } else {
+      void *g = nullptr, *o = nullptr;
+      FX_TRY(ws_get(ctx, &sl.ws, "srv_gather", (size_t)cb * total, &g));
+      FX_TRY(ws_get(ctx, &sl.ws, "srv_out", (size_t)cb * total, &o));
+      int off = 0;
+      for (int i : batch) {
+        FX_TRY(copy_cols((const char*)t.psi + (int64_t)reqs[i].first * cb, cb, (char*)g + (int64_t)off * cb, cb, cb,
+                         reqs[i].count, sl.st));
+        off += reqs[i].count;
+      }
+      phi = g;
+      out = o;
+    }
+    const int64_t ld_out = single ? r0.ld_out : t.nr;
+    if (r0.op == 0) {
+      VxArgs va;
+      va.cell = &t.cell;
+      va.kern = &t.kern;
+      va.psi = t.psi;
+      va.n_psi = t.n;
+      va.ld_psi = t.nr;
+      va.phi = phi;
+      va.n_phi = total;
+      va.ld_phi = t.nr;
+      va.out = out;
+      va.ld_out = ld_out;
+      va.in_dtype = t.dtype;
+      va.out_dtype = t.dtype;
+      va.prec = t.vx_prec;
+      va.work_cap = (size_t)(srv->cfg.vx_work_mb > 0 ? srv->cfg.vx_work_mb : 1024) << 20;
+      FX_TRY(vx_apply(ctx, &sl.ws, va, sl.st, nullptr));
+    } else {
+      FX_TRY(ace_apply_impl(ctx, &sl.ws, t.ace, phi, total, t.nr, out, ld_out, t.dtype, t.dtype, t.ace_prec, sl.st));
+    }
+    if (!single) {
+      int off = 0;
+      for (int i : batch) {
+        FX_TRY(copy_cols((char*)out + (int64_t)off * cb, cb, reqs[i].out, reqs[i].ld_out * (int64_t)esz, cb,
+                         reqs[i].count, sl.st));
+        off += reqs[i].count;
+      }
+    }
+    FX_HIP(hipEventRecord(sl.done, sl.st));
+    return FX_OK;
+  }
+  bool release_idle(const std::vector<char>& idle) override {
+    for (size_t i = 0; i < srv->slots.size(); ++i) {
+      if (!idle[i]) continue;
+      // a failed launch may have queued copies on this slot's stream
+      if (hipStreamSynchronize(srv->slots[i].st) != hipSuccess) return false;
+      ws_release(ctx, &srv->slots[i].ws);
+    }
+    clear_error();
+    return true;
+  }
+  int poll(int slot) override {
+    const hipError_t q = hipEventQuery(srv->slots[slot].done);
+    if (q == hipSuccess) return 1;
+    if (q == hipErrorNotReady) return 0;
+    set_error("device error while serving: %s", hipGetErrorString(q));
+    return -1;
+  }
+  double now() override { return now_s(); }
+  void idle_wait(double seconds) override { std::this_thread::sleep_for(std::chrono::duration<double>(seconds)); }
+  size_t mem_in_use() const override { return ctx->in_use; }
+};
+}  // namespace
 
 extern "C" {
 
@@ -247,223 +339,31 @@ fx_status fx_serve(fx_server* srv, const fx_request* reqs, int32_t n_reqs, fx_st
   ctx->capturing = false;  // the serving loop runs on its own, uncaptured streams
   FX_HIP(hipSetDevice(ctx->device));
   const int nq = n_reqs;
-  std::vector<fx_status> status(nq, FX_ERR_CANCELLED);
-  std::vector<double> lat(nq, -1.0), t_done(nq, 0.0);
-  std::vector<int> order(nq);
-  for (int i = 0; i < nq; ++i) order[i] = i;
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int a, int b) { return reqs[a].t_arrival_s < reqs[b].t_arrival_s; });
-  // validation
   std::vector<char> valid(nq, 1);
   for (int i = 0; i < nq; ++i) {
     const fx_request& r = reqs[i];
     auto it = srv->trajs.find(r.traj);
     if (it == srv->trajs.end() || (r.op != 0 && r.op != 1) || r.count <= 0 || r.first < 0 ||
-        r.first + r.count > it->second.n || !r.out || r.ld_out < it->second.nr) {
+        r.first + r.count > it->second.n || !r.out || r.ld_out < it->second.nr)
       valid[i] = 0;
-      status[i] = FX_ERR_INVALID;
-    }
   }
-  std::deque<int> waiting;
-  size_t next = 0;
-  int64_t done_count = 0, rejected = 0, batches = 0;
-  double pairs_done = 0.0, busy_time = 0.0, busy_since = -1.0;
-  int nbusy = 0;
-  const double t0 = now_s();
-  size_t hbm_peak = ctx->in_use;
-  fx_status fatal = FX_OK;
-
-  auto finish_slot = [&](Slot& sl, double t) {
-    for (int i : sl.reqs) {
-      t_done[i] = t;
-      lat[i] = 1e3 * (t - (t0 + reqs[i].t_arrival_s));
-      status[i] = FX_OK;
-      ++done_count;
-    }
-    sl.reqs.clear();
-    sl.busy = false;
-    if (--nbusy == 0 && busy_since >= 0) {
-      busy_time += t - busy_since;
-      busy_since = -1.0;
-    }
-  };
-
-  // launch one merged batch on slot `sl`; returns FX_ERR_OOM if its workspace
-  // does not fit right now
-  auto launch = [&](Slot& sl, const std::vector<int>& batch) -> fx_status {
-    const fx_request& r0 = reqs[batch[0]];
-    Traj& t = srv->trajs[r0.traj];
-    const size_t esz = dtype_size(t.dtype);
-    const int64_t cb = (int64_t)esz * t.nr;
-    int total = 0;
-    for (int i : batch) total += reqs[i].count;
-    const void* phi = nullptr;
-    void* out = nullptr;
-    const bool single = batch.size() == 1;
-    if (single) {
-      phi = (const char*)t.psi + (int64_t)r0.first * cb;
-      out = r0.out;
-    } else {
-      void *g = nullptr, *o = nullptr;
-      FX_TRY(ws_get(ctx, &sl.ws, "srv_gather", (size_t)cb * total, &g));
-      FX_TRY(ws_get(ctx, &sl.ws, "srv_out", (size_t)cb * total, &o));
-      int off = 0;
-      for (int i : batch) {
-        FX_TRY(copy_cols((const char*)t.psi + (int64_t)reqs[i].first * cb, cb, (char*)g + (int64_t)off * cb, cb, cb,
-                         reqs[i].count, sl.st));
-        off += reqs[i].count;
-      }
-      phi = g;
-      out = o;
-    }
-    const int64_t ld_out = single ? r0.ld_out : t.nr;
-    if (r0.op == 0) {
-      VxArgs va;
-      va.cell = &t.cell;
-      va.kern = &t.kern;
-      va.psi = t.psi;
-      va.n_psi = t.n;
-      va.ld_psi = t.nr;
-      va.phi = phi;
-      va.n_phi = total;
-      va.ld_phi = t.nr;
-      va.out = out;
-      va.ld_out = ld_out;
-      va.in_dtype = t.dtype;
-      va.out_dtype = t.dtype;
-      va.prec = t.vx_prec;
-      va.work_cap = (size_t)(srv->cfg.vx_work_mb > 0 ? srv->cfg.vx_work_mb : 1024) << 20;
-      FX_TRY(vx_apply(ctx, &sl.ws, va, sl.st, nullptr));
-      pairs_done += (double)t.n * total;
-    } else {
-      FX_TRY(ace_apply_impl(ctx, &sl.ws, t.ace, phi, total, t.nr, out, ld_out, t.dtype, t.dtype, t.ace_prec, sl.st));
-      pairs_done += (double)t.n * total;
-    }
-    if (!single) {
-      int off = 0;
-      for (int i : batch) {
-        FX_TRY(copy_cols((char*)out + (int64_t)off * cb, cb, reqs[i].out, reqs[i].ld_out * (int64_t)esz, cb,
-                         reqs[i].count, sl.st));
-        off += reqs[i].count;
-      }
-    }
-    FX_HIP(hipEventRecord(sl.done, sl.st));
-    return FX_OK;
-  };
-
-  while (done_count + rejected < (int64_t)std::count(valid.begin(), valid.end(), 1) || !waiting.empty() || nbusy) {
-    const double t = now_s() - t0;
-    // arrivals
-    while (next < (size_t)nq && reqs[order[next]].t_arrival_s <= t) {
-      if (valid[order[next]]) waiting.push_back(order[next]);
-      ++next;
-    }
-    // completions
-    for (auto& sl : srv->slots) {
-      if (!sl.busy) continue;
-      hipError_t q = hipEventQuery(sl.done);
-      if (q == hipSuccess) {
-        finish_slot(sl, now_s());
-      } else if (q != hipErrorNotReady) {
-        set_error("device error while serving: %s", hipGetErrorString(q));
-        fatal = FX_ERR_DEVICE;
-        break;
-      }
-    }
-    if (fatal != FX_OK) break;
-    // dispatch, only onto streams with nothing running: a batch queued on a
-    // busy stream would wait behind all of that stream's batch (a 72^3 V_X
-    // block is ~15 ms), while waiting in the host queue it takes the first
-    // stream to come free
-    bool progressed = false;
-    for (auto& sl : srv->slots) {
-      if (sl.busy || waiting.empty()) continue;
-      bool stream_busy = false;
-      for (const auto& other : srv->slots)
-        if (other.busy && other.st == sl.st) stream_busy = true;
-      if (stream_busy) continue;
-      // merge: oldest request first, then same trajectory and op in arrival order
-      const int head = waiting.front();
-      const fx_request& rh = reqs[head];
-      const Traj& th = srv->trajs[rh.traj];
-      std::vector<int> batch{head};
-      int64_t pairs = (int64_t)th.n * rh.count;
-      for (size_t w = 1; w < waiting.size(); ++w) {
-        const fx_request& rw = reqs[waiting[w]];
-        if (rw.traj != rh.traj || rw.op != rh.op) continue;
-        const int64_t p = (int64_t)th.n * rw.count;
-        if (pairs + p > srv->cfg.max_batch_pairs) break;
-        batch.push_back(waiting[w]);
-        pairs += p;
-      }
-      fx_status s = launch(sl, batch);
-      if (s == FX_ERR_OOM) {
-        // idle slots keep the workspaces of their last batch: hand them back
-        // (their streams have finished) and try once more
-        for (auto& other : srv->slots) {
-          if (other.busy) continue;
-          // the failed attempt may have queued copies on this slot's stream
-          if (hipStreamSynchronize(other.st) != hipSuccess) {
-            fatal = FX_ERR_DEVICE;
-            break;
-          }
-          ws_release(ctx, &other.ws);
-        }
-        if (fatal != FX_OK) break;
-        clear_error();
-        s = launch(sl, batch);
-      }
-      if (s == FX_ERR_OOM) {
-        if (nbusy > 0) break;  // wait for memory to drain
-        for (int i : batch) {
-          status[i] = FX_ERR_OOM;
-          ++rejected;
-        }
-      } else if (s != FX_OK) {
-        fatal = s;
-        break;
-      } else {
-        sl.busy = true;
-        sl.reqs = batch;
-        if (nbusy++ == 0) busy_since = now_s();
-        ++batches;
-        progressed = true;
-      }
-      // drop the batch from the waiting queue
-      std::deque<int> rest;
-      for (int w : waiting)
-        if (std::find(batch.begin(), batch.end(), w) == batch.end()) rest.push_back(w);
-      waiting.swap(rest);
-      hbm_peak = std::max(hbm_peak, ctx->in_use);
-    }
-    if (fatal != FX_OK) break;
-    if (!progressed) {
-      // nothing to launch: sleep until the next arrival or a short poll interval
-      double wait = 2e-4;
-      if (next < (size_t)nq && waiting.empty() && nbusy == 0) wait = std::max(0.0, reqs[order[next]].t_arrival_s - t);
-      std::this_thread::sleep_for(std::chrono::duration<double>(std::min(wait, 5e-5)));
-    }
-    if (next >= (size_t)nq && waiting.empty() && nbusy == 0) break;
-  }
-  if (fatal != FX_OK) {
+  HipExec ex(srv, reqs);
+  ServeOutcome o;
+  serve_schedule(ex, reqs, nq, valid, srv->cfg.max_batch_pairs, &o);
+  if (o.fatal != FX_OK) {
     (void)hipDeviceSynchronize();
-    for (auto& sl : srv->slots) {
-      sl.busy = false;
-      sl.reqs.clear();
-    }
-    return fatal;
+    return o.fatal;
   }
-  const double wall = now_s() - t0;
   std::vector<double> ok;
   for (int i = 0; i < nq; ++i) {
-    if (per_status) per_status[i] = status[i];
-    if (per_lat_ms) per_lat_ms[i] = lat[i];
-    if (status[i] == FX_OK) ok.push_back(lat[i]);
+    if (per_status) per_status[i] = o.status[i];
+    if (per_lat_ms) per_lat_ms[i] = o.lat_ms[i];
+    if (o.status[i] == FX_OK) ok.push_back(o.lat_ms[i]);
   }
   if (report) {
     fx_serve_report& R = *report;
-    R.p50_ms = percentile(ok, 0.50);
-    R.p99_ms = percentile(ok, 0.99);
+    R.p50_ms = serve_percentile(ok, 0.50);
+    R.p99_ms = serve_percentile(ok, 0.99);
     double sum = 0, mx = 0;
     for (double v : ok) {
       sum += v;
@@ -471,14 +371,14 @@ fx_status fx_serve(fx_server* srv, const fx_request* reqs, int32_t n_reqs, fx_st
     }
     R.mean_ms = ok.empty() ? 0.0 : sum / ok.size();
     R.max_ms = mx;
-    R.wall_s = wall;
-    R.req_per_s = wall > 0 ? ok.size() / wall : 0.0;
-    R.pairs_per_s = wall > 0 ? pairs_done / wall : 0.0;
-    R.busy_frac = wall > 0 ? busy_time / wall : 0.0;
+    R.wall_s = o.wall;
+    R.req_per_s = o.wall > 0 ? ok.size() / o.wall : 0.0;
+    R.pairs_per_s = o.wall > 0 ? o.pairs_done / o.wall : 0.0;
+    R.busy_frac = o.wall > 0 ? o.busy_time / o.wall : 0.0;
     R.n_done = (int64_t)ok.size();
-    R.n_rejected = rejected;
-    R.n_batches = batches;
-    R.hbm_peak_bytes = hbm_peak;
+    R.n_rejected = o.rejected;
+    R.n_batches = o.batches;
+    R.hbm_peak_bytes = o.hbm_peak;
   }
   return FX_OK;
 }
