@@ -114,6 +114,8 @@ def main():
                     help="vx: V_X apply (default); ace: ACE build + apply at 96^3, N = R = 1024; serve: serving replay")
     ap.add_argument("--requests", type=int, default=12000, help="serve leg: measured requests")
     ap.add_argument("--warm-requests", type=int, default=1000, help="serve leg: warm-up requests")
+    ap.add_argument("--serve-work-mb", type=int, default=0,
+                    help="serve leg: pair work volume per V_X launch, MiB (0: the library's default)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -547,7 +549,7 @@ def bench_serve(args):
     classes = {0: "serveA", 1: "serveB", 2: "serveC"}
     ctx = Context(0)
     srv = Server(ctx, max_slots=8, n_streams=4, max_batch_pairs=1 << 15, hbm_budget_bytes=64 << 30,
-                 autotune=args.autotune)
+                 autotune=args.autotune, vx_work_mb=args.serve_work_mb)
     by_class = {}
     t0 = time.perf_counter()
     for c, name in classes.items():
@@ -598,7 +600,7 @@ def bench_serve(args):
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": "Poisson 200 req/s; 50/35/15% classes 24^3 N=16, 48^3 N=128, 72^3 N=432; "
                                "V_X or ACE on blocks of 8 orbitals; complex64; HSE",
-                   "register_s": t_reg},
+                   "register_s": t_reg, "vx_work_mb": args.serve_work_mb or "library default"},
         "report": rep, "ok": ok, "offered_load": rep["busy_frac"], "by_class": breakdown,
     }
     srv.close()
