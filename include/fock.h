@@ -181,13 +181,13 @@ typedef struct fx_vx_config {
                           3 whole x rows, 4 a persistent kernel (one y per workgroup,
                           the next tile's loads issued ahead) with whole x rows where
                           they fit the LDS (else the default tile); 0 automatic (4 at
-                          edge 96, else 1) */
+                          edge 96, 3 at 72, else 1) */
   int32_t c_variant;   /* specialised plane-inverse pass: 1 the edge's default threads,
                           2 a larger count (fewer accumulators per thread, more waves),
                           3 and 4: 2 and 1 with the next work plane copied into LDS
                           while the current one is transformed (where two planes fit
                           the LDS: not FP64 at 72 and 96, which run 2 and 1 instead);
-                          0 automatic (2 at edge 96, else 1) */
+                          0 automatic (2 at edges 96 and 72, else 1) */
   int32_t a_variant;   /* specialised plane-forward pass threads: 1 the edge's default,
                           2 a count that divides the butterflies evenly; 0 automatic (1) */
   int32_t nt_hint;     /* specialised kernels: 1 read and write the pair volume with

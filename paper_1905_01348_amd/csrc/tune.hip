@@ -189,8 +189,8 @@ static fx_status autotune(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* ker
   const bool spec = ct_supported(cell);
   cur.kernels = spec ? 1 : 2;
   cur.a_prefetch = 0;
-  cur.b_variant = spec ? (cell->n[0] == 96 ? 4 : 1) : 0;
-  cur.c_variant = spec ? (cell->n[0] == 96 ? 2 : 1) : 0;
+  cur.b_variant = spec ? (cell->n[0] == 96 ? 4 : (cell->n[0] == 72 ? 3 : 1)) : 0;
+  cur.c_variant = spec ? (cell->n[0] == 96 || cell->n[0] == 72 ? 2 : 1) : 0;
   cur.a_variant = spec ? 1 : 0;
   cur.nt_hint = spec ? 1 : 0;
   rs = trial(cur);

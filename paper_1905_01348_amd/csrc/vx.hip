@@ -365,19 +365,21 @@ static bool pick_ept(int elems, int max_thr, int* ept, int* nthr) {
 
 // z-pass form of the specialised kernels: the persistent kernel with whole x
 // rows is the automatic choice at 96^3, where it measured faster (3.12 vs
-// 3.38 ms per launch of 1170 pairs); elsewhere the autotuner decides.
+// 3.38 ms per launch of 1170 pairs), whole x rows at 72^3 (15.6 vs 16.6 ms
+// for 432 orbitals x 8 targets); elsewhere the autotuner decides.
 static int ct_b_variant(const VxArgs& a) {
   if (a.b_var >= 1 && a.b_var <= 4) return a.b_var;
-  return a.cell->n[0] == 96 ? 4 : 1;
+  return a.cell->n[0] == 96 ? 4 : (a.cell->n[0] == 72 ? 3 : 1);
 }
 
 // Plane-inverse threads of the specialised kernels: the larger count (fewer
-// accumulators per thread, 12 waves per CU instead of 8) is the automatic
-// choice at 96^3, where it measured faster (3.34 vs 3.39 ms per launch of
-// 1170 pairs); elsewhere the autotuner decides.
+// accumulators per thread, more waves per CU) is the automatic choice at
+// 96^3, where it measured faster (3.34 vs 3.39 ms per launch of 1170 pairs),
+// and at 72^3 (15.1 vs 15.6 ms for 432 orbitals x 8 targets, with whole-row
+// z tiles); elsewhere the autotuner decides.
 static int ct_c_variant(const VxArgs& a) {
   if (a.c_var >= 1 && a.c_var <= 4) return a.c_var;
-  return a.cell->n[0] == 96 ? 2 : 1;
+  return a.cell->n[0] == 96 || a.cell->n[0] == 72 ? 2 : 1;
 }
 
 // How the XCDs share the items of the persistent plane passes (bit 0: the
