@@ -1,4 +1,4 @@
-"""HIP graph capture of fx_apply_vx and fx_apply_ace.
+"""HIP graph capture of fx_apply_vx, fx_apply_kinetic and fx_apply_ace.
 
 After one uncaptured call of the same shape (workspace and grid tables in
 place), the call is captured into a graph on a side stream; every replay
@@ -57,6 +57,36 @@ def test_apply_vx_graph_replays_match_eager(ctx, prec):
         assert np.array_equal(_bits(got), _bits(ref)), f"replay {rep}"
         # eager work of the same shape between replays
         ctx.apply_vx(psi, phi, n=n, L=L, prec=prec, out=out_e)
+        torch.cuda.synchronize()
+        assert np.array_equal(_bits(host(out_e)), _bits(ref))
+    del g
+
+
+def test_apply_kinetic_graph_replays_match_eager(ctx):
+    """The kinetic operator (the pair path with the constant orbital, filled by a kernel on every
+    call) captured once and replayed: each replay equals the eager result bitwise."""
+    import torch
+
+    n3, L3 = (24, 18, 16), (10.0, 8.0, 7.0)
+    phi = dev(synth.random_grid_vectors(5, n3, 4))
+    s = torch.cuda.Stream()
+    out_e = torch.empty_like(phi)
+    out_g = torch.empty_like(phi)
+    with torch.cuda.stream(s):
+        ctx.apply_kinetic(phi, n=n3, L=L3, out=out_e)
+    torch.cuda.synchronize()
+    ref = host(out_e)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        ctx.apply_kinetic(phi, n=n3, L=L3, out=out_g)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        out_g.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(_bits(host(out_g)), _bits(ref)), f"replay {rep}"
+        ctx.apply_kinetic(phi, n=n3, L=L3, out=out_e)
         torch.cuda.synchronize()
         assert np.array_equal(_bits(host(out_e)), _bits(ref))
     del g
