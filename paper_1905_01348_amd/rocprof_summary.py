@@ -17,6 +17,10 @@
     python -m paper_1905_01348_amd.rocprof_summary table <dir> [<dir> ...] --kernels a,b,c
         -> a Markdown table of the mean of every counter per dispatch for each kernel.
 
+    python -m paper_1905_01348_amd.rocprof_summary mfma <dir> [--kernel k_tn_mfma]
+        -> executed MFMA TFLOP/s, fraction of the dense peak and matrix-core busy
+           fraction of each matrix-core kernel instantiation.
+
 Input directories are rocprofv3 -d output folders written with
 --output-format csv (the counter runs produce *counter_collection.csv).
 """
@@ -170,6 +174,50 @@ def counter_table(dirs, kernels, title=None, command=None):
     return "\n".join(out) + "\n"
 
 
+MFMA_PEAK_TFLOPS = {"F32": 157.3, "BF16": 2500.0, "F16": 2500.0, "F64": 78.6}
+
+
+def mfma_table(d, kernel_substr, title=None, command=None, xcds=8, simds=1024):
+    """Markdown table for the matrix-core kernels of one rocprofv3 --pmc folder with
+    SQ_INSTS_VALU_MFMA_MOPS_* (MFMA flops = MOPS x 512), SQ_VALU_MFMA_BUSY_CYCLES and
+    GRBM_GUI_ACTIVE: per kernel instantiation, the mean dispatch duration, the executed MFMA
+    TFLOP/s and its fraction of the published dense peak of the operand type, and the matrix
+    cores' busy fraction BUSY / (GUI_ACTIVE / xcds x simds).  GRBM_GUI_ACTIVE is reported
+    summed over the XCDs; the clock column (GUI_ACTIVE / xcds / duration) checks that."""
+    path = _find(d, "*counter_collection.csv")
+    per = {}
+    for r in csv.DictReader(open(path)):
+        name = r.get("Kernel_Name", "")
+        if kernel_substr not in name:
+            continue
+        disp = r.get("Dispatch_Id", "")
+        e = per.setdefault(name, {}).setdefault(disp, {})
+        e[r.get("Counter_Name", "")] = float(r.get("Counter_Value", 0))
+        e["_ns"] = float(r["End_Timestamp"]) - float(r["Start_Timestamp"])
+    out = []
+    if title:
+        out.append(f"# {title}\n")
+    if command:
+        out.append(f"Command:\n\n```\n{command}\n```\n")
+    out.append("| kernel | dispatches | mean ms | MFMA TFLOP/s | operand type | of dense peak | MFMA busy | clock GHz |")
+    out.append("|---|---|---|---|---|---|---|---|")
+    for name, byd in per.items():
+        n = len(byd)
+        ms = sum(e["_ns"] for e in byd.values()) / n / 1e6
+        mops = {t: sum(e.get(f"SQ_INSTS_VALU_MFMA_MOPS_{t}", 0.0) for e in byd.values()) / n for t in MFMA_PEAK_TFLOPS}
+        t_main = max(mops, key=mops.get)
+        flops = 512.0 * sum(mops.values())
+        tf = flops / (ms * 1e-3) / 1e12 if ms > 0 else 0.0
+        gui = sum(e.get("GRBM_GUI_ACTIVE", 0.0) for e in byd.values()) / n
+        busy = sum(e.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0) for e in byd.values()) / n
+        util = busy / (gui / xcds * simds) if gui > 0 else float("nan")
+        ghz = gui / xcds / (ms * 1e-3) / 1e9 if ms > 0 else float("nan")
+        short = name.split("(")[0].replace("void ", "")
+        out.append(f"| `{short}` | {n} | {ms:.2f} | {tf:.1f} | {t_main} | {tf / MFMA_PEAK_TFLOPS[t_main]:.1%} | "
+                   f"{util:.1%} | {ghz:.2f} |")
+    return "\n".join(out) + "\n"
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -192,6 +240,11 @@ def main(argv=None):
     t.add_argument("--durations")
     t.add_argument("--title")
     t.add_argument("--command")
+    m = sub.add_parser("mfma")
+    m.add_argument("dir")
+    m.add_argument("--kernel", default="k_tn_mfma", help="name substring of the matrix-core kernels")
+    m.add_argument("--title")
+    m.add_argument("--command")
     q = sub.add_parser("table")
     q.add_argument("dirs", nargs="+")
     q.add_argument("--kernels", required=True, help="comma-separated name substrings")
@@ -200,6 +253,9 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.cmd == "table":
         sys.stdout.write(counter_table(a.dirs, a.kernels.split(","), a.title, a.command))
+        return
+    if a.cmd == "mfma":
+        sys.stdout.write(mfma_table(a.dir, a.kernel, a.title, a.command))
         return
     if a.cmd == "stats":
         sys.stdout.write(stats(a.csv, a.title, a.command))
