@@ -109,6 +109,10 @@ inline void serve_schedule(ServeExecutor& ex, const fx_request* reqs, int nq, co
   std::stable_sort(order.begin(), order.end(),
                    [&](int a, int b) { return reqs[a].t_arrival_s < reqs[b].t_arrival_s; });
   const int ns = ex.n_slots();
+  if (ns <= 0 && n_valid > 0) {  // nowhere to run: refuse rather than wait forever
+    o.fatal = FX_ERR_INVALID;
+    return;
+  }
   std::vector<char> busy(ns, 0);
   std::vector<std::vector<int>> in_slot(ns);
   std::deque<int> waiting;

@@ -269,6 +269,17 @@ int main() {
     serve_schedule(ex, few.data(), (int)few.size(), all, cap, &o);
     CHECK(o.fatal == FX_ERR_DEVICE, "device error: fatal %d", (int)o.fatal);
   }
+  // no slots: the loop refuses instead of waiting forever
+  {
+    FakeExec ex(0, 1);
+    ex.norb = {{0, 16}, {1, 128}, {2, 432}};
+    std::vector<fx_request> few(reqs.begin(), reqs.begin() + 3);
+    std::vector<char> all(few.size(), 1);
+    ex.reqs = few.data();
+    ServeOutcome o;
+    serve_schedule(ex, few.data(), (int)few.size(), all, cap, &o);
+    CHECK(o.fatal == FX_ERR_INVALID && o.done == 0, "no slots: fatal %d", (int)o.fatal);
+  }
   // no requests at all
   {
     FakeExec ex(2, 1);
