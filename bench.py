@@ -110,7 +110,7 @@ def main():
                          "(launch overhead; every replay checked bitwise against the eager result)")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="vx leg: skip the launch-configuration autotuner (run the automatic configuration)")
-    ap.add_argument("--leg", default="vx", choices=["vx", "ace", "serve", "copy", "step"],
+    ap.add_argument("--leg", default="vx", choices=["vx", "ace", "serve", "copy", "step", "stream"],
                     help="vx: V_X apply (default); ace: ACE build + apply at 96^3, N = R = 1024; serve: serving replay")
     ap.add_argument("--requests", type=int, default=12000, help="serve leg: measured requests")
     ap.add_argument("--warm-requests", type=int, default=1000, help="serve leg: warm-up requests")
@@ -123,6 +123,8 @@ def main():
         sys.exit(2)
     if args.leg == "copy":
         return bench_copy(args)
+    if args.leg == "stream":
+        return bench_stream(args)
     if args.leg == "ace":
         return bench_ace(args)
     if args.leg == "serve":
@@ -149,6 +151,12 @@ def main():
     phi = P[:Nt]
     out = torch.empty((Nt, n, n, n), dtype=torch.complex128 if args.prec != "fp32" else torch.complex64, device=dev)
     ctx = Context(0)
+    # the in-place DRAM stream this GPU sustains (the z pass reads and writes the pair volume in
+    # place), measured before the timed region on a 4 GiB buffer that is freed again
+    probe = torch.empty(4 << 30, dtype=torch.uint8, device=dev)
+    stream_gbps = ctx.debug_stream(probe, 2, iters=5)
+    del probe
+    torch.cuda.empty_cache()
     kname = w.get("kernel", "hse")
     kw = dict(n=n, L=L, kernel=kname, omega=0.106, prec=args.prec, out=out)
     # phi = Psi on a workload edge: the library solves each unordered pair once
@@ -240,6 +248,9 @@ def main():
             # measured DRAM-side bytes (copy-calibrated counters) / launch duration
             "traffic_GBps": traffic / (kern[dom]["avg_ms"] * 1e-3) / 1e9 if traffic else None,
             "algorithmic_bytes_per_launch": bytes_per_launch,
+            # the in-place stream probe of the library on this GPU (4 GiB, non-temporal hints)
+            "stream_inplace_GBps": stream_gbps,
+            "frac_of_stream_inplace": achieved / stream_gbps if stream_gbps > 0 else None,
         },
         "kernels": kern,
     }
@@ -360,6 +371,24 @@ def bench_copy(args):
     print(json.dumps({"metric": "device copy bandwidth", "value": 2 * nbytes / (ms * 1e-3) / 1e9, "unit": "GB/s",
                       "bytes_read_per_copy": nbytes, "bytes_written_per_copy": nbytes, "ms_per_copy": ms,
                       "copies": max(1, args.steps) + reps}))
+
+
+def bench_stream(args):
+    """The library's bandwidth probes on a 4 GiB buffer: read-only, write-only and in-place streams
+    (16 bytes per lane, non-temporal hints) -- the practical DRAM ceilings of this GPU."""
+    import torch
+
+    from paper_1905_01348_amd import Context
+
+    ctx = Context(0)
+    buf = torch.zeros(4 << 30, dtype=torch.uint8, device="cuda:0")
+    iters = max(5, args.steps)
+    rates = {name: ctx.debug_stream(buf, mode, iters=iters) for mode, name in ((0, "read"), (1, "write"),
+                                                                                (2, "in_place"))}
+    ctx.close()
+    print(json.dumps({"metric": "DRAM stream bandwidth (in place)", "value": rates["in_place"], "unit": "GB/s",
+                      "read_GBps": rates["read"], "write_GBps": rates["write"], "in_place_GBps": rates["in_place"],
+                      "bytes": 4 << 30, "passes": iters, "peak_GBps": HBM_PEAK_GBS}))
 
 
 MFMA_PEAK_TFLOPS = {"ace_fp32r": 157.3, "ace_fp32": 157.3, "ace_bf16r": 2500.0, "ace_bf16": 2500.0,

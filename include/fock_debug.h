@@ -42,6 +42,17 @@ fx_status fx_debug_axis_plans(int32_t n, int32_t max_plans, int32_t* radix_out, 
  * allocation of the process.  Errors: FX_ERR_INVALID (k < 0). */
 fx_status fx_debug_fail_alloc(int64_t k);
 
+/* Bandwidth probe: `iters` passes (after one warm-up pass) of a stream over
+ * the device buffer buf of `bytes` bytes (16-byte aligned, a multiple of 16,
+ * at least 4096), 16 bytes per lane with non-temporal hints, on `stream`:
+ * mode 0 reads it (its first 4 KiB may be overwritten), 1 writes it, 2 reads
+ * and writes it in place (adding 1 to every 32-bit word).  *gbps receives the bytes moved (2 x bytes per pass
+ * in place) per second, timed with events on the stream; the call waits for
+ * the passes.  These are the DRAM rates the pass kernels' rates are read
+ * against.  Errors: FX_ERR_INVALID, FX_ERR_DEVICE. */
+fx_status fx_debug_stream(fx_ctx* ctx, int32_t mode, void* buf, size_t bytes, int32_t iters, void* stream,
+                          double* gbps);
+
 #ifdef __cplusplus
 }
 #endif

@@ -120,6 +120,8 @@ _SIGS = {
                                            C.c_void_p, C.c_void_p]),
     "fx_debug_axis_plans": (C.c_int, [C.c_int32, C.c_int32, C.c_void_p, C.POINTER(C.c_int32)]),
     "fx_debug_fail_alloc": (C.c_int, [C.c_int64]),
+    "fx_debug_stream": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_size_t, C.c_int32, C.c_void_p,
+                                  C.POINTER(C.c_double)]),
     "fx_apply_kinetic": (C.c_int, [C.c_void_p, C.POINTER(FxCell), C.c_void_p, C.c_int32, C.c_int64, C.c_void_p,
                                    C.c_int64, C.c_int, C.c_int, C.c_void_p]),
     "fx_pt_residual": (C.c_int, [C.c_void_p, C.POINTER(FxCell), C.POINTER(FxKernel), C.c_void_p, C.c_void_p,
@@ -286,6 +288,14 @@ class Context:
                                   _dtype_code(psi), _dtype_code(out), PREC[prec], _stream_ptr(stream),
                                   C.c_void_p(ex.data_ptr()) if ex is not None else None))
         return (out, ex) if energy else out
+
+    def debug_stream(self, buf, mode, *, iters=5, stream=None):
+        """GB/s of a read (mode 0), write (1) or in-place (2) stream over the device tensor buf."""
+        out = C.c_double()
+        _check(load().fx_debug_stream(self.h, int(mode), C.c_void_p(buf.data_ptr()),
+                                      buf.numel() * buf.element_size(), int(iters), _stream_ptr(stream),
+                                      C.byref(out)))
+        return out.value
 
     # -- end-of-step operations ----------------------------------------------------
     def apply_kinetic(self, phi, *, n, L, out=None, out_dtype=None, stream=None):
