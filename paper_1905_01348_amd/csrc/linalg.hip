@@ -111,16 +111,17 @@ __global__ void __launch_bounds__(256, 2) k_zgemm(int M, int N, int K, const z* 
     }
 #pragma unroll 2
     for (int kk = 0; kk < ZK; ++kk) {
-      z b[4];
+      // the step's operands are read before its multiply-adds, so that the
+      // LDS reads overlap
+      z b[4], a[8];
 #pragma unroll
       for (int j = 0; j < 4; ++j) b[j] = Bs[buf][kk][ty + 16 * j];
-      // one A element live at a time keeps the 8x4 accumulators in registers
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const z a = As[buf][kk][tx + 16 * i];
+      for (int i = 0; i < 8; ++i) a[i] = As[buf][kk][tx + 16 * i];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = zfma(acc[i][j], a, b[j]);
-      }
+      for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = zfma(acc[i][j], a[i], b[j]);
     }
     if (more) {
       FX_ZG_SSTORE(buf ^ 1);
