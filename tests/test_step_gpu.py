@@ -149,6 +149,25 @@ def test_residual_planewave_eigenbasis_kinetic(ctx):
     assert np.abs(R - (psi - half)).max() <= 1e-13 * np.abs(psi - half).max()
 
 
+def test_kinetic_errors(ctx):
+    """Output overlapping the input, an empty block and an unsupported edge are refused."""
+    import torch
+
+    n3, L3 = (12, 12, 12), (6.0,) * 3
+    P = dev(_block(97, n3, 3))
+    with pytest.raises(F.FockError) as ei:
+        ctx.apply_kinetic(P, n=n3, L=L3, out=P)
+    assert ei.value.status == F.FX_ERR_INVALID
+    with pytest.raises(F.FockError) as ei:
+        ctx.apply_kinetic(P[:0], n=n3, L=L3)
+    assert ei.value.status == F.FX_ERR_INVALID
+    Q = dev(_block(98, (10, 10, 10), 2))
+    with pytest.raises(F.FockError) as ei:
+        ctx.apply_kinetic(Q, n=(10, 10, 10), L=L3)
+    assert ei.value.status == F.FX_ERR_UNSUPPORTED
+    torch.cuda.synchronize()
+
+
 def test_internal_kernel_kind_is_rejected(ctx):
     """The library's own kinetic kernel kind is not accepted by the public V_X call."""
     import torch
