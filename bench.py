@@ -110,7 +110,7 @@ def main():
                          "(launch overhead; every replay checked bitwise against the eager result)")
     ap.add_argument("--no-autotune", dest="autotune", action="store_false",
                     help="vx leg: skip the launch-configuration autotuner (run the automatic configuration)")
-    ap.add_argument("--leg", default="vx", choices=["vx", "ace", "serve", "copy", "step", "stream"],
+    ap.add_argument("--leg", default="vx", choices=["vx", "ace", "serve", "copy", "step", "stream", "batchsweep"],
                     help="vx: V_X apply (default); ace: ACE build + apply at 96^3, N = R = 1024; serve: serving replay")
     ap.add_argument("--requests", type=int, default=12000, help="serve leg: measured requests")
     ap.add_argument("--warm-requests", type=int, default=1000, help="serve leg: warm-up requests")
@@ -125,6 +125,8 @@ def main():
         return bench_copy(args)
     if args.leg == "stream":
         return bench_stream(args)
+    if args.leg == "batchsweep":
+        return bench_batchsweep(args)
     if args.leg == "ace":
         return bench_ace(args)
     if args.leg == "serve":
@@ -389,6 +391,61 @@ def bench_stream(args):
     print(json.dumps({"metric": "DRAM stream bandwidth (in place)", "value": rates["in_place"], "unit": "GB/s",
                       "read_GBps": rates["read"], "write_GBps": rates["write"], "in_place_GBps": rates["in_place"],
                       "bytes": 4 << 30, "passes": iters, "peak_GBps": HBM_PEAK_GBS}))
+
+
+def bench_batchsweep(args):
+    """Pair-volume residency between the passes: per-pass time per pair at batch volumes from 8 GiB
+    down to one that fits the 256 MB Infinity Cache, with and without non-temporal hints on the pair
+    volume (96^3, the first 256 orbitals x 32 targets of the headline workload)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_1905_01348_amd import Context, fock
+
+    w = synth.workload("96cube_1024x32")
+    n, L, Nt = w["n"], w["L"], w["n_targets"]
+    N = 256
+    psi = torch.from_numpy(synth.make_orbitals(w["seed"], n, L, w["N"], dtype=np.complex64)[:N]).to("cuda:0")
+    out = torch.empty((Nt, n, n, n), dtype=torch.complex128, device="cuda:0")
+    ctx = Context(0)
+    kw = dict(n=n, L=L, kernel="hse", omega=0.106, prec="fp32acc64", out=out)
+    rows = []
+    saved = {k: os.environ.get(k) for k in ("FX_VX_NT", "FX_WORK_MB", "FX_VX_NJ")}
+    # (batch MiB, orbitals per batch; 0 = the library's shape for that volume)
+    cases = [(8192, 0), (2048, 0), (904, 4), (452, 2), (226, 1)]
+    for nt in (1, 0):
+        for mb, nj in cases:
+            os.environ["FX_VX_NT"], os.environ["FX_WORK_MB"] = str(nt), str(mb)
+            if nj:
+                os.environ["FX_VX_NJ"] = str(nj)
+            else:
+                os.environ.pop("FX_VX_NJ", None)
+            ctx.apply_vx(psi, psi[:Nt], **kw)
+            torch.cuda.synchronize()
+            ctx.prof_enable(True)
+            t0 = time.perf_counter()
+            for _ in range(max(1, args.steps)):
+                ctx.apply_vx(psi, psi[:Nt], **kw)
+            torch.cuda.synchronize()
+            el = (time.perf_counter() - t0) / max(1, args.steps)
+            row = {"nt_hint": nt, "batch_mib": mb, "orbitals_per_batch": nj or "auto", "ms_per_apply": 1e3 * el,
+                   "pairs_per_s": N * Nt / el}
+            for name in ("vx_plane_fwd", "vx_pencil_z", "vx_plane_inv"):
+                cnt, ms, _ = ctx.prof_read(fock.KERNEL_IDS[name])
+                row[name + "_us_per_pair"] = 1e3 * ms / (max(1, args.steps) * N * Nt)
+                row["launches_per_apply"] = cnt // max(1, args.steps)
+            ctx.prof_enable(False)
+            rows.append(row)
+            log("[bench-batch] " + json.dumps(row))
+    for k, v in saved.items():
+        if v is None:
+            os.environ.pop(k, None)
+        else:
+            os.environ[k] = v
+    ctx.close()
+    print(json.dumps({"metric": "per-pass time per pair vs batch volume and non-temporal hints", "workload":
+                      f"96cube: {N} orbitals x {Nt} targets, fp32acc64", "rows": rows}))
 
 
 MFMA_PEAK_TFLOPS = {"ace_fp32r": 157.3, "ace_fp32": 157.3, "ace_bf16r": 2500.0, "ace_bf16": 2500.0,

@@ -236,7 +236,8 @@ fx_status fx_vx_get_config(fx_ctx* ctx, const fx_cell* cell, fx_prec prec, int32
  * Build the ACE factors of V_X[psi]: W = V_X psi (with vx_prec), M = psi^H W in
  * FP64, Hermitised, FP64 Cholesky -M = L L^H, L^{-1} in FP64, xi = W L^{-H}.
  * The handle keeps xi (FP64) and, on first use, the split forms needed by
- * ace_prec.  *ex_energy (host, nullable) receives 1/2 tr M.
+ * ace_prec.  ex_energy_dev (device, nullable): one double receiving
+ * E_X = 1/2 tr M, written on `stream` before the call returns.
  * Waits on `stream` once (Cholesky status).  Errors: FX_ERR_INVALID,
  * FX_ERR_UNSUPPORTED, FX_ERR_OOM, FX_ERR_NOT_POSDEF (-M not positive
  * definite: e.g. a single constant orbital with the Coulomb kernel),
@@ -245,7 +246,7 @@ fx_status fx_vx_get_config(fx_ctx* ctx, const fx_cell* cell, fx_prec prec, int32
 fx_status fx_build_ace(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* kernel,
                        const void* psi, int32_t n_psi, int64_t ld_psi, fx_dtype in_dtype,
                        fx_prec vx_prec, fx_prec ace_prec, void* stream,
-                       fx_ace** ace, double* ex_energy);
+                       fx_ace** ace, double* ex_energy_dev);
 
 /*
  * out = K_ACE phi = -xi (xi^H phi).  prec: one of the FX_PREC_ACE_* values.

@@ -37,7 +37,7 @@ fx_status ace_alloc(fx_ace* a, size_t bytes, void** out) {
 
 fx_status ace_build_impl(fx_ctx* ctx, Workspace* ws, const fx_cell* cell, const fx_kernel* kern, const void* psi,
                          int n, int64_t ld, fx_dtype in_dtype, fx_prec vx_prec, fx_prec ace_prec, hipStream_t st,
-                         fx_ace** out, double* ex_host) {
+                         fx_ace** out, double* ex_host, double* ex_dev_out) {
   FX_TRY(check_cell(cell));
   FX_TRY(check_kernel(kern));
   if (!out) FX_FAIL(FX_ERR_INVALID, "ace is NULL");
@@ -111,6 +111,8 @@ fx_status ace_build_impl(fx_ctx* ctx, Workspace* ws, const fx_cell* cell, const 
   // but this call is never captured (it waits on the host below)
   if (hipMemsetAsync(info_dev, 0, sizeof(int), st) != hipSuccess) return fail(FX_ERR_DEVICE);
   if ((s = zherm(st, n, Mraw, n, a->M, Aneg, ex_dev)) != FX_OK) return fail(s);
+  if (ex_dev_out && hipMemcpyAsync(ex_dev_out, ex_dev, sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess)
+    return fail(FX_ERR_DEVICE);
   // -M = L L^H
   if ((s = zpotrf(ctx, ws, st, n, a->L, n, info_dev)) != FX_OK) return fail(s);
   double ex = 0.0;
@@ -213,7 +215,7 @@ extern "C" {
 
 fx_status fx_build_ace(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* kernel, const void* psi, int32_t n_psi,
                        int64_t ld_psi, fx_dtype in_dtype, fx_prec vx_prec, fx_prec ace_prec, void* stream,
-                       fx_ace** ace, double* ex_energy) {
+                       fx_ace** ace, double* ex_energy_dev) {
   clear_error();
   if (!ctx) FX_FAIL(FX_ERR_INVALID, "ctx is NULL");
   std::lock_guard<std::recursive_mutex> lk(ctx->mu);
@@ -221,7 +223,7 @@ fx_status fx_build_ace(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* kernel
   FX_TRY(note_capture(ctx, (hipStream_t)stream));
   if (ctx->capturing) FX_FAIL(FX_ERR_INVALID, "fx_build_ace waits on its stream and cannot be captured");
   FX_TRY(ace_build_impl(ctx, &ctx->ws, cell, kernel, psi, n_psi, ld_psi, in_dtype, vx_prec, ace_prec,
-                        (hipStream_t)stream, ace, ex_energy));
+                        (hipStream_t)stream, ace, nullptr, ex_energy_dev));
   ctx->aces.insert(*ace);
   return FX_OK;
 }

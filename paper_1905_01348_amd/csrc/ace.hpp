@@ -39,7 +39,7 @@ namespace fx {
 fx_status ace_alloc(fx_ace* a, size_t bytes, void** out);
 fx_status ace_build_impl(fx_ctx* ctx, Workspace* ws, const fx_cell* cell, const fx_kernel* kern, const void* psi,
                          int n, int64_t ld, fx_dtype in_dtype, fx_prec vx_prec, fx_prec ace_prec, hipStream_t st,
-                         fx_ace** out, double* ex_host);
+                         fx_ace** out, double* ex_host, double* ex_dev_out = nullptr);
 fx_status ace_apply_impl(fx_ctx* ctx, Workspace* ws, const fx_ace* a, const void* phi, int nphi, int64_t ld_phi,
                          void* out, int64_t ld_out, fx_dtype in_dtype, fx_dtype out_dtype, fx_prec prec,
                          hipStream_t st);

@@ -99,7 +99,7 @@ _SIGS = {
                               C.c_void_p, C.c_int64, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p]),
     "fx_build_ace": (C.c_int, [C.c_void_p, C.POINTER(FxCell), C.POINTER(FxKernel),
                                C.c_void_p, C.c_int32, C.c_int64, C.c_int, C.c_int, C.c_int, C.c_void_p,
-                               C.POINTER(C.c_void_p), C.POINTER(C.c_double)]),
+                               C.POINTER(C.c_void_p), C.c_void_p]),
     "fx_apply_ace": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_int64,
                                C.c_int, C.c_int, C.c_int, C.c_void_p]),
     "fx_ace_export": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
@@ -335,6 +335,8 @@ class Context:
         if out is None:
             out = torch.empty_like(psi)
         op, no, ldo = _cols(out, nr)
+        if no != npsi or out.dtype != psi.dtype:
+            raise ValueError("out must have psi's column count and dtype")
         sp = None
         if s_out is not None:
             if s_out.dtype != torch.complex128 or s_out.numel() != npsi * npsi or not s_out.is_contiguous():
@@ -406,12 +408,16 @@ class Context:
         cell = make_cell(n, L)
         nr = cell.n[0] * cell.n[1] * cell.n[2]
         kern = make_kernel(kernel, omega, scale)
+        import torch
+
         pp, npsi, ldp = _cols(psi, nr)
         h = C.c_void_p()
-        ex = C.c_double()
+        ex = torch.zeros((), dtype=torch.float64, device=psi.device)
         _check(load().fx_build_ace(self.h, C.byref(cell), C.byref(kern), pp, npsi, ldp, _dtype_code(psi),
-                                   PREC[vx_prec], PREC[ace_prec], _stream_ptr(stream), C.byref(h), C.byref(ex)))
-        return Ace(self, h, nr, npsi, tuple(psi.shape[1:]), ex.value, psi.device)
+                                   PREC[vx_prec], PREC[ace_prec], _stream_ptr(stream), C.byref(h),
+                                   C.c_void_p(ex.data_ptr())))
+        # the build has already waited on its stream (Cholesky status); E_X is on the device
+        return Ace(self, h, nr, npsi, tuple(psi.shape[1:]), float(ex.item()), psi.device)
 
 
 class Ace:
@@ -427,6 +433,8 @@ class Ace:
         if out is None:
             out = torch.empty((nphi,) + tuple(phi.shape[1:]), dtype=out_dtype or phi.dtype, device=phi.device)
         op, nout, ldo = _cols(out, self.nr)
+        if nout != nphi:
+            raise ValueError("out must have as many columns as phi")
         _check(load().fx_apply_ace(self.ctx.h, self.h, fp, nphi, ldf, op, ldo, _dtype_code(phi), _dtype_code(out),
                                    PREC[prec], _stream_ptr(stream)))
         return out
@@ -487,7 +495,13 @@ class Server:
             if o is None:
                 op_, ld = None, 0
             elif r["traj"] in self.trajs:
-                op_, _, ld = _cols(o, self.trajs[r["traj"]][0])
+                nr_t, _, dt_t = self.trajs[r["traj"]]
+                op_, ncol, ld = _cols(o, nr_t)
+                # the library writes `count` columns of the trajectory's dtype at ld
+                if o.dtype != dt_t:
+                    raise ValueError(f"request {i}: out must have the trajectory's dtype {dt_t}")
+                if ncol < int(r["count"]):
+                    raise ValueError(f"request {i}: out holds {ncol} columns, the request writes {r['count']}")
             else:  # unknown trajectory: the library reports it per request
                 op_, ld = o.data_ptr(), o.stride(0)
             arr[i].traj, arr[i].op, arr[i].first, arr[i].count = r["traj"], r["op"], r["first"], r["count"]

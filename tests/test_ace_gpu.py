@@ -1,20 +1,22 @@
 """ACE build and apply on the GPU through the C ABI against the FP64 oracle.
 
-Tolerances (relative, per column): FP64 forms 1e-10; FP32 + residual step
-1e-5 (the stated bar for the FP32 forms); BF16 + residual step 1e-4 (its
-error is ~u_bf16^2 x cond, reported, and must beat the unrefined BF16 form
-by a wide margin); unrefined FP32 1e-5; unrefined BF16 2e-2.
+Tolerances (relative, per column, element-wise and L2): FP64 forms 1e-10
+(including K_ACE psi_i = W_i); FP32 + residual step 1e-5 (the stated bar for
+the FP32 forms); BF16 + residual step 3e-5 (two 8-bit pieces per operand and
+the dropped r_A r_B leave about 3 * 2^-18 per product; it must beat the
+unrefined BF16 form by a wide margin); unrefined FP32 1e-5; unrefined BF16
+2e-2.
 """
 import numpy as np
 import pytest
 
 import oracle
 import synth
-from tests.gpu_util import col_err, dev, host, say
+from tests.gpu_util import rel_err, dev, host, say
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"ace_fp64": 1e-10, "ace_fp32r": 1e-5, "ace_bf16r": 1e-4, "ace_fp32": 1e-5, "ace_bf16": 2e-2}
+TOL = {"ace_fp64": 1e-10, "ace_fp32r": 1e-5, "ace_bf16r": 3e-5, "ace_fp32": 1e-5, "ace_bf16": 2e-2}
 
 
 @pytest.fixture(scope="module")
@@ -59,21 +61,21 @@ def test_ace_build_and_apply_all_precisions(ctx, case):
     nr = int(np.prod(n3))
     assert np.abs(host(M) - ace_ref["M"]).max() <= 1e-10 * np.abs(ace_ref["M"]).max()
     assert np.abs(host(L) - ace_ref["L"]).max() <= 1e-10 * np.abs(ace_ref["L"]).max()
-    assert col_err(host(xi), ace_ref["xi"]) <= 1e-10
+    assert rel_err(host(xi), ace_ref["xi"]) <= 1e-10
     assert abs(ace.ex - ace_ref["ex"]) <= 1e-12 * abs(ace_ref["ex"])
     F = dev(phi)
     errs = {}
     for prec in ("ace_fp64", "ace_fp32r", "ace_bf16r", "ace_fp32", "ace_bf16"):
         y = ace.apply(F, prec=prec, out_dtype=torch.complex128)
         torch.cuda.synchronize()
-        errs[prec] = col_err(host(y), y_ref)
+        errs[prec] = rel_err(host(y), y_ref)
         # K_ACE psi_i = W_i
         yw = ace.apply(P, prec=prec, out_dtype=torch.complex128)
         torch.cuda.synchronize()
-        ew = col_err(host(yw), w.reshape(N, nr))
+        ew = rel_err(host(yw), w.reshape(N, nr))
         say("  ", prec, "K_ACE phi err", errs[prec], "K_ACE psi = W err", ew)
         assert errs[prec] <= TOL[prec], (prec, errs[prec])
-        assert ew <= max(TOL[prec], 1e-9 if prec == "ace_fp64" else TOL[prec]), (prec, ew)
+        assert ew <= TOL[prec], (prec, ew)
     # the residual step must help where the rounding error dominates
     assert errs["ace_bf16r"] < 0.05 * errs["ace_bf16"]
     ace.free()
@@ -96,7 +98,7 @@ def test_ace_complex64_io(ctx):
         y = ace.apply(dev(phi32), prec=prec, out_dtype=torch.complex64)
         torch.cuda.synchronize()
         assert y.dtype == torch.complex64
-        err = col_err(host(y), y32)
+        err = rel_err(host(y), y32)
         say("c64 io", prec, err)
         assert err <= max(TOL[prec], 1e-5)
     ace.free()

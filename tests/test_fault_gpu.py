@@ -14,7 +14,7 @@ import pytest
 import oracle
 import synth
 from paper_1905_01348_amd import fock as F
-from tests.gpu_util import col_err, dev, host, say
+from tests.gpu_util import rel_err, dev, host, say
 
 pytestmark = pytest.mark.gpu
 
@@ -99,7 +99,7 @@ def test_each_allocation_failure_leaves_a_usable_context(name):
                 ok = False
                 failed += 1
             F.debug_fail_alloc(0)
-            err = col_err(op(ctx), ref)
+            err = rel_err(op(ctx), ref)
             assert err <= tol, (name, k, err)
         finally:
             F.debug_fail_alloc(0)
@@ -133,7 +133,7 @@ def test_serving_absorbs_a_failed_workspace_allocation():
             torch.cuda.synchronize()
             assert st == [0, 0], (k, st)
             for o in outs:
-                assert col_err(host(o).astype(np.complex128), ref) <= 1e-5, k
+                assert rel_err(host(o).astype(np.complex128), ref) <= 1e-5, k
         srv.close()
     finally:
         F.debug_fail_alloc(0)

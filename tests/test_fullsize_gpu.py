@@ -2,18 +2,29 @@
 
 The FP64 oracle cannot redo the whole workload in test time (a full V_X
 column is 1024 pair FFTs of 96^3), so the checks are: sampled output columns
-recomputed by the oracle one by one, properties that hold at any size
-(Hermiticity and sign of the projected operator), and the FP32 forms against
-the GPU FP64 form on every column.  Launch configuration as in bench.py.
+recomputed by the oracle one by one, graded element-wise as well as by norm
+(rel_err), properties that hold at any size (Hermiticity and sign of the
+projected operator), and the FP32 forms against the GPU FP64 form on every
+column.  The sampled targets 0, 5, 17 and 31 fall in four different
+eighths of the 32 targets (the plane-inverse pass gives each of the eight
+XCDs a contiguous eighth of a batch's targets) and at both ends of the
+target range; launch configuration as in bench.py.
 """
 import numpy as np
 import pytest
 
 import oracle
 import synth
-from tests.gpu_util import col_err, host, say, workers
+from tests.gpu_util import host, l2_err, rel_err, say, workers
 
 pytestmark = pytest.mark.gpu
+
+VX_COLS = (0, 5, 17, 31)      # targets of the 32-target share checked against the oracle
+ACE_COLS = (5, 700)           # K_ACE psi_k = V_X psi_k checked against the oracle
+# BF16 with one residual step keeps 2 x 8 significant bits of each operand and
+# drops r_A r_B: about 3 * 2^-18 = 1.1e-5 per product, so it does not reach
+# 1e-5 reliably (measured 1.5e-5 element-wise at this size); held to 3e-5
+TOL_BF16R = 3e-5
 
 
 @pytest.fixture(scope="module")
@@ -27,6 +38,18 @@ def share():
     return w, psi, P
 
 
+_ORACLE = {}
+
+
+def oracle_col(share, k):
+    """V_X psi_k over all 1024 orbitals, by the FP64 oracle (cached per module)."""
+    w, psi, _ = share
+    if k not in _ORACLE:
+        say("oracle column", k)
+        _ORACLE[k] = oracle.apply_vx(psi, psi[k:k + 1], w["n"], w["L"], "hse", 0.106, workers=workers())
+    return _ORACLE[k]
+
+
 @pytest.mark.timeout(900)
 def test_vx_share_fullsize(share):
     import torch
@@ -38,32 +61,33 @@ def test_vx_share_fullsize(share):
     out = ctx.apply_vx(P, P[:Nt], n=n, L=L, kernel="hse", omega=0.106, prec="fp32acc64")
     torch.cuda.synchronize()
     o = host(out)
-    k = 5
-    say("oracle column", k)
-    ref = oracle.apply_vx(psi, psi[k:k + 1], n, L, "hse", 0.106, workers=workers())
-    err = col_err(o[k:k + 1], ref)
-    say("fp32acc64 column err", err)
-    assert err <= 1e-5
+    # FP64 form on every column
+    P64 = P.to(torch.complex128)
+    out64 = ctx.apply_vx(P64, P64[:Nt], n=n, L=L, kernel="hse", omega=0.106, prec="fp64")
+    torch.cuda.synchronize()
+    o64 = host(out64)
+    del P64, out64
+    ctx.close()
+    for k in VX_COLS:
+        ref = oracle_col(share, k)
+        err = rel_err(o[k:k + 1], ref)
+        err64 = rel_err(o64[k:k + 1], ref)
+        say("column", k, "fp32acc64 err", err, "(l2", l2_err(o[k:k + 1], ref), ") fp64 err", err64)
+        assert err <= 1e-5, k
+        assert err64 <= 1e-10, k
     # projected operator on the 32 targets: Hermitian, negative diagonal
     T = psi[:Nt].reshape(Nt, -1).astype(np.complex128)
     Mb = T.conj() @ o.reshape(Nt, -1).T
     assert np.abs(Mb - Mb.conj().T).max() <= 1e-6 * np.abs(Mb).max()
     assert np.all(np.diag(Mb).real < 0)
-    # FP64 form on every column
-    P64 = P.to(torch.complex128)
-    out64 = ctx.apply_vx(P64, P64[:Nt], n=n, L=L, kernel="hse", omega=0.106, prec="fp64")
-    torch.cuda.synchronize()
-    e64 = col_err(o, host(out64))
+    e64 = rel_err(o, o64)
     say("fp32acc64 vs fp64 (all columns)", e64)
     assert e64 <= 1e-5
-    assert col_err(host(out64[k:k + 1]), ref) <= 1e-10
-    del P64, out64
-    ctx.close()
 
 
 @pytest.mark.timeout(1200)
 def test_ace_fullsize(share):
-    """ACE at N = R = 1024 on 96^3: K_ACE psi_k = V_X psi_k (oracle column), precision forms vs FP64."""
+    """ACE at N = R = 1024 on 96^3: K_ACE psi_k = V_X psi_k (oracle columns), precision forms vs FP64."""
     import torch
     from paper_1905_01348_amd import Context
 
@@ -72,25 +96,30 @@ def test_ace_fullsize(share):
     ctx = Context(0)
     say("building ACE (1024^2 pairs)")
     ace = ctx.build_ace(P, n=n, L=L, kernel="hse", omega=0.106, vx_prec="fp32acc64", ace_prec="ace_fp64")
-    k = 5
-    ref = oracle.apply_vx(psi, psi[k:k + 1], n, L, "hse", 0.106, workers=workers())
-    for prec, tol in (("ace_fp64", 1e-5), ("ace_fp32r", 1e-5), ("ace_bf16r", 1e-4)):
-        y = ace.apply(P[k:k + 1], prec=prec, out_dtype=torch.complex128)
-        torch.cuda.synchronize()
-        err = col_err(host(y), ref)
-        say("K_ACE psi_k vs oracle V_X psi_k", prec, err)
-        assert err <= tol
+    ks = list(ACE_COLS)
+    ys = {}
+    for prec in ("ace_fp64", "ace_fp32r", "ace_bf16r"):
+        ys[prec] = host(ace.apply(P[ks], prec=prec, out_dtype=torch.complex128))
+    torch.cuda.synchronize()
+    for i, k in enumerate(ks):
+        ref = oracle_col(share, k)
+        for prec in ("ace_fp64", "ace_fp32r", "ace_bf16r"):
+            err = rel_err(ys[prec][i:i + 1], ref)
+            say("K_ACE psi_k vs oracle V_X psi_k", k, prec, err)
+            # the W columns come from the FP32-FFT pair path (fp32acc64), so the forms are held to 1e-5,
+            # except BF16 with one residual step (its floor: see TOL_BF16R)
+            assert err <= (TOL_BF16R if prec == "ace_bf16r" else 1e-5), (k, prec)
     say("right-hand sides (seed 3)")
     phi = torch.from_numpy(synth.make_orbitals(3, n, L, N, dtype=np.complex64)).to("cuda:0")
     y64 = ace.apply(phi, prec="ace_fp64", out_dtype=torch.complex128)
     r64 = host(y64)
     del y64
-    for prec, tol in (("ace_fp32r", 1e-5), ("ace_bf16r", 1e-4)):
+    for prec in ("ace_fp32r", "ace_bf16r"):
         y = ace.apply(phi, prec=prec, out_dtype=torch.complex64)
         torch.cuda.synchronize()
-        err = col_err(host(y), r64)
+        err = rel_err(host(y), r64)
         say(prec, "vs fp64 on 1024 columns", err)
-        assert err <= tol
+        assert err <= (TOL_BF16R if prec == "ace_bf16r" else 1e-5), prec
         del y
     # K_ACE Hermitian on a sample of the right-hand sides
     S = phi[:16].reshape(16, -1).to(torch.complex128)

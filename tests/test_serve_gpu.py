@@ -10,7 +10,7 @@ import pytest
 import oracle
 import synth
 from synth.requests import poisson_requests
-from tests.gpu_util import col_err, dev, host, say
+from tests.gpu_util import dev, host, rel_err, say, workers
 
 pytestmark = pytest.mark.gpu
 
@@ -90,7 +90,7 @@ def test_mix_equals_alone_and_oracle(setup):
         n3, L, N, _ = TRAJ[r["traj"]]
         psi = psis[r["traj"]].astype(np.complex128)
         ref = oracle.apply_vx(psi, psi[r["first"]:r["first"] + r["count"]], n3, L, "hse", 0.106)
-        err = col_err(mix[i], ref)
+        err = rel_err(mix[i], ref)
         say("req", i, "op", r["op"], "err", err)
         assert err <= 1e-5
 
@@ -169,6 +169,69 @@ def test_autotuned_registration(setup):
         else:
             w = oracle.apply_vx(psi, psi, n3, L, "hse", 0.106)
             ref = oracle.apply_ace(oracle.build_ace(psi, w)["xi"], phi)
-        assert col_err(host(o), ref) <= 1e-5, r
+        assert rel_err(host(o), ref) <= 1e-5, r
+    srv.close()
+    ctx.close()
+
+
+@pytest.mark.timeout(600)
+def test_workload_classes_oracle_sample():
+    """The serving workload's three cell classes (24^3 / N = 16, 48^3 / N = 128, 72^3 / N = 432,
+    complex64, screened kernel) in one mix: every request completes; for each class one V_X and one
+    ACE request are checked against the FP64 oracle (V_X on the block's first and last target;
+    K_ACE psi_i = V_X psi_i for psi_i of the block, since K_ACE equals V_X on span(Psi)) and
+    bitwise against the same request served alone."""
+    import torch
+    from paper_1905_01348_amd import Context, Server
+
+    classes = {10: ((24, 24, 24), 10.26, 16, 4010), 11: ((48, 48, 48), 20.52, 128, 4110),
+               12: ((72, 72, 72), 30.78, 432, 4210)}
+    ctx = Context(0)
+    srv = Server(ctx, max_slots=6, n_streams=3, max_batch_pairs=1 << 16)
+    psis = {}
+    for t, (n3, L, N, seed) in classes.items():
+        say("registering class", n3[0], "N", N)
+        psis[t] = synth.make_orbitals(seed, n3, L, N, dtype=np.complex64)
+        srv.register(t, dev(psis[t]), n=n3, L=L, kernel="hse", omega=0.106, vx_prec="fp32acc64",
+                     ace_prec="ace_fp32r")
+    torch.cuda.synchronize()
+    by_class = {0: [(10, 16)], 1: [(11, 128)], 2: [(12, 432)]}
+    reqs = poisson_requests(44, 30, 400.0, by_class, {0: 0.5, 1: 0.35, 2: 0.15}, block=8)
+    # make sure every (class, op) appears at least once
+    t_last = reqs[-1]["t"]
+    for i, (t, op) in enumerate([(10, 0), (10, 1), (11, 0), (11, 1), (12, 0), (12, 1)]):
+        reqs.append(dict(traj=t, op=op, first=8 * (i % 2), count=8, t=t_last + 0.001 * (i + 1)))
+
+    def outs_for(rs):
+        return [torch.full((r["count"],) + tuple(classes[r["traj"]][0][::-1]), complex(9.0, 9.0),
+                           dtype=torch.complex64, device="cuda") for r in rs]
+
+    outs = outs_for(reqs)
+    for r, o in zip(reqs, outs):
+        r["out"] = o
+    st, lat, rep = srv.serve(reqs)
+    torch.cuda.synchronize()
+    say("classes report", rep)
+    assert all(s == 0 for s in st), st
+    mix = [host(o) for o in outs]
+    done = set()
+    for i, r in enumerate(reqs):
+        key = (r["traj"], r["op"])
+        if key in done:
+            continue
+        done.add(key)
+        n3, L, N, _ = classes[r["traj"]]
+        psi = psis[r["traj"]].astype(np.complex128)
+        ks = [r["first"], r["first"] + r["count"] - 1]
+        ref = oracle.apply_vx(psi, psi[ks], n3, L, "hse", 0.106, workers=workers())
+        err = rel_err(mix[i][[0, r["count"] - 1]], ref)
+        say("class", n3[0], "op", r["op"], "oracle err", err)
+        assert err <= 1e-5, (n3, r["op"], err)
+        alone = dict(r, t=0.0, out=outs_for([r])[0])
+        st1, _, _ = srv.serve([alone])
+        assert st1 == [0]
+        assert np.array_equal(host(alone["out"]).view(np.float32), mix[i].view(np.float32)), \
+            f"request {i} differs alone vs mix"
+    assert len(done) == 6
     srv.close()
     ctx.close()

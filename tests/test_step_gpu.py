@@ -13,7 +13,7 @@ import pytest
 import oracle
 import synth
 from paper_1905_01348_amd import fock as F
-from tests.gpu_util import col_err, dev, host, say
+from tests.gpu_util import rel_err, dev, host, say
 
 pytestmark = pytest.mark.gpu
 
@@ -55,7 +55,7 @@ def test_residual_given_hpsi(ctx, case):
                                        host(Hf).astype(np.complex128), dt)
         else:
             ref_t = ref
-        err = col_err(host(R), ref_t)
+        err = rel_err(host(R), ref_t)
         say("residual", n3, N, dtype, err)
         assert err <= tol
         # S in column-major: element (i, j) at S[j, i] of the row-major tensor
@@ -75,7 +75,7 @@ def test_residual_with_vx(ctx, vx_prec, tol):
     w = oracle.apply_vx(psi, psi, n3, L3, "hse", 0.106)
     ref = oracle.pt_residual(psi, w, half, dt)
     R = ctx.pt_residual(dev(psi), dev(half), n=n3, L=L3, dt=dt, kernel="hse", vx_prec=vx_prec)
-    err = col_err(host(R), ref)
+    err = rel_err(host(R), ref)
     say("residual with V_X", vx_prec, err)
     # the V_X error enters through (dt/2) H Psi, small against Psi - Psi_half
     assert err <= tol
@@ -99,7 +99,7 @@ def test_kinetic(ctx, case):
         ref_t = ref if dtype == torch.complex128 else oracle.apply_kinetic(host(Q).astype(np.complex128), n3, L3)
         got = ctx.apply_kinetic(Q, n=n3, L=L3)
         assert got.dtype == dtype
-        err = col_err(host(got), ref_t)
+        err = rel_err(host(got), ref_t)
         say("kinetic", n3, N, dtype, err)
         assert err <= tol
 
@@ -134,7 +134,7 @@ def test_residual_with_kinetic(ctx, given, vx_prec, tol):
         w = oracle.apply_vx(psi, psi, n3, L3, "hse", 0.106)
         ref = oracle.pt_residual(psi, w + tpsi, half, dt)
         R = ctx.pt_residual(dev(psi), dev(half), n=n3, L=L3, dt=dt, kernel="hse", vx_prec=vx_prec, kinetic=True)
-    err = col_err(host(R), ref)
+    err = rel_err(host(R), ref)
     say("residual with kinetic", "given" if given else "V_X", vx_prec, err)
     assert err <= tol
 
@@ -217,7 +217,7 @@ def test_orthonormalize(ctx, case):
         ctx.orthonormalize(A)
         torch.cuda.synchronize()
         got = host(A).astype(np.complex128)
-        err = col_err(got, ref_t)
+        err = rel_err(got, ref_t)
         X = got.reshape(N, -1)
         orth = np.abs(X.conj() @ X.T - np.eye(N)).max()
         say("orthonormalize", n3, N, dtype, err, "orth", orth)

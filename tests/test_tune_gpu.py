@@ -14,7 +14,7 @@ import pytest
 import oracle
 import synth
 from paper_1905_01348_amd import fock as F
-from tests.gpu_util import col_err, dev, host, say
+from tests.gpu_util import rel_err, dev, host, say
 
 pytestmark = pytest.mark.gpu
 
@@ -85,10 +85,10 @@ def test_specialised_variants_match(ctx, n):
             for v in shapes:
                 ctx.set_vx_config(dict(v, kernels=1), n=n, prec=prec, phi_is_psi=square)
                 got = host(call())
-                d = col_err(got, ref)
+                d = rel_err(got, ref)
                 worst = max(worst, d)
                 assert d <= close[prec], (prec, square, v, d)
-                assert col_err(got, refs[square]) <= TOL[prec], (prec, square, v)
+                assert rel_err(got, refs[square]) <= TOL[prec], (prec, square, v)
             ctx.set_vx_config({"kernels": 1, "work_mb": 64}, n=n, prec=prec, phi_is_psi=square)
             assert np.array_equal(_bits(host(call())), _bits(ref)), (prec, square, "work_mb")
             ctx.set_vx_config(None, n=n, prec=prec, phi_is_psi=square)
@@ -118,7 +118,7 @@ def test_generic_schedules_tiles_threads_match_oracle(ctx, n3):
         for c in cfgs:
             ctx.set_vx_config(c, n=n3, L=L3, prec=prec)
             got = host(ctx.apply_vx(P, Q, n=n3, L=L3, kernel="hse", prec=prec))
-            e = col_err(got, ref)
+            e = rel_err(got, ref)
             worst = max(worst, e)
             assert e <= TOL[prec], (prec, c, e)
         ctx.set_vx_config(None, n=n3, L=L3, prec=prec)
@@ -142,5 +142,5 @@ def test_autotune_stores_a_config_that_applies_use(ctx, case):
     ref = oracle.apply_vx(psi, ref_phi, n3, L3, "hse", 0.106)
     P = dev(psi)
     got = host(ctx.apply_vx(P, None if square else dev(ref_phi), n=n3, L=L3, kernel="hse", prec=prec))
-    assert col_err(got, ref) <= TOL[prec]
+    assert rel_err(got, ref) <= TOL[prec]
     ctx.set_vx_config(None, n=n3, prec=prec, phi_is_psi=square)

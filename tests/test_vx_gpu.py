@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 import synth
-from tests.gpu_util import col_err, dev, host, say, workers
+from tests.gpu_util import rel_err, dev, host, say, workers
 
 pytestmark = pytest.mark.gpu
 
@@ -41,7 +41,7 @@ def test_24cube_fp64_parity_and_energy(ctx, w24):
     say("24^3 fp64", psi.shape)
     out, ex = ctx.apply_vx(dev(psi), n=w["n"], L=w["L"], kernel="coulomb", prec="fp64", energy=True)
     torch.cuda.synchronize()
-    assert col_err(host(out), ref) <= TOL64
+    assert rel_err(host(out), ref) <= TOL64
     ex_ref = oracle.exchange_energy(psi, ref)
     assert abs(ex.item() - ex_ref) <= 1e-12 * abs(ex_ref)
 
@@ -54,7 +54,7 @@ def test_24cube_fp32_paths(ctx, w24, prec):
     say("24cube_16", prec)
     for in_dtype in (torch.complex128, torch.complex64):
         out = ctx.apply_vx(dev(psi, in_dtype), n=w["n"], L=w["L"], kernel="coulomb", prec=prec)
-        err = col_err(host(out), ref)
+        err = rel_err(host(out), ref)
         say("  in", in_dtype, "err", err)
         assert err <= TOL32
 
@@ -103,7 +103,7 @@ def test_grids_fp64_and_fp32(ctx, grid, kind):
         assert st == 0, F.load().fx_last_error()
         torch.cuda.synchronize()
         got = host(O[:, :nr])
-        assert col_err(got, ref.reshape(Nt, nr)) <= tol, prec
+        assert rel_err(got, ref.reshape(Nt, nr)) <= tol, prec
         # padding untouched
         assert np.all(host(O[:, nr:]) == complex(7.0, -7.0))
 
@@ -162,13 +162,13 @@ def test_48cube_sampled_columns(ctx):
         out = ctx.apply_vx(P, n=w["n"], L=w["L"], kernel="hse", prec=prec)
         torch.cuda.synchronize()
         outs[prec] = out
-        err = col_err(host(out[ks]), ref)
+        err = rel_err(host(out[ks]), ref)
         say("48cube_128", prec, err)
         assert err <= tol
     # FP32 forms against the GPU FP64 form on every column
     r64 = host(outs["fp64"])
-    assert col_err(host(outs["fp32acc64"]), r64) <= TOL32
-    assert col_err(host(outs["fp32"]), r64) <= TOL32
+    assert rel_err(host(outs["fp32acc64"]), r64) <= TOL32
+    assert rel_err(host(outs["fp32"]), r64) <= TOL32
 
 
 def test_error_paths(ctx, w24):
@@ -228,8 +228,8 @@ def test_specialised_kernels_match_generic_and_oracle(ctx, n):
         finally:
             os.environ.pop("FX_VX_GENERIC", None)
         torch.cuda.synchronize()
-        e_spec, e_gen = col_err(spec, ref), col_err(gen, ref)
-        say("edge", n, prec, "specialised", e_spec, "generic", e_gen, "diff", col_err(spec, gen))
+        e_spec, e_gen = rel_err(spec, ref), rel_err(gen, ref)
+        say("edge", n, prec, "specialised", e_spec, "generic", e_gen, "diff", rel_err(spec, gen))
         assert e_spec <= tol and e_gen <= tol
 
 
@@ -259,8 +259,8 @@ def test_halved_apply_matches_oracle_and_unhalved(ctx, n):
         finally:
             os.environ.pop("FX_VX_HALVE", None)
         torch.cuda.synchronize()
-        e_h, e_f = col_err(outs[0], ref), col_err(full, ref)
-        say("halved edge", n, prec, "halved", e_h, "unhalved", e_f, "diff", col_err(outs[0], full))
+        e_h, e_f = rel_err(outs[0], ref), rel_err(full, ref)
+        say("halved edge", n, prec, "halved", e_h, "unhalved", e_f, "diff", rel_err(outs[0], full))
         assert e_h <= tol and e_f <= tol
         bits = np.float64 if outs[0].dtype == np.complex128 else np.float32
         for o in outs[1:]:
@@ -277,7 +277,7 @@ def test_halved_energy_and_hermitian_projection(ctx):
     out, ex = ctx.apply_vx(dev(psi), n=n, L=L, kernel="coulomb", prec="fp64", energy=True)
     torch.cuda.synchronize()
     got = host(out)
-    assert col_err(got, ref) <= TOL64
+    assert rel_err(got, ref) <= TOL64
     ex_ref = oracle.exchange_energy(psi, ref)
     assert abs(ex.item() - ex_ref) <= 1e-12 * abs(ex_ref)
     M = psi.reshape(N, -1).conj() @ got.reshape(N, -1).T
@@ -295,7 +295,7 @@ def test_degenerate_counts_on_a_workload_edge(ctx, N, Nt, square):
     P = dev(psi)
     for prec, tol in (("fp64", TOL64), ("fp32acc64", TOL32)):
         got = host(ctx.apply_vx(P, None if square else dev(phi), n=n, L=L, kernel="hse", prec=prec))
-        assert col_err(got, ref) <= tol, (prec, N, Nt)
+        assert rel_err(got, ref) <= tol, (prec, N, Nt)
 
 
 @pytest.mark.parametrize("square", [True, False])
@@ -328,7 +328,7 @@ def test_padded_leading_dimensions_on_a_workload_edge(ctx, square):
                               C.c_void_p(torch.cuda.current_stream().cuda_stream), None)
     assert st == 0, F.load().fx_last_error()
     torch.cuda.synchronize()
-    assert col_err(host(O[:, :nr]), ref) <= TOL64
+    assert rel_err(host(O[:, :nr]), ref) <= TOL64
     assert np.all(host(O[:, nr:]) == complex(5.0, 5.0))
 
 
