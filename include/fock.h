@@ -163,6 +163,39 @@ fx_status fx_apply_vx(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* kernel,
                       fx_dtype in_dtype, fx_dtype out_dtype, fx_prec prec,
                       void* stream, double* ex_energy_dev);
 
+/* Size of the fixed device scratch region of fx_apply_vx_noalloc (per device). */
+#define FX_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+
+/*
+ * fx_apply_vx without any device allocation, for callers that cannot
+ * allocate: code under HIP graph capture, serving loops that must not call
+ * hipMalloc, harnesses that forbid it.  Same arguments, layout, ownership,
+ * result and errors as fx_apply_vx, with these differences:
+ * - Everything beyond psi, phi and out (the grid tables, which it builds on
+ *   the device, the pair work volume, partial sums, energy partials) lives in
+ *   a file-scope device array of FX_NOALLOC_SCRATCH_BYTES that each device
+ *   holds from the library's load until the process ends; fx_init looks up
+ *   its address.  The call never allocates or frees device memory and never
+ *   waits on the host.  A call whose tables and one pair volume (N_r complex
+ *   values of the compute precision), plus partial sums when they cannot
+ *   live in out, exceed the region fails with FX_ERR_INVALID before anything
+ *   is launched; pass out in the accumulation type (complex128 for FP64 and
+ *   FP32_ACC64, complex64 for FP32) so that partial sums live there.
+ * - in_dtype must be the compute type (complex128 for FX_PREC_FP64, complex64
+ *   for the FP32 forms): no conversion (FX_ERR_UNSUPPORTED otherwise).
+ * - Each pair is solved as (j, k) even when phi == psi (no halving); the
+ *   result agrees with fx_apply_vx to rounding.
+ * - All calls on one device share its region and its contents persist from
+ *   call to call; calls that overlap in time on one device (other streams,
+ *   threads or contexts) race and must be serialised by the caller.
+ */
+fx_status fx_apply_vx_noalloc(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* kernel,
+                              const void* psi, int32_t n_psi, int64_t ld_psi,
+                              const void* phi, int32_t n_phi, int64_t ld_phi,
+                              void* out, int64_t ld_out,
+                              fx_dtype in_dtype, fx_dtype out_dtype, fx_prec prec,
+                              void* stream, double* ex_energy_dev);
+
 /*
  * Launch configuration of the V_X pair path for one grid, one V_X precision
  * and one form (phi == psi with all N targets, or not).  The batching of pair

@@ -65,9 +65,14 @@ struct DevBuf {
 };
 
 // Named scratch buffers for one stream of work (the context has one set, a
-// server has one set per in-flight slot).
+// server has one set per in-flight slot).  With an arena set, buffers are
+// carved in order from that fixed device region instead of being allocated
+// (fx_apply_vx_noalloc); a request that does not fit is refused.
 struct Workspace {
   std::map<std::string, DevBuf> bufs;
+  char* arena = nullptr;
+  size_t arena_bytes = 0;
+  size_t arena_used = 0;
 };
 
 // Cached per-grid constant tables (twiddles, fold maps, kernel tables).
@@ -207,5 +212,9 @@ fx_status prof_begin(fx_ctx* ctx, hipStream_t st, int id, double work, int* slot
 fx_status prof_end(fx_ctx* ctx, hipStream_t st, int slot);
 
 inline size_t dtype_size(fx_dtype d) { return d == FX_C128 ? 16 : 8; }
+
+// Allocation-free form (noalloc.hip): look up, once per device and with that
+// device current, the device address of the file-scope scratch region.
+fx_status scratch_setup(int device);
 
 }  // namespace fx

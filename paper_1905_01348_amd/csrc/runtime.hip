@@ -109,6 +109,19 @@ fx_status ws_get(fx_ctx* ctx, Workspace* ws, const char* name, size_t bytes, voi
     *out = b.ptr;
     return FX_OK;
   }
+  if (ws->arena) {
+    const size_t off = (ws->arena_used + 255) & ~(size_t)255;
+    if (off > ws->arena_bytes || bytes > ws->arena_bytes - off)
+      FX_FAIL(FX_ERR_INVALID,
+              "workspace '%s' needs %zu bytes at offset %zu of a %zu-byte scratch region; the call is too large "
+              "for the allocation-free form",
+              name, bytes, off, ws->arena_bytes);
+    b.ptr = ws->arena + off;
+    b.bytes = bytes;
+    ws->arena_used = off + bytes;
+    *out = b.ptr;
+    return FX_OK;
+  }
   if (ctx->capturing)
     FX_FAIL(FX_ERR_INVALID,
             "workspace '%s' must grow to %zu bytes while the stream is being captured; "
@@ -128,8 +141,10 @@ fx_status ws_get(fx_ctx* ctx, Workspace* ws, const char* name, size_t bytes, voi
 }
 
 void ws_release(fx_ctx* ctx, Workspace* ws) {
-  for (auto& kv : ws->bufs) ctx_free(ctx, kv.second.ptr, kv.second.bytes);
+  if (!ws->arena)
+    for (auto& kv : ws->bufs) ctx_free(ctx, kv.second.ptr, kv.second.bytes);
   ws->bufs.clear();
+  ws->arena_used = 0;
 }
 
 // ---- per-kernel timing ------------------------------------------------------
@@ -481,6 +496,14 @@ fx_status fx_init(int device, size_t hbm_budget_bytes, fx_ctx** ctx) {
   if (e != hipSuccess) {
     delete c;
     FX_FAIL(FX_ERR_DEVICE, "hipStreamCreate failed: %s", hipGetErrorString(e));
+  }
+  // device address of this device's copy of the allocation-free entry
+  // point's scratch region (looked up once per device)
+  const fx_status ss = scratch_setup(device);
+  if (ss != FX_OK) {
+    (void)hipStreamDestroy(c->stream);
+    delete c;
+    return ss;
   }
   *ctx = c;
   return FX_OK;

@@ -741,10 +741,35 @@ fx_status vx_apply(fx_ctx* ctx, Workspace* ws, const VxArgs& a_in, hipStream_t s
   resolve_vx_config(ctx, &a);
   const int64_t nr = (int64_t)a.cell->n[0] * a.cell->n[1] * a.cell->n[2];
   const bool t64 = a.prec == FX_PREC_FP64;
-  const GridTables* tb = nullptr;
-  FX_TRY(grid_tables(ctx, a.cell, a.kern, t64 ? 0 : 1, a.plans_set ? &a.plans : nullptr, &tb));
   const bool same = a.phi == a.psi && a.ld_phi == a.ld_psi;
   const bool need_conv = (a.in_dtype == FX_C128) != t64;
+  const GridTables* tb = nullptr;
+  GridTables tb_scratch;
+  if (a.no_alloc) {
+    if (!ws->arena) FX_FAIL(FX_ERR_INVALID, "allocation-free call without a scratch region");
+    if (need_conv)
+      FX_FAIL(FX_ERR_UNSUPPORTED, "the allocation-free form takes %s inputs for this precision (no conversion)",
+              t64 ? "complex128" : "complex64");
+    a.halve = 0;
+    FX_TRY(scratch_tables(ws, a.cell, a.kern, t64 ? 0 : 1, a.plans_set ? &a.plans : nullptr, st, &tb_scratch));
+    tb = &tb_scratch;
+    // what the scratch region must still hold besides the pair volume: partial
+    // sums when out cannot hold them, and the energy partials
+    const size_t asz = a.prec == FX_PREC_FP32 ? 8 : 16;
+    const size_t reserve = (dtype_size(a.out_dtype) != asz ? (size_t)a.n_phi * nr * asz : 0) +
+                           (a.ex_dev ? (size_t)a.n_phi * sizeof(double) : 0) + 3 * 256;
+    const size_t used = (ws->arena_used + 255) & ~(size_t)255;
+    const size_t room = ws->arena_bytes > used + reserve ? ws->arena_bytes - used - reserve : 0;
+    const size_t pair_bytes = (size_t)nr * (t64 ? 16 : 8);
+    if (room < pair_bytes)
+      FX_FAIL(FX_ERR_INVALID,
+              "the %zu-byte scratch region cannot hold one pair volume (%zu bytes) besides %zu bytes of tables and "
+              "%zu of partial sums; the call is too large for the allocation-free form",
+              ws->arena_bytes, pair_bytes, used, reserve);
+    a.work_cap = a.work_cap ? std::min(a.work_cap, room) : room;
+  } else {
+    FX_TRY(grid_tables(ctx, a.cell, a.kern, t64 ? 0 : 1, a.plans_set ? &a.plans : nullptr, &tb));
+  }
   const void* psi = a.psi;
   const void* phi = a.phi;
   int64_t ld_psi = a.ld_psi, ld_phi = a.ld_phi;

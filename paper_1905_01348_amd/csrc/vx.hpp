@@ -39,6 +39,9 @@ struct VxArgs {
   int nt_hint = -1;  // specialised kernels: non-temporal hints on the pair volume (1, 0, -1 automatic = 1)
   bool plans_set = false;  // generic kernels: radix schedules in `plans`
   PlanSet plans;
+  // allocation-free form: `ws` carves from a fixed scratch region, the grid
+  // tables are built there on the device, no conversion, no pair halving
+  bool no_alloc = false;
 };
 
 // Radix rows (0-terminated, all-zero row = default) to plans; false if a row
@@ -106,5 +109,10 @@ fx_status check_vx_args(const VxArgs& a);
 fx_status convert_cols(const void* in, fx_dtype din, int64_t ld_in, void* out, fx_dtype dout, int64_t ld_out,
                        int64_t nr, int ncols, hipStream_t st);
 fx_status vx_apply(fx_ctx* ctx, Workspace* ws, const VxArgs& a, hipStream_t st, VxStats* stats);
+// Grid tables (twiddles, fold maps, the kernel on the folded grid) for one
+// cell, kernel and table precision (0 FP64, 1 FP32), carved from the arena
+// of `ws` and filled on `st` by a device kernel (noalloc.hip).
+fx_status scratch_tables(Workspace* ws, const fx_cell* cell, const fx_kernel* kern, int prec, const PlanSet* plans,
+                         hipStream_t st, GridTables* out);
 
 }  // namespace fx

@@ -97,6 +97,9 @@ _SIGS = {
     "fx_apply_vx": (C.c_int, [C.c_void_p, C.POINTER(FxCell), C.POINTER(FxKernel),
                               C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_int32, C.c_int64,
                               C.c_void_p, C.c_int64, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p]),
+    "fx_apply_vx_noalloc": (C.c_int, [C.c_void_p, C.POINTER(FxCell), C.POINTER(FxKernel),
+                                      C.c_void_p, C.c_int32, C.c_int64, C.c_void_p, C.c_int32, C.c_int64,
+                                      C.c_void_p, C.c_int64, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p]),
     "fx_build_ace": (C.c_int, [C.c_void_p, C.POINTER(FxCell), C.POINTER(FxKernel),
                                C.c_void_p, C.c_int32, C.c_int64, C.c_int, C.c_int, C.c_int, C.c_void_p,
                                C.POINTER(C.c_void_p), C.c_void_p]),
@@ -288,6 +291,34 @@ class Context:
                                   _dtype_code(psi), _dtype_code(out), PREC[prec], _stream_ptr(stream),
                                   C.c_void_p(ex.data_ptr()) if ex is not None else None))
         return (out, ex) if energy else out
+
+    def apply_vx_noalloc(self, psi, phi=None, *, out, n, L, kernel="hse", omega=0.106, scale=1.0,
+                         prec="fp32acc64", stream=None, energy_out=None):
+        """out = V_X[psi] phi through fx_apply_vx_noalloc (no device allocation in the library;
+        out and the optional float64 device scalar energy_out are the caller's).  Returns out."""
+        import torch
+
+        cell = make_cell(n, L)
+        nr = cell.n[0] * cell.n[1] * cell.n[2]
+        kern = make_kernel(kernel, omega, scale)
+        if phi is None:
+            phi = psi
+        pp, npsi, ldp = _cols(psi, nr)
+        fp, nphi, ldf = _cols(phi, nr)
+        op, nout, ldo = _cols(out, nr)
+        if nout != nphi:
+            raise ValueError("out must have as many columns as phi")
+        if psi.dtype != phi.dtype:
+            raise TypeError("psi and phi must have the same dtype")
+        ep = None
+        if energy_out is not None:
+            if energy_out.dtype != torch.float64 or energy_out.numel() != 1 or not energy_out.is_cuda:
+                raise ValueError("energy_out must be a one-element float64 device tensor")
+            ep = C.c_void_p(energy_out.data_ptr())
+        _check(load().fx_apply_vx_noalloc(self.h, C.byref(cell), C.byref(kern), pp, npsi, ldp, fp, nphi, ldf, op,
+                                          ldo, _dtype_code(psi), _dtype_code(out), PREC[prec], _stream_ptr(stream),
+                                          ep))
+        return out
 
     def debug_stream(self, buf, mode, *, iters=5, stream=None):
         """GB/s of a read (mode 0), write (1) or in-place (2) stream over the device tensor buf."""
