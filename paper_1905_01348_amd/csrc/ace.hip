@@ -50,7 +50,7 @@ fx_status ace_build_impl(fx_ctx* ctx, Workspace* ws, const fx_cell* cell, const 
   if (in_dtype != FX_C128 && in_dtype != FX_C64) FX_FAIL(FX_ERR_UNSUPPORTED, "unknown in_dtype %d", in_dtype);
   if (vx_prec != FX_PREC_FP64 && vx_prec != FX_PREC_FP32 && vx_prec != FX_PREC_FP32_ACC64)
     FX_FAIL(FX_ERR_UNSUPPORTED, "vx_prec %d is not a V_X precision", vx_prec);
-  if (ace_prec < FX_PREC_ACE_FP64 || ace_prec > FX_PREC_ACE_BF16)
+  if (ace_prec < FX_PREC_ACE_FP64 || ace_prec > FX_PREC_ACE_FP16)
     FX_FAIL(FX_ERR_UNSUPPORTED, "ace_prec %d is not an ACE precision", ace_prec);
 
   fx_ace* a = new fx_ace();
@@ -168,7 +168,7 @@ fx_status ace_apply_impl(fx_ctx* ctx, Workspace* ws, const fx_ace* ac, const voi
   if (ld_phi < nr || ld_out < nr) FX_FAIL(FX_ERR_INVALID, "leading dimensions must be >= N_r = %lld", (long long)nr);
   if (in_dtype != FX_C128 && in_dtype != FX_C64) FX_FAIL(FX_ERR_UNSUPPORTED, "unknown in_dtype %d", in_dtype);
   if (out_dtype != FX_C128 && out_dtype != FX_C64) FX_FAIL(FX_ERR_UNSUPPORTED, "unknown out_dtype %d", out_dtype);
-  if (prec < FX_PREC_ACE_FP64 || prec > FX_PREC_ACE_BF16)
+  if (prec < FX_PREC_ACE_FP64 || prec > FX_PREC_ACE_FP16)
     FX_FAIL(FX_ERR_UNSUPPORTED, "precision %d is not an ACE precision", prec);
   {
     const size_t isz = dtype_size(in_dtype), osz = dtype_size(out_dtype);

@@ -17,6 +17,7 @@ struct AceSplit {
   bool ready = false;
   int64_t kc = 0, kn = 0;
   void *col_p = nullptr, *col_r = nullptr, *row_p = nullptr, *row_r = nullptr;
+  void* smax = nullptr;  // FP16 forms: largest |xi| as FP32 bits (its power-of-two factor)
 };
 
 struct fx_ace {
@@ -30,7 +31,7 @@ struct fx_ace {
   void* xi = nullptr;  // complex double, N_r x N, ld N_r
   void* L = nullptr;   // complex double, N x N, column-major (lower Cholesky factor of -M)
   void* M = nullptr;   // complex double, N x N, Hermitised Psi^H W
-  AceSplit f32, b16;   // split forms for FP32 and BF16 matrix cores
+  AceSplit f32, b16, f16;  // split forms for FP32, BF16 and FP16 matrix cores
   fx::Workspace ws;
   std::vector<std::pair<void*, size_t>> owned;
 };

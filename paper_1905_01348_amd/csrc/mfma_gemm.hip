@@ -14,11 +14,17 @@
 //                   y(r,n) = -(D(r,2n), D(r,2n+1)).
 //
 // Precision forms: every operand X is split as X_p = round(X) and
-// r_X = round(X - X_p) (FP32 or BF16), and with the residual step the GEMM
-// computes A_p B_p (main accumulator) and A_p r_B + r_A B_p (correction
+// r_X = round(X - X_p) (FP32, BF16 or FP16), and with the residual step the
+// GEMM computes A_p B_p (main accumulator) and A_p r_B + r_A B_p (correction
 // accumulator), both in FP32 on the matrix cores, added in FP64 at the end.
+// FP16 operands are scaled by powers of two first (xi by one factor, each
+// right-hand side and each column of C by its own) so that the largest
+// magnitude lands in [2^13, 2^14): the 11-bit significand then holds the
+// values and their residuals without overflow or loss to subnormals, and the
+// exact power-of-two factors are divided out in FP64 afterwards.
 #include <algorithm>
 #include <cstdint>
+#include <type_traits>
 
 #include "fft.hpp"
 #include "mfma_gemm.hpp"
@@ -28,6 +34,7 @@ namespace fx {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 halfx8 __attribute__((ext_vector_type(8)));
 
 // ---- rounding ---------------------------------------------------------------
 // float -> bfloat16, round to nearest even (NaN kept quiet)
@@ -47,6 +54,8 @@ struct Prec<float> {
   static constexpr int PAD = 4;   // LDS row padding (elements)
   __device__ static float round(double x) { return (float)x; }
   __device__ static double widen(float s) { return (double)s; }
+  __device__ static float round_f(float x) { return x; }
+  __device__ static float widen_f(float s) { return s; }
 };
 template <>
 struct Prec<uint16_t> {
@@ -54,7 +63,54 @@ struct Prec<uint16_t> {
   static constexpr int PAD = 8;
   __device__ static uint16_t round(double x) { return f2bf((float)x); }
   __device__ static double widen(uint16_t s) { return (double)bf2f(s); }
+  __device__ static uint16_t round_f(float x) { return f2bf(x); }
+  __device__ static float widen_f(uint16_t s) { return bf2f(s); }
 };
+
+template <>
+struct Prec<_Float16> {
+  static constexpr int BK = 64;
+  static constexpr int PAD = 8;
+  __device__ static _Float16 round(double x) { return (_Float16)x; }
+  __device__ static double widen(_Float16 s) { return (double)s; }
+  __device__ static _Float16 round_f(float x) { return (_Float16)x; }
+  __device__ static float widen_f(_Float16 s) { return (float)s; }
+};
+
+// Power-of-two factor that takes a largest magnitude m (as FP32 bits; m >= 0)
+// into [2^13, 2^14); 1 for the FP32 and BF16 forms (no maxima) and for m = 0.
+__device__ inline double scale_of(const unsigned* maxbits, int i) {
+  if (!maxbits) return 1.0;
+  const float m = __uint_as_float(maxbits[i]);
+  if (!(m > 0.f) || !isfinite(m)) return 1.0;
+  int e = 0;
+  (void)frexpf(m, &e);  // m = f 2^e, f in [0.5, 1)
+  return ldexp(1.0, 14 - e);
+}
+
+// Largest |x| of each column (per_col) or of all columns, as FP32 bits
+// (monotone for non-negative floats, so an integer max merges blocks);
+// `out` must hold zeros first.  x: real view, column c at x + c * ld.
+template <typename T>
+__global__ void k_absmax(const T* __restrict__ x, int64_t ld, int64_t len, int per_col, unsigned* __restrict__ out) {
+  __shared__ float red[256];
+  const int c = blockIdx.y;
+  const T* col = x + (int64_t)c * ld;
+  float m = 0.f;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < len; i += (int64_t)gridDim.x * blockDim.x)
+    m = fmaxf(m, (float)fabs((double)col[i]));
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax(out + (per_col ? c : 0), __float_as_uint(red[0]));
+}
+
+__global__ void k_zero_u32(unsigned* __restrict__ p, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
+}
 
 constexpr int KPAD = 64;  // reduction dims of split arrays are padded to this
 static int64_t roundk(int64_t k) { return (k + KPAD - 1) / KPAD * KPAD; }
@@ -111,7 +167,7 @@ __global__ void __launch_bounds__(256, (MfmaWaves<S>::value)) k_tn_mfma(int M, i
                                                  const S* __restrict__ Ar, int64_t lda, const S* __restrict__ Bp,
                                                  const S* __restrict__ Br, int64_t ldb, double* __restrict__ partial,
                                                  void* __restrict__ out, int64_t ldo, int out_c64, double alpha,
-                                                 int tiles_m, int tiles_n) {
+                                                 const double* __restrict__ colalpha, int tiles_m, int tiles_n) {
   constexpr int BK = Prec<S>::BK;
   constexpr int LDK = BK + Prec<S>::PAD;
   constexpr int EPV = 16 / sizeof(S);  // elements per 16-byte vector
@@ -247,6 +303,31 @@ __global__ void __launch_bounds__(256, (MfmaWaves<S>::value)) k_tn_mfma(int M, i
               }
             }
       }
+    } else if constexpr (std::is_same<S, _Float16>::value) {
+#pragma unroll
+      for (int kk = 0; kk < BK / 16; ++kk) {
+        const int kc = kk * 16 + (lane >> 5) * 8;
+        halfx8 a[2], b[2], a2[2], b2[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          a[t] = __builtin_bit_cast(halfx8, *reinterpret_cast<const uint4*>(sAp + (ar + 32 * t) * LDK + kc));
+          b[t] = __builtin_bit_cast(halfx8, *reinterpret_cast<const uint4*>(sBp + (br + 32 * t) * LDK + kc));
+          if (REFINE) {
+            a2[t] = __builtin_bit_cast(halfx8, *reinterpret_cast<const uint4*>(sAr + (ar + 32 * t) * LDK + kc));
+            b2[t] = __builtin_bit_cast(halfx8, *reinterpret_cast<const uint4*>(sBr + (br + 32 * t) * LDK + kc));
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a[i], b[j], acc[i][j], 0, 0, 0);
+            if (REFINE) {
+              cor[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a[i], b2[j], cor[i][j], 0, 0, 0);
+              cor[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a2[i], b[j], cor[i][j], 0, 0, 0);
+            }
+          }
+      }
     } else {
 #pragma unroll
       for (int kk = 0; kk < BK / 16; ++kk) {
@@ -316,10 +397,11 @@ __global__ void __launch_bounds__(256, (MfmaWaves<S>::value)) k_tn_mfma(int M, i
         const double re = stg[ml * SL + 2 * tl], im = stg[ml * SL + 2 * tl + 1];
         if (m < M && n < N) {
           const int64_t idx = (int64_t)(n >> 1) * ldo + m;
+          const double al = colalpha ? colalpha[n >> 1] : alpha;
           if (out_c64)
-            reinterpret_cast<float2*>(out)[idx] = make_float2((float)(-alpha * re), (float)(-alpha * im));
+            reinterpret_cast<float2*>(out)[idx] = make_float2((float)(-al * re), (float)(-al * im));
           else
-            reinterpret_cast<double2*>(out)[idx] = make_double2(-alpha * re, -alpha * im);
+            reinterpret_cast<double2*>(out)[idx] = make_double2(-al * re, -al * im);
         }
       }
       wave_lds_sync();
@@ -330,11 +412,12 @@ __global__ void __launch_bounds__(256, (MfmaWaves<S>::value)) k_tn_mfma(int M, i
 // xi (complex double, N_r x N, ld N_r) -> col form: row m = interleaved column m.
 template <typename S>
 __global__ void k_split_col(const double* __restrict__ xi, int64_t nr, int n, int64_t kc, S* __restrict__ p,
-                            S* __restrict__ r) {
+                            S* __restrict__ r, const unsigned* __restrict__ smax) {
   const int64_t total = (int64_t)n * kc;
+  const double sc = scale_of(smax, 0);
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t m = i / kc, k = i - m * kc;
-    const double v = k < 2 * nr ? xi[m * 2 * nr + k] : 0.0;
+    const double v = k < 2 * nr ? sc * xi[m * 2 * nr + k] : 0.0;
     const S hp = Prec<S>::round(v);
     p[i] = hp;
     r[i] = Prec<S>::round(v - Prec<S>::widen(hp));
@@ -345,8 +428,10 @@ __global__ void k_split_col(const double* __restrict__ xi, int64_t nr, int n, in
 // to kn.  64 grid points x 32 orbitals per block through LDS.
 template <typename S>
 __global__ void __launch_bounds__(256) k_split_row(const double* __restrict__ xi, int64_t nr, int n, int64_t kn,
-                                                   S* __restrict__ p, S* __restrict__ r) {
+                                                   S* __restrict__ p, S* __restrict__ r,
+                                                   const unsigned* __restrict__ smax) {
   __shared__ double2 t[32][65];
+  const double sc = scale_of(smax, 0);
   const int64_t r0 = (int64_t)blockIdx.x * 64;
   const int m0 = blockIdx.y * 32;
   for (int e = threadIdx.x; e < 32 * 64; e += 256) {
@@ -363,7 +448,7 @@ __global__ void __launch_bounds__(256) k_split_row(const double* __restrict__ xi
     const int64_t rr = r0 + ri;
     if (rr >= nr) continue;
     const double2 v = t[kk >> 1][ri];
-    const double x = (kk & 1) ? v.y : v.x;
+    const double x = sc * ((kk & 1) ? v.y : v.x);
     const int64_t idx = rr * kn + 2 * (int64_t)m0 + kk;
     const S hp = Prec<S>::round(x);
     p[idx] = hp;
@@ -374,11 +459,24 @@ __global__ void __launch_bounds__(256) k_split_row(const double* __restrict__ xi
 // phi (complex, ld) -> B source rows: row n = interleaved phi_n, padded to kc.
 template <typename S, typename TI>
 __global__ void k_split_phi(const TI* __restrict__ phi, int64_t ld, int64_t nr, int R, int64_t kc,
-                            S* __restrict__ p, S* __restrict__ r) {
+                            S* __restrict__ p, S* __restrict__ r, const unsigned* __restrict__ smax) {
   const int64_t total = (int64_t)R * kc;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t n = i / kc, k = i - n * kc;
-    const double v = k < 2 * nr ? (double)phi[n * 2 * ld + k] : 0.0;
+    const double sc = scale_of(smax, (int)n);
+    if constexpr (std::is_same<TI, float>::value) {
+      // FP32 input: the scaled value and its residual are exact in FP32
+      // (a power-of-two factor that stays finite; X - round(X) of an FP32 X),
+      // so the split is the same as in FP64, at FP32 speed
+      if (sc < 0x1p100) {
+        const float v = k < 2 * nr ? (float)sc * phi[n * 2 * ld + k] : 0.f;
+        const S hp = Prec<S>::round_f(v);
+        p[i] = hp;
+        r[i] = Prec<S>::round_f(v - Prec<S>::widen_f(hp));
+        continue;
+      }
+    }
+    const double v = k < 2 * nr ? sc * (double)phi[n * 2 * ld + k] : 0.0;
     const S hp = Prec<S>::round(v);
     p[i] = hp;
     r[i] = Prec<S>::round(v - Prec<S>::widen(hp));
@@ -394,7 +492,9 @@ __global__ void k_reduce_cn(const double* __restrict__ partial, int nsplit, int 
   const int64_t M = n, NN = 2 * (int64_t)R;
   const int64_t total = (int64_t)R * (kn / 2);
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t nc = i / (kn / 2), k = i - nc * (kn / 2);
+    // neighbouring threads take neighbouring right-hand sides: their partial
+    // sums are adjacent in memory (the reads are the bulk of the traffic)
+    const int64_t k = i / R, nc = i - k * R;
     double cr = 0.0, ci = 0.0;
     if (k < n) {
       for (int s = 0; s < nsplit; ++s) {
@@ -414,9 +514,74 @@ __global__ void k_reduce_cn(const double* __restrict__ partial, int nsplit, int 
   }
 }
 
+// The same for scaled FP16 operands, in two passes.  First
+// C(k, nc) = (fixed-order FP64 sum of the partials) / (s_xi s_nc), exact
+// since the factors are powers of two, into an FP64 buffer, with each
+// right-hand side's largest magnitude merged into cmax[nc] (zeroed first).
+// Then the split of t_nc C with t_nc the power of two of cmax[nc], and
+// colalpha[nc] = 1 / (s_xi t_nc) for the epilogue of y = -xi C.
+__global__ void k_sum_cn_scaled(const double* __restrict__ partial, int nsplit, int n, int R,
+                                const unsigned* __restrict__ xmax, const unsigned* __restrict__ pmax,
+                                double2* __restrict__ c64, unsigned* __restrict__ cmax) {
+  const int64_t M = n, NN = 2 * (int64_t)R;
+  const double sx = scale_of(xmax, 0);
+  const int64_t total = (int64_t)n * R;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t k = i / R, nc = i - k * R;
+    double cr = 0.0, ci = 0.0;
+    for (int s = 0; s < nsplit; ++s) {
+      cr += partial[((int64_t)s * M + k) * NN + 2 * nc];
+      ci += partial[((int64_t)s * M + k) * NN + 2 * nc + 1];
+    }
+    const double f = 1.0 / (sx * scale_of(pmax, (int)nc));
+    c64[i] = double2{cr * f, ci * f};
+    atomicMax(cmax + nc, __float_as_uint((float)fmax(fabs(cr * f), fabs(ci * f))));
+  }
+}
+
+template <typename S>
+__global__ void k_split_cn_scaled(const double2* __restrict__ c64, int n, int R, int64_t kn,
+                                  const unsigned* __restrict__ xmax, const unsigned* __restrict__ cmax,
+                                  S* __restrict__ p, S* __restrict__ r, double* __restrict__ colalpha) {
+  const double sx = scale_of(xmax, 0);
+  const int64_t total = (int64_t)R * (kn / 2);
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t nc = i / (kn / 2), k = i - nc * (kn / 2);
+    const double t = scale_of(cmax, (int)nc);
+    if (k == 0) colalpha[nc] = 1.0 / (sx * t);
+    double cr = 0.0, ci = 0.0;
+    if (k < n) {
+      const double2 c = c64[k * R + nc];
+      cr = c.x * t;
+      ci = c.y * t;
+    }
+    const double v[4] = {cr, -ci, ci, cr};
+    const int64_t base0 = (2 * nc) * kn + 2 * k, base1 = (2 * nc + 1) * kn + 2 * k;
+    const int64_t idx[4] = {base0, base0 + 1, base1, base1 + 1};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const S hp = Prec<S>::round(v[q]);
+      p[idx[q]] = hp;
+      r[idx[q]] = Prec<S>::round(v[q] - Prec<S>::widen(hp));
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
+// FP16 operands are scaled by powers of two (see the header comment).
+template <typename S>
+constexpr bool kScaled = std::is_same<S, _Float16>::value;
+
+// workspace names per element size: {phi p, phi r, B p, B r}
+template <typename S>
+static const char* split_name(int which) {
+  static const char* n32[4] = {"mf_phi_p32", "mf_phi_r32", "mf_bnn_p32", "mf_bnn_r32"};
+  static const char* n16[4] = {"mf_phi_p16", "mf_phi_r16", "mf_bnn_p16", "mf_bnn_r16"};
+  return sizeof(S) == 4 ? n32[which] : n16[which];
+}
+
 template <typename K>
 static fx_status allow_lds_mfma(K kernel, size_t bytes) {
   return allow_dynamic_lds(reinterpret_cast<const void*>(kernel), bytes);
@@ -434,12 +599,23 @@ static fx_status prepare_split_t(fx_ace* a, AceSplit* sp, hipStream_t st) {
   FX_TRY(ace_alloc(a, cb, &sp->col_r));
   FX_TRY(ace_alloc(a, rb, &sp->row_p));
   FX_TRY(ace_alloc(a, rb, &sp->row_r));
+  const unsigned* smax = nullptr;
+  if (kScaled<S>) {
+    // one power-of-two factor for all of xi, from its largest magnitude
+    FX_TRY(ace_alloc(a, 256, &sp->smax));
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, (unsigned*)sp->smax, 1);
+    FX_LAUNCH_CHECK();
+    hipLaunchKernelGGL((k_absmax<double>), dim3(std::max(1, 4096 / std::max(n, 1)) , (unsigned)n), dim3(256), 0, st,
+                       (const double*)a->xi, 2 * nr, 2 * nr, 0, (unsigned*)sp->smax);
+    FX_LAUNCH_CHECK();
+    smax = (const unsigned*)sp->smax;
+  }
   const int64_t tc = (int64_t)n * sp->kc;
   hipLaunchKernelGGL((k_split_col<S>), dim3((unsigned)std::min<int64_t>((tc + 255) / 256, 16384)), dim3(256), 0, st,
-                     (const double*)a->xi, nr, n, sp->kc, (S*)sp->col_p, (S*)sp->col_r);
+                     (const double*)a->xi, nr, n, sp->kc, (S*)sp->col_p, (S*)sp->col_r, smax);
   FX_LAUNCH_CHECK();
   hipLaunchKernelGGL((k_split_row<S>), dim3((unsigned)((nr + 63) / 64), (unsigned)(sp->kn / 64)), dim3(256), 0, st,
-                     (const double*)a->xi, nr, n, sp->kn, (S*)sp->row_p, (S*)sp->row_r);
+                     (const double*)a->xi, nr, n, sp->kn, (S*)sp->row_p, (S*)sp->row_r, smax);
   FX_LAUNCH_CHECK();
   sp->ready = true;
   return FX_OK;
@@ -448,6 +624,7 @@ static fx_status prepare_split_t(fx_ace* a, AceSplit* sp, hipStream_t st) {
 fx_status ace_prepare_split(fx_ace* a, fx_prec prec, hipStream_t st) {
   if (prec == FX_PREC_ACE_FP32R || prec == FX_PREC_ACE_FP32) return prepare_split_t<float>(a, &a->f32, st);
   if (prec == FX_PREC_ACE_BF16R || prec == FX_PREC_ACE_BF16) return prepare_split_t<uint16_t>(a, &a->b16, st);
+  if (prec == FX_PREC_ACE_FP16R || prec == FX_PREC_ACE_FP16) return prepare_split_t<_Float16>(a, &a->f16, st);
   return FX_OK;
 }
 
@@ -459,20 +636,37 @@ static fx_status apply_t(fx_ctx* ctx, Workspace* ws, fx_ace* a, AceSplit* sp, co
   const int64_t nr = a->nr;
   const int n = a->n;
   FX_TRY(prepare_split_t<S>(a, sp, st));
-  // phi split
+  // phi split (FP16: each right-hand side scaled by its own power of two)
   void *php = nullptr, *phr = nullptr;
   const size_t pb = sizeof(S) * (size_t)R * sp->kc;
-  FX_TRY(ws_get(ctx, ws, sizeof(S) == 4 ? "mf_phi_p32" : "mf_phi_p16", pb, &php));
-  FX_TRY(ws_get(ctx, ws, sizeof(S) == 4 ? "mf_phi_r32" : "mf_phi_r16", pb, &phr));
+  FX_TRY(ws_get(ctx, ws, split_name<S>(0), pb, &php));
+  FX_TRY(ws_get(ctx, ws, split_name<S>(1), pb, &phr));
+  unsigned* pmax = nullptr;
+  double* colalpha = nullptr;
+  if (kScaled<S>) {
+    void* t = nullptr;
+    FX_TRY(ws_get(ctx, ws, "mf_phimax", sizeof(unsigned) * (size_t)R, &t));
+    pmax = (unsigned*)t;
+    FX_TRY(ws_get(ctx, ws, "mf_colalpha", sizeof(double) * (size_t)R, &t));
+    colalpha = (double*)t;
+    hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)std::min(64, (R + 255) / 256)), dim3(256), 0, st, pmax, R);
+    FX_LAUNCH_CHECK();
+    const dim3 g((unsigned)std::max<int64_t>(1, std::min<int64_t>(64, (2 * nr + 65535) / 65536)), (unsigned)R);
+    if (in_dtype == FX_C128)
+      hipLaunchKernelGGL((k_absmax<double>), g, dim3(256), 0, st, (const double*)phi, 2 * ld_phi, 2 * nr, 1, pmax);
+    else
+      hipLaunchKernelGGL((k_absmax<float>), g, dim3(256), 0, st, (const float*)phi, 2 * ld_phi, 2 * nr, 1, pmax);
+    FX_LAUNCH_CHECK();
+  }
   const int64_t tp = (int64_t)R * sp->kc;
   int slot;
   FX_TRY(prof_begin(ctx, st, FX_K_SPLIT, (double)R * nr * (in_dtype == FX_C128 ? 16 : 8) + 2.0 * pb, &slot));
   if (in_dtype == FX_C128)
     hipLaunchKernelGGL((k_split_phi<S, double>), dim3((unsigned)std::min<int64_t>((tp + 255) / 256, 16384)),
-                       dim3(256), 0, st, (const double*)phi, ld_phi, nr, R, sp->kc, (S*)php, (S*)phr);
+                       dim3(256), 0, st, (const double*)phi, ld_phi, nr, R, sp->kc, (S*)php, (S*)phr, pmax);
   else
     hipLaunchKernelGGL((k_split_phi<S, float>), dim3((unsigned)std::min<int64_t>((tp + 255) / 256, 16384)),
-                       dim3(256), 0, st, (const float*)phi, ld_phi, nr, R, sp->kc, (S*)php, (S*)phr);
+                       dim3(256), 0, st, (const float*)phi, ld_phi, nr, R, sp->kc, (S*)php, (S*)phr, pmax);
   FX_LAUNCH_CHECK();
   FX_TRY(prof_end(ctx, st, slot));
 
@@ -498,18 +692,36 @@ static fx_status apply_t(fx_ctx* ctx, Workspace* ws, fx_ace* a, AceSplit* sp, co
     FX_TRY(prof_begin(ctx, st, FX_K_GEMM_CN, (REFINE ? 3.0 : 1.0) * 2.0 * n * 2.0 * R * (double)sp->kc, &slot));
     hipLaunchKernelGGL(kern, dim3((unsigned)(tiles * nsplit)), dim3(256), lds, st, n, 2 * R, (int)sp->kc,
                        (int)kchunk, (const S*)sp->col_p, (const S*)sp->col_r, sp->kc, (const S*)php, (const S*)phr,
-                       sp->kc, (double*)part, (void*)nullptr, (int64_t)0, 0, 0.0, tiles_m, tiles_n);
+                       sp->kc, (double*)part, (void*)nullptr, (int64_t)0, 0, 0.0, (const double*)nullptr, tiles_m,
+                       tiles_n);
     FX_LAUNCH_CHECK();
     FX_TRY(prof_end(ctx, st, slot));
     // reduce -> B operand of the second product
     void *bp = nullptr, *br = nullptr;
     const size_t bb = sizeof(S) * (size_t)2 * R * sp->kn;
-    FX_TRY(ws_get(ctx, ws, sizeof(S) == 4 ? "mf_bnn_p32" : "mf_bnn_p16", bb, &bp));
-    FX_TRY(ws_get(ctx, ws, sizeof(S) == 4 ? "mf_bnn_r32" : "mf_bnn_r16", bb, &br));
+    FX_TRY(ws_get(ctx, ws, split_name<S>(2), bb, &bp));
+    FX_TRY(ws_get(ctx, ws, split_name<S>(3), bb, &br));
     const int64_t tr = (int64_t)R * (sp->kn / 2);
     FX_TRY(prof_begin(ctx, st, FX_K_REDUCE, 8.0 * nsplit * n * 2.0 * R + 2.0 * bb, &slot));
-    hipLaunchKernelGGL((k_reduce_cn<S>), dim3((unsigned)std::min<int64_t>((tr + 255) / 256, 16384)), dim3(256), 0, st,
-                       (const double*)part, nsplit, n, R, sp->kn, (S*)bp, (S*)br);
+    if (kScaled<S>) {
+      void *c64 = nullptr, *cmax = nullptr;
+      FX_TRY(ws_get(ctx, ws, "mf_c64", 16 * (size_t)n * R, &c64));
+      FX_TRY(ws_get(ctx, ws, "mf_cmax", sizeof(unsigned) * (size_t)R, &cmax));
+      hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)std::min(64, (R + 255) / 256)), dim3(256), 0, st,
+                         (unsigned*)cmax, R);
+      FX_LAUNCH_CHECK();
+      const int64_t tc = (int64_t)n * R;
+      hipLaunchKernelGGL(k_sum_cn_scaled, dim3((unsigned)std::min<int64_t>((tc + 255) / 256, 16384)), dim3(256), 0,
+                         st, (const double*)part, nsplit, n, R, (const unsigned*)sp->smax, (const unsigned*)pmax,
+                         (double2*)c64, (unsigned*)cmax);
+      FX_LAUNCH_CHECK();
+      hipLaunchKernelGGL((k_split_cn_scaled<S>), dim3((unsigned)std::min<int64_t>((tr + 255) / 256, 16384)),
+                         dim3(256), 0, st, (const double2*)c64, n, R, sp->kn, (const unsigned*)sp->smax,
+                         (const unsigned*)cmax, (S*)bp, (S*)br, colalpha);
+    } else {
+      hipLaunchKernelGGL((k_reduce_cn<S>), dim3((unsigned)std::min<int64_t>((tr + 255) / 256, 16384)), dim3(256), 0,
+                         st, (const double*)part, nsplit, n, R, sp->kn, (S*)bp, (S*)br);
+    }
     FX_LAUNCH_CHECK();
     FX_TRY(prof_end(ctx, st, slot));
     // y = -xi C: M = nr, N = 2R, K = kn
@@ -521,7 +733,8 @@ static fx_status apply_t(fx_ctx* ctx, Workspace* ws, fx_ace* a, AceSplit* sp, co
     FX_TRY(prof_begin(ctx, st, FX_K_GEMM_NN, (REFINE ? 3.0 : 1.0) * 2.0 * (double)nr * 2.0 * R * (double)sp->kn, &slot));
     hipLaunchKernelGGL(kern2, dim3((unsigned)(tm2 * tn2)), dim3(256), lds2, st, (int)nr, 2 * R, (int)sp->kn,
                        (int)sp->kn, (const S*)sp->row_p, (const S*)sp->row_r, sp->kn, (const S*)bp, (const S*)br,
-                       sp->kn, (double*)nullptr, out, ld_out, out_dtype == FX_C64 ? 1 : 0, 1.0, tm2, tn2);
+                       sp->kn, (double*)nullptr, out, ld_out, out_dtype == FX_C64 ? 1 : 0, 1.0,
+                       (const double*)colalpha, tm2, tn2);
     FX_LAUNCH_CHECK();
     FX_TRY(prof_end(ctx, st, slot));
   }
@@ -539,6 +752,10 @@ fx_status ace_apply_mfma(fx_ctx* ctx, Workspace* ws, fx_ace* a, const void* phi,
       return apply_t<uint16_t, true>(ctx, ws, a, &a->b16, phi, nphi, ld_phi, out, ld_out, in_dtype, out_dtype, st);
     case FX_PREC_ACE_BF16:
       return apply_t<uint16_t, false>(ctx, ws, a, &a->b16, phi, nphi, ld_phi, out, ld_out, in_dtype, out_dtype, st);
+    case FX_PREC_ACE_FP16R:
+      return apply_t<_Float16, true>(ctx, ws, a, &a->f16, phi, nphi, ld_phi, out, ld_out, in_dtype, out_dtype, st);
+    case FX_PREC_ACE_FP16:
+      return apply_t<_Float16, false>(ctx, ws, a, &a->f16, phi, nphi, ld_phi, out, ld_out, in_dtype, out_dtype, st);
     default:
       FX_FAIL(FX_ERR_UNSUPPORTED, "precision %d is not a matrix-core ACE precision", prec);
   }

@@ -28,7 +28,7 @@ FX_C128, FX_C64 = 0, 1
 FX_COULOMB, FX_HSE = 0, 1
 PREC = {
     "fp64": 0, "fp32": 1, "fp32acc64": 2,
-    "ace_fp64": 3, "ace_fp32r": 4, "ace_bf16r": 5, "ace_fp32": 6, "ace_bf16": 7,
+    "ace_fp64": 3, "ace_fp32r": 4, "ace_bf16r": 5, "ace_fp32": 6, "ace_bf16": 7, "ace_fp16r": 8, "ace_fp16": 9,
 }
 KIND = {"coulomb": FX_COULOMB, "hse": FX_HSE}
 KERNEL_IDS = {"vx_plane_fwd": 0, "vx_pencil_z": 1, "vx_plane_inv": 2, "convert": 3, "gemm_cn": 4, "gemm_nn": 5,

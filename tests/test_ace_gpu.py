@@ -16,7 +16,8 @@ from tests.gpu_util import rel_err, dev, host, say
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"ace_fp64": 1e-10, "ace_fp32r": 1e-5, "ace_bf16r": 3e-5, "ace_fp32": 1e-5, "ace_bf16": 2e-2}
+TOL = {"ace_fp64": 1e-10, "ace_fp32r": 1e-5, "ace_bf16r": 3e-5, "ace_fp16r": 1e-5, "ace_fp32": 1e-5,
+       "ace_bf16": 2e-2, "ace_fp16": 3e-3}
 
 
 @pytest.fixture(scope="module")
@@ -65,7 +66,7 @@ def test_ace_build_and_apply_all_precisions(ctx, case):
     assert abs(ace.ex - ace_ref["ex"]) <= 1e-12 * abs(ace_ref["ex"])
     F = dev(phi)
     errs = {}
-    for prec in ("ace_fp64", "ace_fp32r", "ace_bf16r", "ace_fp32", "ace_bf16"):
+    for prec in ("ace_fp64", "ace_fp32r", "ace_bf16r", "ace_fp16r", "ace_fp32", "ace_bf16", "ace_fp16"):
         y = ace.apply(F, prec=prec, out_dtype=torch.complex128)
         torch.cuda.synchronize()
         errs[prec] = rel_err(host(y), y_ref)
@@ -78,6 +79,7 @@ def test_ace_build_and_apply_all_precisions(ctx, case):
         assert ew <= TOL[prec], (prec, ew)
     # the residual step must help where the rounding error dominates
     assert errs["ace_bf16r"] < 0.05 * errs["ace_bf16"]
+    assert errs["ace_fp16r"] < 0.05 * errs["ace_fp16"]
     ace.free()
 
 
@@ -94,13 +96,33 @@ def test_ace_complex64_io(ctx):
     ref32 = oracle.build_ace(psi32, w32)
     phi32 = phi.astype(np.complex64)
     y32 = oracle.apply_ace(ref32["xi"], phi32.astype(np.complex128))
-    for prec in ("ace_fp32r", "ace_bf16r", "ace_fp64"):
+    for prec in ("ace_fp32r", "ace_bf16r", "ace_fp16r", "ace_fp64"):
         y = ace.apply(dev(phi32), prec=prec, out_dtype=torch.complex64)
         torch.cuda.synchronize()
         assert y.dtype == torch.complex64
         err = rel_err(host(y), y32)
         say("c64 io", prec, err)
         assert err <= max(TOL[prec], 1e-5)
+    ace.free()
+
+
+def test_fp16_scaling_per_right_hand_side(ctx):
+    """FP16 operands are scaled by powers of two per right-hand side (and per column of xi^H phi):
+    right-hand sides 12 orders of magnitude apart still each meet 1e-5 against the FP64 form."""
+    import torch
+
+    n3, L3, N = (12, 12, 12), (6.0, 6.0, 6.0), 24
+    psi = synth.make_orbitals(8, n3, L3, N, ecut=1e4)
+    ace = ctx.build_ace(dev(psi), n=n3, L=L3, kernel="hse", omega=0.4, vx_prec="fp64", ace_prec="ace_fp16r")
+    phi = synth.random_grid_vectors(9, n3, 4)
+    phi *= np.array([1e-8, 1e4, 1.0, 1e-3])[:, None, None, None]
+    F = dev(phi)
+    y64 = host(ace.apply(F, prec="ace_fp64", out_dtype=torch.complex128))
+    for prec in ("ace_fp16r", "ace_bf16r", "ace_fp32r"):
+        y = host(ace.apply(F, prec=prec, out_dtype=torch.complex128))
+        err = rel_err(y, y64)
+        say("scaled right-hand sides", prec, err)
+        assert err <= TOL[prec], prec
     ace.free()
 
 

@@ -98,12 +98,12 @@ def test_ace_fullsize(share):
     ace = ctx.build_ace(P, n=n, L=L, kernel="hse", omega=0.106, vx_prec="fp32acc64", ace_prec="ace_fp64")
     ks = list(ACE_COLS)
     ys = {}
-    for prec in ("ace_fp64", "ace_fp32r", "ace_bf16r"):
+    for prec in ("ace_fp64", "ace_fp32r", "ace_bf16r", "ace_fp16r"):
         ys[prec] = host(ace.apply(P[ks], prec=prec, out_dtype=torch.complex128))
     torch.cuda.synchronize()
     for i, k in enumerate(ks):
         ref = oracle_col(share, k)
-        for prec in ("ace_fp64", "ace_fp32r", "ace_bf16r"):
+        for prec in ("ace_fp64", "ace_fp32r", "ace_bf16r", "ace_fp16r"):
             err = rel_err(ys[prec][i:i + 1], ref)
             say("K_ACE psi_k vs oracle V_X psi_k", k, prec, err)
             # the W columns come from the FP32-FFT pair path (fp32acc64), so the forms are held to 1e-5,
@@ -114,7 +114,7 @@ def test_ace_fullsize(share):
     y64 = ace.apply(phi, prec="ace_fp64", out_dtype=torch.complex128)
     r64 = host(y64)
     del y64
-    for prec in ("ace_fp32r", "ace_bf16r"):
+    for prec in ("ace_fp32r", "ace_bf16r", "ace_fp16r"):
         y = ace.apply(phi, prec=prec, out_dtype=torch.complex64)
         torch.cuda.synchronize()
         err = rel_err(host(y), r64)
