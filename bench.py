@@ -7,8 +7,11 @@ accumulation over j.  Orbitals are synthetic (seeded random planewaves below
 10 Ha, Loewdin-orthonormalised) and resident in HBM before timing starts.
 
 Prints one JSON line: pairs/s, the roofline of the dominant kernel (timed with
-HIP events on its own stream), the FP64 form on the same GPU and the FP64 CPU
-oracle on a bounded sample of the same workload.
+HIP events on its own stream), the FP64 form on the same GPU (with its own
+roofline) and the FP64 CPU oracle on a bounded sample of the same workload;
+then, as extra keys measured after the timed steps, the ACE apply at the same
+cell (N = R = 1024: ms per apply, error and matrix-core roofline of each
+precision form) and a short serving replay (p50/p99 by cell class).
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -114,6 +117,12 @@ def main():
                     help="vx: V_X apply (default); ace: ACE build + apply at 96^3, N = R = 1024; serve: serving replay")
     ap.add_argument("--requests", type=int, default=12000, help="serve leg: measured requests")
     ap.add_argument("--warm-requests", type=int, default=1000, help="serve leg: warm-up requests")
+    ap.add_argument("--extra-legs", default="ace,serve",
+                    help="vx leg, headline workload: legs run after the timed V_X steps and reported as extra keys "
+                         "(comma list of ace, serve; empty for none)")
+    ap.add_argument("--extra-ace-steps", type=int, default=2, help="timed applies per ACE precision in the extra leg")
+    ap.add_argument("--extra-requests", type=int, default=3000, help="measured requests of the extra serving replay")
+    ap.add_argument("--extra-warm-requests", type=int, default=300, help="warm-up requests of the extra serving replay")
     ap.add_argument("--serve-work-mb", type=int, default=0,
                     help="serve leg: pair work volume per V_X launch, MiB (0: the library's default)")
     args = ap.parse_args()
@@ -282,17 +291,32 @@ def main():
         kw64 = dict(kw, prec="fp64", out=out64)
         ctx.apply_vx(P64, P64[:Nt], **kw64)
         torch.cuda.synchronize()
+        ctx.prof_enable(True)
         t0 = time.perf_counter()
         for _ in range(args.fp64_steps):
             ctx.apply_vx(P64, P64[:Nt], **kw64)
         torch.cuda.synchronize()
         el64 = time.perf_counter() - t0
+        kern64 = {}
+        for name in ("vx_plane_fwd", "vx_pencil_z", "vx_plane_inv"):
+            cnt, ms, work = ctx.prof_read(fock.KERNEL_IDS[name])
+            if cnt:
+                kern64[name] = {"launches": cnt, "avg_ms": ms / cnt, "total_ms": ms,
+                                "bytes_per_launch": work / cnt, "algorithmic_GBps": work / (ms * 1e-3) / 1e9}
+        ctx.prof_enable(False)
         v64 = pairs * args.fp64_steps / el64
         ref = out64.reshape(Nt, -1)
         err = (torch.linalg.vector_norm(out.reshape(Nt, -1).to(torch.complex128) - ref, dim=1)
                / torch.linalg.vector_norm(ref, dim=1)).max().item()
         result["fp64_same_gpu"] = {"value": v64, "unit": "pairs/s", "ms_per_step": 1e3 * el64 / args.fp64_steps,
-                                   "speedup_of_value": value / v64, "max_col_rel_err_of_value_vs_fp64": err}
+                                   "speedup_of_value": value / v64, "max_col_rel_err_of_value_vs_fp64": err,
+                                   "kernels": kern64}
+        if kern64:
+            d64 = max(kern64, key=lambda k: kern64[k]["total_ms"])
+            a64 = kern64[d64]["algorithmic_GBps"]
+            # FP64 pair path: 16 bytes per complex value, the same passes and byte model
+            result["fp64_same_gpu"]["roofline"] = {"bound": "hbm", "kernel": d64, "achieved": a64,
+                                                   "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": a64 / HBM_PEAK_GBS}
         log(f"[bench] fp64 {v64:.0f} pairs/s; {args.prec} vs fp64: max column relative error {err:.2e}")
         del P64, out64
     del out
@@ -313,6 +337,30 @@ def main():
         log("[bench] CPU oracle baseline ...")
         result["cpu_baseline"] = cpu_baseline(psi_h, w, args.cpu_seconds)
     ctx.close()
+    legs = [x for x in args.extra_legs.split(",") if x] if args.workload == "96cube_1024x32" else []
+    if legs:
+        del P, phi
+        torch.cuda.empty_cache()
+    if "ace" in legs:
+        # the ACE operator at the same cell and orbitals (N = R = 1024): precision forms against FP64
+        log("[bench] extra leg: ACE apply at 96^3, N = R = 1024 ...")
+        a = ace_leg(args, max(1, args.extra_ace_steps), args.autotune,
+                    precs=("ace_fp64", "ace_fp32r", "ace_bf16r", "ace_fp16r"))
+        result["ace_apply_96cube_N1024"] = {
+            "ms_per_apply": {p: e["ms_per_apply"] for p, e in a["precisions"].items()},
+            "elem_err_vs_fp64": {p: e["max_col_elem_err_vs_fp64"] for p, e in a["precisions"].items()},
+            "gemm_roofline": {p: {g: e[g + "_roofline"] for g in ("gemm_cn", "gemm_nn") if g + "_roofline" in e}
+                              for p, e in a["precisions"].items()},
+            "build_s": a["config"]["build_s"], "steps": a["steps"]}
+    if "serve" in legs:
+        log("[bench] extra leg: serving replay ...")
+        sv = serve_leg(args, args.extra_requests, args.extra_warm_requests, args.autotune)
+        result["serve_replay"] = {"p50_ms": sv["report"]["p50_ms"], "p99_ms": sv["report"]["p99_ms"],
+                                  "req_per_s": sv["report"]["req_per_s"], "busy_frac": sv["report"]["busy_frac"],
+                                  "n_done": sv["report"]["n_done"], "n_rejected": sv["report"]["n_rejected"],
+                                  "requests": args.extra_requests, "warm_requests": args.extra_warm_requests,
+                                  "by_class": sv["by_class"], "register_s": sv["config"]["register_s"],
+                                  "workload": sv["config"]["workload"]}
     print(json.dumps(result))
 
 
@@ -454,6 +502,11 @@ MFMA_PEAK_TFLOPS = {"ace_fp32r": 157.3, "ace_fp32": 157.3, "ace_bf16r": 2500.0, 
 
 def bench_ace(args):
     """ACE at one GPU's share of the 512-atom cell: 96^3 grid, N = 1024 orbitals, R = 1024 right-hand sides."""
+    print(json.dumps(ace_leg(args, args.steps, args.autotune)))
+
+
+def ace_leg(args, steps, autotune, precs=("ace_fp64", "ace_fp32r", "ace_bf16r", "ace_fp16r", "ace_fp32", "ace_bf16",
+                                         "ace_fp16")):
     import numpy as np
     import torch
 
@@ -469,7 +522,7 @@ def bench_ace(args):
     phi = torch.from_numpy(synth.make_orbitals(3, n, L, R, dtype=np.complex64)).to("cuda:0")
     ctx = Context(0)
     tune = None
-    if args.autotune:
+    if autotune:
         t0 = time.perf_counter()
         cfg, ms_k = ctx.vx_autotune(n=n, L=L, n_psi=N, n_phi=N, phi_is_psi=True, prec="fp32acc64")
         tune = {"config": cfg, "ms_per_1000_pairs_probe": ms_k, "seconds": time.perf_counter() - t0}
@@ -491,15 +544,15 @@ def bench_ace(args):
     out = torch.empty_like(phi)
     res = {}
     ref = None
-    for prec in ("ace_fp64", "ace_fp32r", "ace_bf16r", "ace_fp16r", "ace_fp32", "ace_bf16", "ace_fp16"):
+    for prec in precs:
         ace.apply(phi, prec=prec, out=out)  # first use builds the split copies of xi
         torch.cuda.synchronize()
         ctx.prof_enable(True)
         t0 = time.perf_counter()
-        for _ in range(args.steps):
+        for _ in range(steps):
             ace.apply(phi, prec=prec, out=out)
         torch.cuda.synchronize()
-        el = (time.perf_counter() - t0) / args.steps
+        el = (time.perf_counter() - t0) / steps
         kern = {}
         for name in ("gemm_cn", "gemm_nn", "reduce", "split"):
             cnt, ms, work = ctx.prof_read(fock.KERNEL_IDS[name])
@@ -533,7 +586,7 @@ def bench_ace(args):
         "metric": "ACE apply orbital-pair equivalents/s",
         "value": N * R / (res[main_p]["ms_per_apply"] * 1e-3),
         "unit": "pairs/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "n_gpus": 1, "steps": steps, "warmup": 1,
         "ms_per_step": res[main_p]["ms_per_apply"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
@@ -546,7 +599,9 @@ def bench_ace(args):
     }
     ace.free()
     ctx.close()
-    print(json.dumps(result))
+    del psi, phi, out, ref
+    torch.cuda.empty_cache()
+    return result
 
 
 def bench_step(args):
@@ -628,6 +683,10 @@ def bench_step(args):
 
 def bench_serve(args):
     """Serving replay: Poisson arrivals (200/s) over 12 resident trajectories of three cell sizes."""
+    print(json.dumps(serve_leg(args, args.requests, args.warm_requests, args.autotune)))
+
+
+def serve_leg(args, nreq_measured, nreq_warm, autotune):
     import numpy as np
     import torch
 
@@ -638,7 +697,7 @@ def bench_serve(args):
     classes = {0: "serveA", 1: "serveB", 2: "serveC"}
     ctx = Context(0)
     srv = Server(ctx, max_slots=8, n_streams=4, max_batch_pairs=1 << 15, hbm_budget_bytes=64 << 30,
-                 autotune=args.autotune, vx_work_mb=args.serve_work_mb)
+                 autotune=autotune, vx_work_mb=args.serve_work_mb)
     by_class = {}
     t0 = time.perf_counter()
     for c, name in classes.items():
@@ -668,9 +727,9 @@ def bench_serve(args):
             r["out"] = outs[key]
         return srv.serve(reqs)
 
-    if args.warm_requests:
-        run(4, args.warm_requests)
-    st, lat, rep = run(5, args.requests)
+    if nreq_warm:
+        run(4, nreq_warm)
+    st, lat, rep = run(5, nreq_measured)
     ok = sum(1 for s in st if s == 0)
     # latency by cell class and operation (nearest-rank percentiles)
     names = {0: "24^3 N=16", 1: "48^3 N=128", 2: "72^3 N=432"}
@@ -684,7 +743,7 @@ def bench_serve(args):
                                                   "mean_ms": float(np.mean(ls))}
     result = {
         "metric": "serving p99 latency",
-        "value": rep["p99_ms"], "unit": "ms", "n_gpus": 1, "steps": args.requests, "warmup": args.warm_requests,
+        "value": rep["p99_ms"], "unit": "ms", "n_gpus": 1, "steps": nreq_measured, "warmup": nreq_warm,
         "ms_per_step": rep["mean_ms"], "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": "Poisson 200 req/s; 50/35/15% classes 24^3 N=16, 48^3 N=128, 72^3 N=432; "
@@ -694,7 +753,8 @@ def bench_serve(args):
     }
     srv.close()
     ctx.close()
-    print(json.dumps(result))
+    torch.cuda.empty_cache()
+    return result
 
 
 if __name__ == "__main__":
