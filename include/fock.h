@@ -368,10 +368,18 @@ fx_status fx_density(fx_ctx* ctx, const void* psi, int32_t n, int64_t ld, int64_
  * fx_serve_create: batches run on n_streams streams, at most one per stream at
  *   a time (a batch waits in the host queue rather than behind another
  *   stream's batch); max_slots bounds the workspaces kept for them (slot i
- *   uses stream i mod n_streams); same-grid requests that are waiting are
- *   merged into one launch of up to max_batch_pairs pairs; admission keeps the
- *   memory of resident trajectories plus in-flight requests within
- *   hbm_budget_bytes (0 = the context budget).
+ *   uses stream i mod n_streams).  Waiting requests of one operation are
+ *   merged into one launch of up to max_batch_pairs pairs: K_ACE requests of
+ *   one trajectory; V_X requests of up to eight trajectories that share the
+ *   grid (edge 24, 48, 72 or 96), cell lengths, kernel, orbital count, dtype
+ *   and precision (orbitals in the compute type), each target paired with
+ *   its own trajectory's orbitals (V_X requests on other grids merge within
+ *   their trajectory).  Results do not depend on the merge.  Admission keeps
+ *   the memory of resident trajectories plus in-flight requests within
+ *   hbm_budget_bytes (0 = the context budget): a batch that cannot fit even
+ *   with every slot idle is refused with FX_ERR_OOM; an arrival that finds
+ *   max_queue requests already waiting is refused with FX_ERR_BUSY (0 = no
+ *   limit).
  * fx_serve_register: copy psi (N_r x n, dtype) into library-owned resident
  *   memory as trajectory `traj`, and build its ACE factors (ace_prec).
  * fx_serve: replay `n_reqs` requests whose arrival times (seconds from the
@@ -380,7 +388,16 @@ fx_status fx_density(fx_ctx* ctx, const void* psi, int32_t n, int64_t ld, int64_
  *   its `out` (device, ld_out, dtype of the trajectory).  Returns when every
  *   request has finished; per_req_status/per_req_latency_ms (nullable host
  *   arrays of n_reqs) receive each request's status and latency (completion
- *   time minus arrival time), and report the aggregate.
+ *   time minus arrival time), and report the aggregate.  Statuses: FX_OK,
+ *   FX_ERR_INVALID (unknown trajectory or operation, orbitals out of range,
+ *   NULL out), FX_ERR_OOM, FX_ERR_BUSY, FX_ERR_CANCELLED (cancelled, or not
+ *   reached because the loop stopped on a device error).
+ * fx_serve_cancel: cancel request `request` (an index into the request array
+ *   of the fx_serve call running on this server, or of the next call if none
+ *   is running); callable from another thread while fx_serve runs.  A
+ *   request not yet dispatched is dropped with FX_ERR_CANCELLED; one already
+ *   on the device completes normally.  Cancellations are forgotten when
+ *   fx_serve returns.
  */
 typedef struct fx_serve_cfg {
   int32_t max_slots;
@@ -394,6 +411,7 @@ typedef struct fx_serve_cfg {
   int32_t autotune_targets; /* targets per V_X request the tuning assumes (0 = 8) */
   int32_t vx_work_mb;  /* pair work volume per launch of a served V_X batch, MiB (0 = 1024):
                           short launches let requests on other streams interleave */
+  int32_t max_queue;   /* waiting requests beyond which arrivals get FX_ERR_BUSY (0 = no limit) */
 } fx_serve_cfg;
 
 typedef struct fx_request {
@@ -409,8 +427,9 @@ typedef struct fx_request {
 typedef struct fx_serve_report {
   double p50_ms, p99_ms, mean_ms, max_ms;
   double req_per_s, pairs_per_s, busy_frac, wall_s;
-  int64_t n_done, n_rejected, n_batches;
+  int64_t n_done, n_rejected, n_batches; /* n_rejected: FX_ERR_OOM and FX_ERR_BUSY */
   size_t hbm_peak_bytes;
+  int64_t n_cancelled;
 } fx_serve_report;
 
 fx_status fx_serve_create(fx_ctx* ctx, const fx_serve_cfg* cfg, fx_server** srv);
@@ -419,6 +438,7 @@ fx_status fx_serve_register(fx_server* srv, int32_t traj, const fx_cell* cell, c
                             fx_prec vx_prec, fx_prec ace_prec);
 fx_status fx_serve(fx_server* srv, const fx_request* reqs, int32_t n_reqs,
                    fx_status* per_req_status, double* per_req_latency_ms, fx_serve_report* report);
+fx_status fx_serve_cancel(fx_server* srv, int32_t request);
 /* Release a server: its resident orbitals, ACE factors, workspaces and streams
  * (after waiting for the device), and the context budget it capped.  Valid
  * before or after fx_finalize of its context. */

@@ -1,17 +1,24 @@
 // fx_serve: continuous batching of V_X and K_ACE requests over orbitals kept
 // resident on the device (the host scheduling is in serve_sched.hpp).
 //
-// One host loop replays the arrivals.  Waiting requests of the same
-// trajectory and operation are merged into one launch (their target orbitals
-// gathered into one block) up to max_batch_pairs pairs; a merged batch runs
-// on a free slot, each slot owning a stream and a workspace, so batches that
-// are in flight overlap on the device.  A slot's completion event stamps the
-// latency of every request in it.  Admission keeps resident orbitals, ACE
-// factors and slot workspaces inside the HBM budget: a batch whose workspace
-// does not fit waits for a slot to drain, and is refused (FX_ERR_OOM) only if
-// it cannot fit with every slot idle.
+// One host loop replays the arrivals.  Waiting requests of one operation are
+// merged into one launch (their target orbitals gathered into one block) up
+// to max_batch_pairs pairs: ACE requests of one trajectory; V_X requests of
+// up to eight trajectories that share the grid, kernel, orbital count and
+// precision (on the specialised grids), each target paired with its own
+// trajectory's orbitals.  A merged batch runs on a free slot, each slot
+// owning a stream and a workspace, so batches that are in flight overlap on
+// the device.  A slot's completion event stamps the latency of every request
+// in it.  Admission keeps resident orbitals, ACE factors and slot workspaces
+// inside the HBM budget: a batch whose workspace does not fit waits for a
+// slot to drain, and is refused (FX_ERR_OOM) only if it cannot fit with every
+// slot idle; an arrival that finds max_queue requests waiting is refused
+// (FX_ERR_BUSY); fx_serve_cancel drops a request that has not started.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
+#include <mutex>
+#include <set>
 #include <cmath>
 #include <deque>
 #include <map>
@@ -36,6 +43,7 @@ struct Traj {
   void* psi = nullptr;  // owned, ld nr
   size_t psi_bytes = 0;
   fx_ace* ace = nullptr;
+  int vx_class = 0;  // V_X requests of trajectories with the same class may share a launch
 };
 
 struct Slot {
@@ -81,6 +89,11 @@ struct fx_server {
   size_t saved_budget = 0;  // the context budget before the server capped it
   std::map<int, Traj> trajs;
   std::vector<Slot> slots;
+  // requests of the running (or next) fx_serve call cancelled by
+  // fx_serve_cancel, which takes only this lock (fx_serve holds the context's)
+  std::mutex cancel_mu;
+  std::set<int> cancelled;
+  std::atomic<int> n_cancelled{0};
 };
 
 static double now_s() {
@@ -148,8 +161,23 @@ struct HipExec final : ServeExecutor {
   int n_slots() const override { return (int)srv->slots.size(); }
   int stream_of(int slot) const override { return stream_id[slot]; }
   int orbitals(int traj) const override { return srv->trajs.at(traj).n; }
-  fx_status launch(int slot, const std::vector<int>& batch) override {
+  int merge_class(int traj, int op) const override { return op == 0 ? srv->trajs.at(traj).vx_class : traj; }
+  bool cancelled(int req) const override {
+    if (srv->n_cancelled.load(std::memory_order_acquire) == 0) return false;
+    std::lock_guard<std::mutex> lk(srv->cancel_mu);
+    return srv->cancelled.count(req) != 0;
+  }
+  fx_status launch(int slot, const std::vector<int>& batch_in) override {
     Slot& sl = srv->slots[slot];
+    // the batch's requests grouped by trajectory (first appearance first), each
+    // trajectory's requests in batch order: the targets of one trajectory are
+    // contiguous in the gathered block
+    std::vector<int> trajs_in, batch;
+    for (int i : batch_in)
+      if (std::find(trajs_in.begin(), trajs_in.end(), reqs[i].traj) == trajs_in.end()) trajs_in.push_back(reqs[i].traj);
+    for (int tj : trajs_in)
+      for (int i : batch_in)
+        if (reqs[i].traj == tj) batch.push_back(i);
     const fx_request& r0 = reqs[batch[0]];
     Traj& t = srv->trajs[r0.traj];
     const size_t esz = dtype_size(t.dtype);
@@ -159,6 +187,20 @@ struct HipExec final : ServeExecutor {
     const void* phi = nullptr;
     void* out = nullptr;
     const bool single = batch.size() == 1;
+    TrajSegs segs;
+    if (trajs_in.size() > 1) {
+      if ((int)trajs_in.size() > kMaxTrajSegs) FX_FAIL(FX_ERR_INVALID, "batch over %d trajectories", kMaxTrajSegs);
+      int off = 0;
+      for (int i : batch) {
+        if (segs.n == 0 || srv->trajs[reqs[i].traj].psi != segs.psi[segs.n - 1]) {
+          segs.start[segs.n] = off;
+          segs.psi[segs.n] = srv->trajs[reqs[i].traj].psi;
+          ++segs.n;
+        }
+        off += reqs[i].count;
+      }
+      segs.start[segs.n] = off;
+    }
     if (single) {
       phi = (const char*)t.psi + (int64_t)r0.first * cb;
       out = r0.out;
@@ -168,7 +210,8 @@ struct HipExec final : ServeExecutor {
       FX_TRY(ws_get(ctx, &sl.ws, "srv_out", (size_t)cb * total, &o));
       int off = 0;
       for (int i : batch) {
-        FX_TRY(copy_cols((const char*)t.psi + (int64_t)reqs[i].first * cb, cb, (char*)g + (int64_t)off * cb, cb, cb,
+        const Traj& ti = srv->trajs[reqs[i].traj];
+        FX_TRY(copy_cols((const char*)ti.psi + (int64_t)reqs[i].first * cb, cb, (char*)g + (int64_t)off * cb, cb, cb,
                          reqs[i].count, sl.st));
         off += reqs[i].count;
       }
@@ -178,6 +221,7 @@ struct HipExec final : ServeExecutor {
     const int64_t ld_out = single ? r0.ld_out : t.nr;
     if (r0.op == 0) {
       VxArgs va;
+      va.segs = segs;
       va.cell = &t.cell;
       va.kern = &t.kern;
       va.psi = t.psi;
@@ -239,6 +283,7 @@ fx_status fx_serve_create(fx_ctx* ctx, const fx_serve_cfg* cfg, fx_server** srv)
   if (cfg->n_streams <= 0 || cfg->n_streams > cfg->max_slots)
     FX_FAIL(FX_ERR_INVALID, "n_streams = %d not in [1, max_slots]", cfg->n_streams);
   if (cfg->max_batch_pairs <= 0) FX_FAIL(FX_ERR_INVALID, "max_batch_pairs must be positive");
+  if (cfg->max_queue < 0) FX_FAIL(FX_ERR_INVALID, "max_queue = %d must be >= 0", cfg->max_queue);
   std::lock_guard<std::recursive_mutex> lk(ctx->mu);
   FX_HIP(hipSetDevice(ctx->device));
   fx_server* s = new fx_server();
@@ -324,6 +369,23 @@ fx_status fx_serve_register(fx_server* srv, int32_t traj, const fx_cell* cell, c
   // the build's scratch is not needed while serving
   FX_HIP(hipDeviceSynchronize());
   ws_release(ctx, &ctx->ws);
+  // V_X requests may share launches with those of trajectories that pair the
+  // same way: same grid (specialised kernels), cell, kernel, orbital count,
+  // dtype and precision, with no conversion of the orbitals
+  t.vx_class = traj;
+  const bool conv = (dtype == FX_C128) != (vx_prec == FX_PREC_FP64);
+  if (ct_supported(cell) && !conv) {
+    for (const auto& kv : srv->trajs) {
+      const Traj& u = kv.second;
+      bool same = u.n == t.n && u.dtype == t.dtype && u.vx_prec == t.vx_prec && u.kern.kind == t.kern.kind &&
+                  u.kern.scale == t.kern.scale && (t.kern.kind != FX_HSE || u.kern.omega == t.kern.omega);
+      for (int a = 0; a < 3; ++a) same = same && u.cell.n[a] == t.cell.n[a] && u.cell.len[a] == t.cell.len[a];
+      if (same && ct_supported(&u.cell)) {
+        t.vx_class = u.vx_class;
+        break;
+      }
+    }
+  }
   srv->trajs[traj] = t;
   return FX_OK;
 }
@@ -349,7 +411,13 @@ fx_status fx_serve(fx_server* srv, const fx_request* reqs, int32_t n_reqs, fx_st
   }
   HipExec ex(srv, reqs);
   ServeOutcome o;
-  serve_schedule(ex, reqs, nq, valid, srv->cfg.max_batch_pairs, &o);
+  serve_schedule(ex, reqs, nq, valid, srv->cfg.max_batch_pairs, &o, srv->cfg.max_queue);
+  {
+    // cancellations refer to this call's requests only
+    std::lock_guard<std::mutex> lk(srv->cancel_mu);
+    srv->cancelled.clear();
+    srv->n_cancelled.store(0, std::memory_order_release);
+  }
   if (o.fatal != FX_OK) {
     (void)hipDeviceSynchronize();
     return o.fatal;
@@ -379,7 +447,18 @@ fx_status fx_serve(fx_server* srv, const fx_request* reqs, int32_t n_reqs, fx_st
     R.n_rejected = o.rejected;
     R.n_batches = o.batches;
     R.hbm_peak_bytes = o.hbm_peak;
+    R.n_cancelled = o.cancelled;
   }
+  return FX_OK;
+}
+
+fx_status fx_serve_cancel(fx_server* srv, int32_t request) {
+  clear_error();
+  if (!srv) FX_FAIL(FX_ERR_INVALID, "srv is NULL");
+  if (request < 0) FX_FAIL(FX_ERR_INVALID, "request index %d is negative", request);
+  std::lock_guard<std::mutex> lk(srv->cancel_mu);
+  srv->cancelled.insert(request);
+  srv->n_cancelled.fetch_add(1, std::memory_order_release);
   return FX_OK;
 }
 

@@ -1,15 +1,20 @@
 // Host scheduling of the serving loop, separate from the device work so that
 // it can be built and tested on a CPU with a simulated executor.
 //
-// The loop replays arrivals in time order.  Waiting requests are dispatched
-// oldest first; a dispatch merges the oldest waiting request with later ones of
-// the same trajectory and operation, in arrival order, while the batch stays
-// within max_batch_pairs pairs (pairs = orbitals of the trajectory x targets).
-// A batch goes to an idle slot whose stream has nothing running.  If its
-// workspace does not fit, the idle slots hand back their workspaces and the
-// launch is tried once more; if it still does not fit it waits for a running
-// batch to finish, or is refused (FX_ERR_OOM) when nothing is running.  A
-// request's latency runs from its arrival to the completion of its batch.
+// The loop replays arrivals in time order.  An arrival that finds max_queue
+// requests already waiting is refused (FX_ERR_BUSY); a request the caller has
+// cancelled before it was dispatched is dropped (FX_ERR_CANCELLED).  Waiting
+// requests are dispatched oldest first; a dispatch merges the oldest waiting
+// request with later ones of the same operation and merge class (requests
+// that can share one launch: for V_X, trajectories on the same grid with the
+// same kernel, orbital count and precision; otherwise one trajectory), in
+// arrival order, from at most kServeMaxTrajs trajectories, while the batch
+// stays within max_batch_pairs pairs (pairs = orbitals x targets).  A batch
+// goes to an idle slot whose stream has nothing running.  If its workspace
+// does not fit, the idle slots hand back their workspaces and the launch is
+// tried once more; if it still does not fit it waits for a running batch to
+// finish, or is refused (FX_ERR_OOM) when nothing is running.  A request's
+// latency runs from its arrival to the completion of its batch.
 #pragma once
 
 #include <algorithm>
@@ -23,6 +28,10 @@
 
 namespace fx {
 
+// Trajectories one merged launch may draw on (the pass kernels take a table of
+// this many orbital blocks).
+constexpr int kServeMaxTrajs = 8;
+
 // What the scheduler needs from the device side.
 struct ServeExecutor {
   virtual ~ServeExecutor() = default;
@@ -31,6 +40,17 @@ struct ServeExecutor {
   virtual int stream_of(int slot) const = 0;
   // orbitals of a trajectory (a request of `count` targets is orbitals x count pairs)
   virtual int orbitals(int traj) const = 0;
+  // requests of one operation whose trajectories have the same class may share
+  // a launch (the trajectory itself: never merged with other trajectories)
+  virtual int merge_class(int traj, int op) const {
+    (void)op;
+    return traj;
+  }
+  // the caller has cancelled request `req` (checked before it is dispatched)
+  virtual bool cancelled(int req) const {
+    (void)req;
+    return false;
+  }
   // enqueue `batch` (request indices, merged in this order) on `slot`:
   // FX_OK, FX_ERR_OOM if its workspace does not fit now, or another error
   virtual fx_status launch(int slot, const std::vector<int>& batch) = 0;
@@ -47,9 +67,12 @@ struct ServeExecutor {
 };
 
 struct ServeOutcome {
-  std::vector<fx_status> status;  // per request: FX_OK, FX_ERR_INVALID, FX_ERR_OOM, FX_ERR_CANCELLED
+  // per request: FX_OK, FX_ERR_INVALID, FX_ERR_OOM, FX_ERR_BUSY, or
+  // FX_ERR_CANCELLED (cancelled by the caller, or never reached because the
+  // loop ended on an error)
+  std::vector<fx_status> status;
   std::vector<double> lat_ms;     // per request, -1 when not served
-  int64_t done = 0, rejected = 0, batches = 0;
+  int64_t done = 0, rejected = 0, cancelled = 0, batches = 0;
   double pairs_done = 0.0, busy_time = 0.0, wall = 0.0;
   size_t hbm_peak = 0;
   fx_status fatal = FX_OK;  // a device error or a launch failure other than FX_ERR_OOM
@@ -66,24 +89,28 @@ inline double serve_percentile(std::vector<double> v, double q) {
 }
 
 // The merge of one dispatch: the oldest waiting request, then later waiting
-// requests of the same trajectory and operation in arrival order while the
-// pairs stay within max_pairs (the first request that would exceed it ends
-// the merge).
+// requests of the same operation and merge class in arrival order, from at
+// most kServeMaxTrajs trajectories, while the pairs stay within max_pairs (the
+// first request that would exceed it ends the merge).
 inline std::vector<int> serve_merge(const std::deque<int>& waiting, const fx_request* reqs, const ServeExecutor& ex,
                                     int64_t max_pairs) {
   std::vector<int> batch;
   if (waiting.empty()) return batch;
   const int head = waiting.front();
   const fx_request& rh = reqs[head];
-  const int64_t n = ex.orbitals(rh.traj);
+  const int cls = ex.merge_class(rh.traj, rh.op);
+  std::vector<int> trajs{rh.traj};
   batch.push_back(head);
-  int64_t pairs = n * rh.count;
+  int64_t pairs = (int64_t)ex.orbitals(rh.traj) * rh.count;
   for (size_t w = 1; w < waiting.size(); ++w) {
     const fx_request& rw = reqs[waiting[w]];
-    if (rw.traj != rh.traj || rw.op != rh.op) continue;
-    const int64_t p = n * rw.count;
+    if (rw.op != rh.op || ex.merge_class(rw.traj, rw.op) != cls) continue;
+    const bool new_traj = std::find(trajs.begin(), trajs.end(), rw.traj) == trajs.end();
+    if (new_traj && (int)trajs.size() >= kServeMaxTrajs) continue;
+    const int64_t p = (int64_t)ex.orbitals(rw.traj) * rw.count;
     if (pairs + p > max_pairs) break;
     batch.push_back(waiting[w]);
+    if (new_traj) trajs.push_back(rw.traj);
     pairs += p;
   }
   return batch;
@@ -92,7 +119,7 @@ inline std::vector<int> serve_merge(const std::deque<int>& waiting, const fx_req
 // Run the loop over nq requests; valid[i] == 0 marks a request the caller has
 // rejected (its status stays FX_ERR_INVALID).
 inline void serve_schedule(ServeExecutor& ex, const fx_request* reqs, int nq, const std::vector<char>& valid,
-                           int64_t max_batch_pairs, ServeOutcome* out) {
+                           int64_t max_batch_pairs, ServeOutcome* out, int64_t max_queue = 0) {
   ServeOutcome& o = *out;
   o = ServeOutcome();
   o.status.assign(nq, FX_ERR_CANCELLED);
@@ -136,11 +163,33 @@ inline void serve_schedule(ServeExecutor& ex, const fx_request* reqs, int nq, co
     }
   };
 
-  while (o.done + o.rejected < n_valid || !waiting.empty() || nbusy) {
+  while (o.done + o.rejected + o.cancelled < n_valid || !waiting.empty() || nbusy) {
     const double t = ex.now() - t0;
     while (next < (size_t)nq && reqs[order[next]].t_arrival_s <= t) {
-      if (valid[order[next]]) waiting.push_back(order[next]);
-      ++next;
+      const int i = order[next++];
+      if (!valid[i]) continue;
+      if (ex.cancelled(i)) {
+        o.status[i] = FX_ERR_CANCELLED;
+        ++o.cancelled;
+      } else if (max_queue > 0 && (int64_t)waiting.size() >= max_queue) {
+        o.status[i] = FX_ERR_BUSY;  // admission control: the queue is full
+        ++o.rejected;
+      } else {
+        waiting.push_back(i);
+      }
+    }
+    // waiting requests cancelled since they arrived leave the queue
+    if (!waiting.empty()) {
+      std::deque<int> keep;
+      for (int w : waiting) {
+        if (ex.cancelled(w)) {
+          o.status[w] = FX_ERR_CANCELLED;
+          ++o.cancelled;
+        } else {
+          keep.push_back(w);
+        }
+      }
+      waiting.swap(keep);
     }
     for (int s = 0; s < ns; ++s) {
       if (!busy[s]) continue;

@@ -502,6 +502,8 @@ static fx_status run_batches(fx_ctx* ctx, Workspace* ws, const VxArgs& a, const 
   if (a.kernels == 1 && !use_ct)
     FX_FAIL(FX_ERR_UNSUPPORTED, "no specialised kernels for grid %dx%dx%d with this radix schedule", g.nx, g.ny,
             g.nz);
+  if (a.segs.n > 0 && (!use_ct || psi == phi))
+    FX_FAIL(FX_ERR_UNSUPPORTED, "multi-trajectory launches need the specialised kernels and phi != psi");
   if (use_ct && a.halve != 0 && psi == phi && ld_psi == ld_phi && a.n_psi == a.n_phi)
     return run_halved<T, A>(ctx, ws, a, tb, psi, ld_psi, pairs_cap, st, stats);
   // Batch shape: up to 16 orbitals per batch first (the plane-inverse pass
@@ -569,7 +571,7 @@ static fx_status run_batches(fx_ctx* ctx, Workspace* ws, const VxArgs& a, const 
       int slot;
       if (use_ct) {
         CtBatch<T> cb{psi, ld_psi, phi, ld_phi, reinterpret_cast<cpx<T>*>(work), j0, jb, k0, kb, npairs, twx, kf,
-                      tb->fold[0], 0, a.a_pipe > 0 ? 1 : 0, ct_b_variant(a), ct_c_variant(a), a.a_var == 2 ? 2 : 1, a.nt_hint != 0 ? 1 : 0, ct_zsplit()};
+                      tb->fold[0], 0, a.a_pipe > 0 ? 1 : 0, ct_b_variant(a), ct_c_variant(a), a.a_var == 2 ? 2 : 1, a.nt_hint != 0 ? 1 : 0, ct_zsplit(), a.segs};
         CtAcc<A> ca{acc, ld_acc, first, a.out, a.ld_out, out_c64 ? 1 : 0, last, a.pipe};
         FX_TRY(prof_begin(ctx, st, FX_K_VX_PLANE_FWD, 2.0 * vol, &slot));
         FX_TRY(ct_pass_a<T>(ctx, st, g.nx, cb));
@@ -745,6 +747,8 @@ fx_status vx_apply(fx_ctx* ctx, Workspace* ws, const VxArgs& a_in, hipStream_t s
   const bool need_conv = (a.in_dtype == FX_C128) != t64;
   const GridTables* tb = nullptr;
   GridTables tb_scratch;
+  if (a.segs.n > 0 && need_conv)
+    FX_FAIL(FX_ERR_UNSUPPORTED, "multi-trajectory launches take orbitals in the compute type");
   if (a.no_alloc) {
     if (!ws->arena) FX_FAIL(FX_ERR_INVALID, "allocation-free call without a scratch region");
     if (need_conv)

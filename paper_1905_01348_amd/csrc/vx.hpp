@@ -6,6 +6,28 @@
 
 namespace fx {
 
+// Orbital blocks of a multi-trajectory launch (served V_X requests of several
+// trajectories on one grid): targets [start[s], start[s+1]) of the launch
+// pair with the n_psi orbitals at psi[s] (same count and stride for every
+// block).  n == 0: one block, the launch's psi.
+constexpr int kMaxTrajSegs = 8;
+struct TrajSegs {
+  int n = 0;
+  int start[kMaxTrajSegs + 1] = {0};
+  const void* psi[kMaxTrajSegs] = {nullptr};
+};
+
+// The orbital block of target k (device and host).
+template <typename T>
+__host__ __device__ inline const cpx<T>* seg_psi(const TrajSegs& s, const cpx<T>* dflt, int k) {
+  if (s.n == 0) return dflt;
+  int g = 0;
+#pragma unroll
+  for (int i = 1; i < kMaxTrajSegs; ++i)
+    if (i < s.n && k >= s.start[i]) g = i;
+  return reinterpret_cast<const cpx<T>*>(s.psi[g]);
+}
+
 struct VxArgs {
   const fx_cell* cell = nullptr;
   const fx_kernel* kern = nullptr;
@@ -39,6 +61,9 @@ struct VxArgs {
   int nt_hint = -1;  // specialised kernels: non-temporal hints on the pair volume (1, 0, -1 automatic = 1)
   bool plans_set = false;  // generic kernels: radix schedules in `plans`
   PlanSet plans;
+  // several trajectories' orbital blocks (specialised kernels, phi != psi);
+  // psi is then the first block's
+  TrajSegs segs;
   // allocation-free form: `ws` carves from a fixed scratch region, the grid
   // tables are built there on the device, no conversion, no pair halving
   bool no_alloc = false;
@@ -85,6 +110,7 @@ struct CtBatch {
   int a_var;        // plane-forward pass: 1 default threads, 2 the second thread count
   int nts;          // the pair volume is read and written with non-temporal hints
   int zsplit = 0;   // plane passes split over the XCDs by z (bit 0: forward, bit 1: inverse) or by unit
+  TrajSegs segs;    // per-target orbital blocks (multi-trajectory launches; n == 0: psi for all)
 };
 template <typename A>
 struct CtAcc {

@@ -95,7 +95,7 @@ __global__ void __launch_bounds__(NT, (PassAWaves<T, PIPE, NT>::value)) k_pass_a
                                                                   const cpx<T>* __restrict__ phi, int64_t ld_phi,
                                                                   cpx<T>* __restrict__ work, int j0, int nj, int k0,
                                                                   int tri, int nitems, const cpx<T>* __restrict__ twg,
-                                                                  int zsplit) {
+                                                                  int zsplit, TrajSegs segs) {
   constexpr int NXY = N * N, SX = N + 1, EPT = CeilDiv<NXY, NT>::value;
   constexpr size_t NR = (size_t)NXY * N;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -111,7 +111,7 @@ __global__ void __launch_bounds__(NT, (PassAWaves<T, PIPE, NT>::value)) k_pass_a
     im.at(li, &p, &z);
     int jj, kk;
     pair_of(p, nj, tri, &jj, &kk);
-    const cpx<T>* a = psi + (int64_t)(j0 + jj) * ld_psi + (size_t)z * NXY;
+    const cpx<T>* a = seg_psi<T>(segs, psi, k0 + kk) + (int64_t)(j0 + jj) * ld_psi + (size_t)z * NXY;
     const cpx<T>* b = phi + (int64_t)(k0 + kk) * ld_phi + (size_t)z * NXY;
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
@@ -334,7 +334,7 @@ __global__ void __launch_bounds__(NT) k_pass_c_ct(const cpx<T>* __restrict__ mul
                                                                   int tri, int m0, int t0, int nitems, cpx<A>* acc,
                                                                   int64_t ld_acc, int first, void* out, int64_t ld_out,
                                                                   int out_c64, int last, const cpx<T>* __restrict__ twg,
-                                                                  int zsplit) {
+                                                                  int zsplit, TrajSegs segs) {
   constexpr int NXY = N * N, SX = N + 1, EPT = CeilDiv<NXY, NT>::value;
   constexpr size_t NR = (size_t)NXY * N;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -375,7 +375,8 @@ __global__ void __launch_bounds__(NT) k_pass_c_ct(const cpx<T>* __restrict__ mul
     int lo, hi;
     range(tt, &lo, &hi);
     for (int l = lo; l < hi; ++l) {
-      const cpx<T>* pm = mult + (int64_t)(m0 + l) * ld_mult + (size_t)z * NXY;
+      // (multi-trajectory launches are never halved: role 0, target t's own orbitals)
+      const cpx<T>* pm = seg_psi<T>(segs, mult, t) + (int64_t)(m0 + l) * ld_mult + (size_t)z * NXY;
       if (STG) {
         if (!staged) plane_to_lds<T, N, NT, NTS>(plane_ptr(tt, l, z), stg, tid);
         __builtin_amdgcn_s_waitcnt(0);  // this wave's part of the copy has landed
@@ -509,7 +510,7 @@ static fx_status pass_a_shape(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b) 
   int grid = 0;
   FX_TRY(ct_prepare(ctx, kern, NT, lds, items, true, &grid));
   hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, st, b.psi, b.ld_psi, b.phi, b.ld_phi, b.work, b.j0, b.nj, b.k0,
-                     b.tri, items, b.tw, b.zsplit & 1);
+                     b.tri, items, b.tw, b.zsplit & 1, b.segs);
   FX_LAUNCH_CHECK();
   return FX_OK;
 }
@@ -591,10 +592,12 @@ static fx_status pass_c_shape(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b, 
   FX_TRY(ct_prepare(ctx, kern, NT, lds, items, true, &grid));
   if (role)
     hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, st, b.phi, b.ld_phi, (const cpx<T>*)b.work, b.nj, b.nk, b.tri,
-                       b.k0, b.j0, items, c.acc, c.ld_acc, c.first, c.out, c.ld_out, c.out_c64, c.last, b.tw, (b.zsplit >> 1) & 1);
+                       b.k0, b.j0, items, c.acc, c.ld_acc, c.first, c.out, c.ld_out, c.out_c64, c.last, b.tw, (b.zsplit >> 1) & 1,
+                       TrajSegs{});
   else
     hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, st, b.psi, b.ld_psi, (const cpx<T>*)b.work, b.nj, b.nk, b.tri,
-                       b.j0, b.k0, items, c.acc, c.ld_acc, c.first, c.out, c.ld_out, c.out_c64, c.last, b.tw, (b.zsplit >> 1) & 1);
+                       b.j0, b.k0, items, c.acc, c.ld_acc, c.first, c.out, c.ld_out, c.out_c64, c.last, b.tw, (b.zsplit >> 1) & 1,
+                       b.segs);
   FX_LAUNCH_CHECK();
   return FX_OK;
 }

@@ -46,7 +46,7 @@ class FxKernel(C.Structure):
 class FxServeCfg(C.Structure):
     _fields_ = [("max_slots", C.c_int32), ("n_streams", C.c_int32), ("max_batch_pairs", C.c_int32),
                 ("hbm_budget_bytes", C.c_size_t), ("autotune", C.c_int32), ("autotune_targets", C.c_int32),
-                ("vx_work_mb", C.c_int32)]
+                ("vx_work_mb", C.c_int32), ("max_queue", C.c_int32)]
 
 
 class FxRequest(C.Structure):
@@ -58,7 +58,7 @@ class FxServeReport(C.Structure):
     _fields_ = [("p50_ms", C.c_double), ("p99_ms", C.c_double), ("mean_ms", C.c_double), ("max_ms", C.c_double),
                 ("req_per_s", C.c_double), ("pairs_per_s", C.c_double), ("busy_frac", C.c_double),
                 ("wall_s", C.c_double), ("n_done", C.c_int64), ("n_rejected", C.c_int64),
-                ("n_batches", C.c_int64), ("hbm_peak_bytes", C.c_size_t)]
+                ("n_batches", C.c_int64), ("hbm_peak_bytes", C.c_size_t), ("n_cancelled", C.c_int64)]
 
 
 class FxVxConfig(C.Structure):
@@ -114,6 +114,7 @@ _SIGS = {
     "fx_serve": (C.c_int, [C.c_void_p, C.POINTER(FxRequest), C.c_int32, C.POINTER(C.c_int),
                            C.POINTER(C.c_double), C.POINTER(FxServeReport)]),
     "fx_serve_destroy": (C.c_int, [C.c_void_p]),
+    "fx_serve_cancel": (C.c_int, [C.c_void_p, C.c_int32]),
     "fx_prof_enable": (C.c_int, [C.c_void_p, C.c_int]),
     "fx_prof_read": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                C.POINTER(C.c_double)]),
@@ -496,12 +497,13 @@ class Server:
     """Continuous-batching server over resident trajectories (fx_serve_*)."""
 
     def __init__(self, ctx, max_slots=8, n_streams=4, max_batch_pairs=1 << 16, hbm_budget_bytes=0, autotune=False,
-                 autotune_targets=8, vx_work_mb=0):
+                 autotune_targets=8, vx_work_mb=0, max_queue=0):
         cfg = FxServeCfg()
         cfg.max_slots, cfg.n_streams, cfg.max_batch_pairs = int(max_slots), int(n_streams), int(max_batch_pairs)
         cfg.hbm_budget_bytes = int(hbm_budget_bytes)
         cfg.autotune, cfg.autotune_targets = (1 if autotune else 0), int(autotune_targets)
         cfg.vx_work_mb = int(vx_work_mb)
+        cfg.max_queue = int(max_queue)
         h = C.c_void_p()
         _check(load().fx_serve_create(ctx.h, C.byref(cfg), C.byref(h)))
         self.ctx, self.h = ctx, h
@@ -545,6 +547,10 @@ class Server:
         _check(load().fx_serve(self.h, arr, n, st, lat, C.byref(rep)))
         report = {f: getattr(rep, f) for f, _ in FxServeReport._fields_}
         return [st[i] for i in range(n)], [lat[i] for i in range(n)], report
+
+    def cancel(self, index):
+        """Cancel request `index` of the running (or next) serve call; thread-safe."""
+        _check(load().fx_serve_cancel(self.h, int(index)))
 
     def close(self):
         if self.h:

@@ -36,6 +36,8 @@ struct Launch {
 struct FakeExec final : ServeExecutor {
   int ns, nstreams;
   std::map<int, int> norb;         // trajectory -> orbitals
+  std::map<int, int> cls;          // trajectory -> merge class of its V_X requests (none: the trajectory)
+  std::set<int> cancel;            // requests the caller has cancelled
   double c0 = 1e-4, c1 = 2e-8;     // service time = c0 + c1 * pairs (seconds)
   size_t bytes_per_pair = 1000, budget = (size_t)1 << 40, in_use = 0;
   std::vector<size_t> ws;          // workspace held by each slot
@@ -52,6 +54,11 @@ struct FakeExec final : ServeExecutor {
   int n_slots() const override { return ns; }
   int stream_of(int s) const override { return s % nstreams; }
   int orbitals(int traj) const override { return norb.at(traj); }
+  int merge_class(int traj, int op) const override {
+    auto it = cls.find(traj);
+    return op == 0 && it != cls.end() ? it->second : traj;
+  }
+  bool cancelled(int req) const override { return cancel.count(req) != 0; }
   int64_t pairs_of(const std::vector<int>& b) const {
     int64_t p = 0;
     for (int i : b) p += (int64_t)norb.at(reqs[i].traj) * reqs[i].count;
@@ -124,10 +131,13 @@ static void check_log(const FakeExec& ex, const std::vector<fx_request>& reqs, c
   for (const Launch& l : ex.log) {
     const fx_request& h = reqs[l.batch[0]];
     int64_t pairs = 0;
+    std::set<int> trajs;
     for (size_t k = 0; k < l.batch.size(); ++k) {
       const fx_request& r = reqs[l.batch[k]];
       ++seen[l.batch[k]];
-      CHECK(r.traj == h.traj && r.op == h.op, "%s: batch mixes trajectories or operations", what);
+      trajs.insert(r.traj);
+      CHECK(r.op == h.op && ex.merge_class(r.traj, r.op) == ex.merge_class(h.traj, h.op),
+            "%s: batch mixes operations or merge classes", what);
       CHECK(r.t_arrival_s <= l.t_start - 100.0 + 1e-12, "%s: request %d launched before it arrived", what,
             l.batch[k]);
       if (k) CHECK(reqs[l.batch[k - 1]].t_arrival_s <= r.t_arrival_s, "%s: batch not in arrival order", what);
@@ -135,6 +145,7 @@ static void check_log(const FakeExec& ex, const std::vector<fx_request>& reqs, c
     }
     CHECK(l.batch.size() == 1 || pairs <= max_pairs, "%s: merged batch of %lld pairs over the cap", what,
           (long long)pairs);
+    CHECK((int)trajs.size() <= kServeMaxTrajs, "%s: batch draws on %zu trajectories", what, trajs.size());
   }
   // one stream runs one batch at a time
   for (size_t a = 0; a < ex.log.size(); ++a)
@@ -155,7 +166,9 @@ static void check_log(const FakeExec& ex, const std::vector<fx_request>& reqs, c
       CHECK(seen[i] == 1, "%s: request %zu served %d times", what, i, seen[i]);
       CHECK(o.lat_ms[i] >= 1e3 * ex.c0 - 1e-9, "%s: latency %g below the service time", what, o.lat_ms[i]);
     } else {
-      CHECK(o.status[i] == FX_ERR_OOM && seen[i] == 0, "%s: request %zu status %d", what, i, (int)o.status[i]);
+      CHECK((o.status[i] == FX_ERR_OOM || o.status[i] == FX_ERR_BUSY || o.status[i] == FX_ERR_CANCELLED) &&
+                seen[i] == 0,
+            "%s: request %zu status %d", what, i, (int)o.status[i]);
     }
   }
 }
@@ -279,6 +292,71 @@ int main() {
     ServeOutcome o;
     serve_schedule(ex, few.data(), (int)few.size(), all, cap, &o);
     CHECK(o.fatal == FX_ERR_INVALID && o.done == 0, "no slots: fatal %d", (int)o.fatal);
+  }
+  // merge classes: V_X requests of trajectories of one class share launches
+  // (at most kServeMaxTrajs trajectories each), never across classes or with ACE
+  {
+    std::vector<fx_request> r = make_requests(11, 800, 4000.0);
+    for (size_t i = 0; i < r.size(); ++i) r[i].traj = (int)(i * 7 % 13);  // 13 trajectories
+    FakeExec ex(4, 2);
+    for (int t = 0; t < 13; ++t) {
+      ex.norb[t] = t < 10 ? 32 : 64;
+      if (t < 10) ex.cls[t] = 100;      // ten of one class: more than one launch may hold
+      else if (t < 12) ex.cls[t] = 200;  // two of another
+    }
+    ex.reqs = r.data();
+    std::vector<char> all(r.size(), 1);
+    ServeOutcome o;
+    serve_schedule(ex, r.data(), (int)r.size(), all, cap, &o);
+    CHECK(o.fatal == FX_OK && o.done == (int64_t)r.size(), "classes: done %lld", (long long)o.done);
+    check_log(ex, r, all, o, cap, "classes");
+    int mixed = 0;
+    for (const Launch& l : ex.log) {
+      std::set<int> t;
+      for (int i : l.batch) t.insert(r[i].traj);
+      if (t.size() > 1) {
+        ++mixed;
+        CHECK(r[l.batch[0]].op == 0, "classes: an ACE batch mixes trajectories");
+      }
+    }
+    CHECK(mixed > 0, "classes: no launch merged trajectories of one class");
+  }
+  // admission: an arrival that finds max_queue requests waiting is refused with FX_ERR_BUSY
+  {
+    std::vector<fx_request> r = make_requests(13, 300, 1e6);  // a burst
+    FakeExec ex(1, 1);
+    ex.norb = {{0, 16}, {1, 128}, {2, 432}};
+    ex.reqs = r.data();
+    std::vector<char> all(r.size(), 1);
+    ServeOutcome o;
+    serve_schedule(ex, r.data(), (int)r.size(), all, 1, &o, 4);
+    int64_t busy = 0;
+    for (auto st : o.status) busy += st == FX_ERR_BUSY;
+    CHECK(o.fatal == FX_OK && busy > 0 && o.done + busy == (int64_t)r.size() && o.rejected == busy,
+          "queue cap: done %lld busy %lld", (long long)o.done, (long long)busy);
+    check_log(ex, r, all, o, 1, "queue cap");
+    ServeOutcome o2;
+    FakeExec ex2(1, 1);
+    ex2.norb = ex.norb;
+    ex2.reqs = r.data();
+    serve_schedule(ex2, r.data(), (int)r.size(), all, 1, &o2, 0);
+    CHECK(o2.done == (int64_t)r.size(), "no queue cap: every request served");
+  }
+  // cancellation: cancelled requests never run and report FX_ERR_CANCELLED
+  {
+    std::vector<fx_request> r = make_requests(17, 200, 3000.0);
+    FakeExec ex(2, 2);
+    ex.norb = {{0, 16}, {1, 128}, {2, 432}};
+    ex.reqs = r.data();
+    for (int i = 0; i < 200; i += 9) ex.cancel.insert(i);
+    std::vector<char> all(r.size(), 1);
+    ServeOutcome o;
+    serve_schedule(ex, r.data(), (int)r.size(), all, cap, &o);
+    bool ok = o.fatal == FX_OK && o.cancelled == (int64_t)ex.cancel.size() &&
+              o.done + o.cancelled == (int64_t)r.size();
+    for (int i : ex.cancel) ok = ok && o.status[i] == FX_ERR_CANCELLED;
+    CHECK(ok, "cancel: done %lld cancelled %lld", (long long)o.done, (long long)o.cancelled);
+    check_log(ex, r, all, o, cap, "cancel");
   }
   // no requests at all
   {

@@ -235,3 +235,109 @@ def test_workload_classes_oracle_sample():
     assert len(done) == 6
     srv.close()
     ctx.close()
+
+
+def test_same_grid_trajectories_share_a_launch():
+    """V_X requests of two trajectories on one grid (same cell, kernel, orbital count and precision)
+    run as one launch, each target paired with its own trajectory's orbitals: one batch, results
+    bitwise equal to each request served alone and within 1e-5 of the oracle. ACE requests of the
+    two trajectories stay in separate launches."""
+    import torch
+    from paper_1905_01348_amd import Context, Server
+
+    n3, L, N = (24, 24, 24), 10.26, 16
+    ctx = Context(0)
+    srv = Server(ctx, max_slots=1, n_streams=1, max_batch_pairs=1 << 16)
+    psis = {}
+    for t, seed in ((5, 501), (6, 502)):
+        psis[t] = synth.make_orbitals(seed, n3, L, N, dtype=np.complex64)
+        srv.register(t, dev(psis[t]), n=n3, L=L, kernel="hse", omega=0.106, vx_prec="fp32acc64",
+                     ace_prec="ace_fp32r")
+
+    def outs(rs):
+        return [torch.full((r["count"], 24, 24, 24), complex(9.0, 9.0), dtype=torch.complex64, device="cuda")
+                for r in rs]
+
+    reqs = [dict(traj=5, op=0, first=0, count=4, t=0.0), dict(traj=6, op=0, first=8, count=4, t=0.0),
+            dict(traj=5, op=0, first=12, count=4, t=0.0), dict(traj=6, op=0, first=2, count=3, t=0.0)]
+    for r, o in zip(reqs, outs(reqs)):
+        r["out"] = o
+    st, lat, rep = srv.serve(reqs)
+    torch.cuda.synchronize()
+    say("two trajectories, V_X:", rep)
+    assert st == [0, 0, 0, 0]
+    assert rep["n_batches"] == 1, "same-grid V_X requests of two trajectories should share one launch"
+    for i, r in enumerate(reqs):
+        psi = psis[r["traj"]].astype(np.complex128)
+        ref = oracle.apply_vx(psi, psi[r["first"]:r["first"] + r["count"]], n3, L, "hse", 0.106)
+        mixed = host(r["out"])
+        err = rel_err(mixed, ref)
+        say("  request", i, "traj", r["traj"], "oracle err", err)
+        assert err <= 1e-5
+        alone = dict(r, out=outs([r])[0])
+        st1, _, rep1 = srv.serve([alone])
+        assert st1 == [0] and rep1["n_batches"] == 1
+        assert np.array_equal(host(alone["out"]).view(np.float32), mixed.view(np.float32)), i
+    ace_reqs = [dict(traj=5, op=1, first=0, count=4, t=0.0), dict(traj=6, op=1, first=0, count=4, t=0.0)]
+    for r, o in zip(ace_reqs, outs(ace_reqs)):
+        r["out"] = o
+    st, lat, rep = srv.serve(ace_reqs)
+    assert st == [0, 0] and rep["n_batches"] == 2
+    srv.close()
+    ctx.close()
+
+
+def test_admission_busy_and_cancel():
+    """A queue cap refuses arrivals with FX_ERR_BUSY; cancelled requests report FX_ERR_CANCELLED and
+    the others complete; a cancellation from another thread while serving leaves every request
+    either done or cancelled."""
+    import threading
+
+    import torch
+    from paper_1905_01348_amd import Context, Server
+
+    ctx = Context(0)
+    n3, L, N = (24, 24, 24), 10.26, 16
+    psi = synth.make_orbitals(77, n3, L, N, dtype=np.complex64)
+
+    def mk(n):
+        rs = [dict(traj=0, op=i % 2, first=(4 * i) % 16, count=4, t=0.0) for i in range(n)]
+        for r in rs:
+            r["out"] = torch.zeros((4, 24, 24, 24), dtype=torch.complex64, device="cuda")
+        return rs
+
+    srv = Server(ctx, max_slots=1, n_streams=1, max_batch_pairs=64, max_queue=3)
+    srv.register(0, dev(psi), n=n3, L=L)
+    st, lat, rep = srv.serve(mk(12))
+    say("queue cap 3:", st, rep)
+    assert st.count(-6) > 0 and all(s in (0, -6) for s in st)
+    assert rep["n_rejected"] == st.count(-6) and rep["n_done"] == st.count(0)
+    srv.close()
+
+    srv = Server(ctx, max_slots=1, n_streams=1, max_batch_pairs=64)
+    srv.register(0, dev(psi), n=n3, L=L)
+    reqs = mk(10)
+    for i in (1, 4, 7):
+        srv.cancel(i)
+    st, lat, rep = srv.serve(reqs)
+    say("cancelled 1, 4, 7:", st, rep)
+    assert [i for i, s in enumerate(st) if s == -7] == [1, 4, 7] and rep["n_cancelled"] == 3
+    assert all(s == 0 for i, s in enumerate(st) if i not in (1, 4, 7))
+    for i in (1, 4, 7):
+        assert torch.count_nonzero(reqs[i]["out"]).item() == 0
+    # cancellations were forgotten when serve returned
+    st, lat, rep = srv.serve(mk(4))
+    assert st == [0, 0, 0, 0]
+    # from another thread while serving (arrivals spread over 0.2 s)
+    reqs = mk(40)
+    for i, r in enumerate(reqs):
+        r["t"] = 0.005 * i
+    th = threading.Thread(target=lambda: [srv.cancel(i) for i in range(20, 40)])
+    th.start()
+    st, lat, rep = srv.serve(reqs)
+    th.join()
+    say("threaded cancel:", rep)
+    assert all(s in (0, -7) for s in st) and all(s == 0 for s in st[:10])
+    assert rep["n_done"] + rep["n_cancelled"] == 40
+    srv.close()
+    ctx.close()

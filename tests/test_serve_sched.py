@@ -2,11 +2,13 @@
 paper_1905_01348_amd/csrc/serve_sched.hpp with a simulated executor (virtual clock, workspaces
 against a byte budget, injected allocation and device failures), built with g++ and the address
 and undefined-behaviour sanitizers.  Checks: nearest-rank percentiles; the merge rule; a replay in
-which every valid request is served once, batches never mix trajectories or operations nor pass
-the pair cap, a stream never runs two batches at once, heads go oldest first, and a second run
-schedules identically; a small budget, where batches wait while others run and only a batch that
-cannot fit alone is refused; an allocation failure absorbed by one release and retry; a device
-error ending the loop; an empty replay."""
+which every valid request is served once, batches never mix operations or merge classes nor pass
+the pair cap or the trajectory cap, a stream never runs two batches at once, heads go oldest
+first, and a second run schedules identically; V_X requests of different trajectories of one
+class sharing launches (ACE requests never); a small budget, where batches wait while others run
+and only a batch that cannot fit alone is refused; admission refusing arrivals with FX_ERR_BUSY
+when the queue is full; cancelled requests never running; an allocation failure absorbed by one
+release and retry; a device error ending the loop; an empty replay."""
 import os
 import shutil
 import subprocess
