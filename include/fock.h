@@ -267,6 +267,29 @@ fx_status fx_vx_set_config(fx_ctx* ctx, const fx_cell* cell, fx_prec prec, int32
 fx_status fx_vx_get_config(fx_ctx* ctx, const fx_cell* cell, fx_prec prec, int32_t phi_is_psi, fx_vx_config* cfg,
                            int32_t* is_set);
 
+/* Save the context's launch configurations to a text file, or load those of
+ * this kind of device (architecture and CU count) from one (*n_loaded: how
+ * many; nullable).  Lines for other devices are kept on save.  With the
+ * environment variable FX_TUNE_CACHE set to a path, fx_init loads that file
+ * if it exists and fx_vx_autotune saves to it after tuning.  Errors:
+ * FX_ERR_INVALID (NULL argument, unreadable or malformed file). */
+fx_status fx_vx_load_configs(fx_ctx* ctx, const char* path, int32_t* n_loaded);
+fx_status fx_vx_save_configs(fx_ctx* ctx, const char* path);
+
+/* Replay cache for fx_apply_vx and fx_apply_ace (the batched launches of
+ * Sec. 3.2 without their per-launch cost): with max_entries > 0, the first
+ * call with a given set of arguments (pointers included) runs as usual and is
+ * then captured into a HIP graph held by the context; later calls with the
+ * same arguments replay that graph on their stream.  Inputs are read when the
+ * graph runs, so new values in the same buffers give new results; any other
+ * argument makes a new entry (least recently used ones are dropped).
+ * Entries made before a workspace was reallocated or a launch configuration
+ * changed are never replayed.  Calls whose stream is itself being captured
+ * bypass the cache.  max_entries = 0 (the default) turns it off and frees
+ * the graphs.  Waits for the device.  Errors: FX_ERR_INVALID, FX_ERR_DEVICE. */
+fx_status fx_graph_cache(fx_ctx* ctx, int32_t max_entries);
+fx_status fx_graph_cache_stats(fx_ctx* ctx, int64_t* hits, int64_t* misses, int32_t* entries);
+
 /*
  * Build the ACE factors of V_X[psi]: W = V_X psi (with vx_prec), M = psi^H W in
  * FP64, Hermitised, FP64 Cholesky -M = L L^H, L^{-1} in FP64, xi = W L^{-H}.

@@ -238,8 +238,14 @@ fx_status fx_apply_ace(fx_ctx* ctx, const fx_ace* ace, const void* phi, int32_t 
   std::lock_guard<std::recursive_mutex> lk(ctx->mu);
   FX_HIP(hipSetDevice(ctx->device));
   FX_TRY(note_capture(ctx, (hipStream_t)stream));
-  return ace_apply_impl(ctx, &const_cast<fx_ace*>(ace)->ws, ace, phi, n_phi, ld_phi, out, ld_out, in_dtype,
-                        out_dtype, prec, (hipStream_t)stream);
+  auto body = [&](hipStream_t s) {
+    return ace_apply_impl(ctx, &const_cast<fx_ace*>(ace)->ws, ace, phi, n_phi, ld_phi, out, ld_out, in_dtype,
+                          out_dtype, prec, s);
+  };
+  if (ctx->graph_max <= 0) return body((hipStream_t)stream);
+  KeyBytes k;
+  k.add(1).add(ace).add(phi).add(n_phi).add(ld_phi).add(out).add(ld_out).add(in_dtype).add(out_dtype).add(prec);
+  return graph_call(ctx, k.b, (hipStream_t)stream, body);
 }
 
 fx_status fx_ace_export(const fx_ace* ace, void* xi, void* L, void* M) {

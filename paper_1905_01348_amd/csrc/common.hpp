@@ -115,6 +115,20 @@ struct fx_ctx {
   int n_cu = 0;
   std::recursive_mutex mu;
   fx::Workspace ws;  // workspace of the context's own calls
+  // generations: bumped whenever a workspace is reallocated or released, or a
+  // launch configuration changes -- a cached graph made before is stale
+  uint64_t ws_gen = 0, cfg_gen = 0;
+  // replay cache of fx_apply_vx / fx_apply_ace calls (fx_graph_cache)
+  struct GraphEntry {
+    std::vector<unsigned char> key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t ws_gen = 0, cfg_gen = 0, last_use = 0;
+  };
+  int graph_max = 0;
+  uint64_t graph_tick = 0;
+  int64_t graph_hits = 0, graph_misses = 0;
+  std::vector<GraphEntry> graphs;
   std::map<fx::TableKey, fx::GridTables> tables;
   // tuned V_X launch configurations, keyed by (n[3], prec, phi == psi form)
   std::map<std::array<int, 5>, fx_vx_config> vx_tuning;
@@ -150,6 +164,18 @@ void ctx_free(fx_ctx* ctx, void* p, size_t bytes);
 // Let `kernel` use `bytes` of dynamic LDS on the current device (the
 // attribute is set once per device and kernel, never again afterwards).
 fx_status allow_dynamic_lds(const void* kernel, size_t bytes);
+
+// Replay cache: run `body` on `st` through a cached graph of the call
+// described by `key` (every argument, pointers included).  With the cache
+// off, or `st` itself being captured, body(st) runs as is.  On a miss body
+// runs eagerly on st (so every workspace exists and the result is made), is
+// then captured on the context's own stream, and the graph is kept (least
+// recently used entries go first); later calls with the same key replay it
+// on st.  Entries made before a workspace was reallocated or a launch
+// configuration changed are dropped.
+template <typename F>
+fx_status graph_call(fx_ctx* ctx, const std::vector<unsigned char>& key, hipStream_t st, F body);
+void graph_cache_clear(fx_ctx* ctx);
 
 // Record whether `st` is being captured into a graph (ctx->capturing).
 fx_status note_capture(fx_ctx* ctx, hipStream_t st);
@@ -213,8 +239,79 @@ fx_status prof_end(fx_ctx* ctx, hipStream_t st, int slot);
 
 inline size_t dtype_size(fx_dtype d) { return d == FX_C128 ? 16 : 8; }
 
+// Bytes of a call's arguments, for graph_call keys.
+struct KeyBytes {
+  std::vector<unsigned char> b;
+  template <typename V>
+  KeyBytes& add(const V& v) {
+    const unsigned char* p = reinterpret_cast<const unsigned char*>(&v);
+    b.insert(b.end(), p, p + sizeof(V));
+    return *this;
+  }
+};
+
+template <typename F>
+fx_status graph_call(fx_ctx* ctx, const std::vector<unsigned char>& key, hipStream_t st, F body) {
+  if (ctx->graph_max <= 0 || ctx->capturing) return body(st);
+  auto& G = ctx->graphs;
+  for (size_t i = 0; i < G.size(); ++i) {
+    if (G[i].key != key) continue;
+    if (G[i].ws_gen == ctx->ws_gen && G[i].cfg_gen == ctx->cfg_gen) {
+      G[i].last_use = ++ctx->graph_tick;
+      ++ctx->graph_hits;
+      FX_HIP(hipGraphLaunch(G[i].exec, st));
+      return FX_OK;
+    }
+    (void)hipGraphExecDestroy(G[i].exec);
+    (void)hipGraphDestroy(G[i].graph);
+    G.erase(G.begin() + i);
+    break;
+  }
+  ++ctx->graph_misses;
+  FX_TRY(body(st));
+  // capture the same call on the context's stream; workspaces and tables now
+  // exist, so the body allocates nothing and waits for nothing
+  hipGraph_t g = nullptr;
+  FX_HIP(hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal));
+  ctx->capturing = true;
+  const fx_status s = body(ctx->stream);
+  ctx->capturing = false;
+  const hipError_t e = hipStreamEndCapture(ctx->stream, &g);
+  if (s != FX_OK || e != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    clear_error();
+    return FX_OK;  // the eager result stands; this call is just not cached
+  }
+  hipGraphExec_t x = nullptr;
+  if (hipGraphInstantiate(&x, g, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return FX_OK;
+  }
+  if ((int)G.size() >= ctx->graph_max) {
+    size_t lru = 0;
+    for (size_t i = 1; i < G.size(); ++i)
+      if (G[i].last_use < G[lru].last_use) lru = i;
+    (void)hipGraphExecDestroy(G[lru].exec);
+    (void)hipGraphDestroy(G[lru].graph);
+    G.erase(G.begin() + lru);
+  }
+  fx_ctx::GraphEntry en;
+  en.key = key;
+  en.graph = g;
+  en.exec = x;
+  en.ws_gen = ctx->ws_gen;
+  en.cfg_gen = ctx->cfg_gen;
+  en.last_use = ++ctx->graph_tick;
+  G.push_back(std::move(en));
+  return FX_OK;
+}
+
 // Allocation-free form (noalloc.hip): look up, once per device and with that
 // device current, the device address of the file-scope scratch region.
 fx_status scratch_setup(int device);
+
+// Tuned launch configurations from / to a file (tune.hip).
+fx_status load_configs_impl(fx_ctx* ctx, const char* path, int* n_loaded);
+fx_status save_configs_impl(fx_ctx* ctx, const char* path);
 
 }  // namespace fx

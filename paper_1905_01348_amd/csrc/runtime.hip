@@ -137,6 +137,7 @@ fx_status ws_get(fx_ctx* ctx, Workspace* ws, const char* name, size_t bytes, voi
   FX_TRY(ctx_alloc(ctx, bytes, &b.ptr));
   b.bytes = bytes;
   *out = b.ptr;
+  ctx->ws_gen++;
   return FX_OK;
 }
 
@@ -145,6 +146,15 @@ void ws_release(fx_ctx* ctx, Workspace* ws) {
     for (auto& kv : ws->bufs) ctx_free(ctx, kv.second.ptr, kv.second.bytes);
   ws->bufs.clear();
   ws->arena_used = 0;
+  if (ctx) ctx->ws_gen++;
+}
+
+void graph_cache_clear(fx_ctx* ctx) {
+  for (auto& g : ctx->graphs) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+  }
+  ctx->graphs.clear();
 }
 
 // ---- per-kernel timing ------------------------------------------------------
@@ -505,6 +515,21 @@ fx_status fx_init(int device, size_t hbm_budget_bytes, fx_ctx** ctx) {
     delete c;
     return ss;
   }
+  // FX_TUNE_CACHE: tuned launch configurations kept in a file (a missing
+  // file is not an error; an unreadable one is)
+  if (const char* e = getenv("FX_TUNE_CACHE")) {
+    if (*e) {
+      if (FILE* f = fopen(e, "r")) {
+        fclose(f);
+        const fx_status ls = load_configs_impl(c, e, nullptr);
+        if (ls != FX_OK) {
+          (void)hipStreamDestroy(c->stream);
+          delete c;
+          return ls;
+        }
+      }
+    }
+  }
   *ctx = c;
   return FX_OK;
 }
@@ -518,6 +543,7 @@ fx_status fx_finalize(fx_ctx* ctx) {
   // they stay valid for fx_serve_destroy / fx_ace_free only
   serve_detach_all(ctx);
   ace_detach_all(ctx);
+  graph_cache_clear(ctx);
   ws_release(ctx, &ctx->ws);
   for (auto& kv : ctx->tables) {
     GridTables& t = kv.second;
@@ -533,6 +559,29 @@ fx_status fx_finalize(fx_ctx* ctx) {
   ctx->ev_pool.clear();
   (void)hipStreamDestroy(ctx->stream);
   delete ctx;
+  return FX_OK;
+}
+
+fx_status fx_graph_cache(fx_ctx* ctx, int32_t max_entries) {
+  clear_error();
+  if (!ctx) FX_FAIL(FX_ERR_INVALID, "ctx is NULL");
+  if (max_entries < 0 || max_entries > 4096) FX_FAIL(FX_ERR_INVALID, "max_entries = %d not in [0, 4096]", max_entries);
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  FX_HIP(hipSetDevice(ctx->device));
+  FX_HIP(hipDeviceSynchronize());
+  graph_cache_clear(ctx);
+  ctx->graph_max = max_entries;
+  ctx->graph_hits = ctx->graph_misses = 0;
+  return FX_OK;
+}
+
+fx_status fx_graph_cache_stats(fx_ctx* ctx, int64_t* hits, int64_t* misses, int32_t* entries) {
+  clear_error();
+  if (!ctx) FX_FAIL(FX_ERR_INVALID, "ctx is NULL");
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  if (hits) *hits = ctx->graph_hits;
+  if (misses) *misses = ctx->graph_misses;
+  if (entries) *entries = (int32_t)ctx->graphs.size();
   return FX_OK;
 }
 

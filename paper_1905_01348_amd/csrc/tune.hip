@@ -11,7 +11,11 @@
 // least 2% faster, so timing noise does not flip settled choices.
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstring>
 #include <limits>
+#include <string>
+#include <vector>
 
 #include "common.hpp"
 #include "vx.hpp"
@@ -58,6 +62,122 @@ static fx_status check_config(const fx_cell* cell, const fx_vx_config& c) {
 }
 
 static bool is_vx_prec(fx_prec p) { return p == FX_PREC_FP64 || p == FX_PREC_FP32 || p == FX_PREC_FP32_ACC64; }
+
+// ---- configuration file -------------------------------------------------------
+// One configuration per line:
+//   fxcfg <device> <nx> <ny> <nz> <prec> <phi_is_psi> <kernels> <work_mb> <a_prefetch>
+//         <b_variant> <c_variant> <a_variant> <nt_hint> <b_xtile> <b_threads> <12 radix entries>
+// where <device> is the architecture and CU count ("gfx950/256"): a tuned
+// launch shape holds for that kind of device only.  Lines starting with '#'
+// are comments; lines for other devices are kept when the file is rewritten.
+static std::string device_tag(int device) {
+  hipDeviceProp_t p;
+  if (hipGetDeviceProperties(&p, device) != hipSuccess) return "unknown";
+  std::string arch(p.gcnArchName);
+  const size_t c = arch.find(':');
+  if (c != std::string::npos) arch.resize(c);
+  return arch + "/" + std::to_string(p.multiProcessorCount);
+}
+
+static std::string config_line(const std::string& tag, const std::array<int, 5>& k, const fx_vx_config& c) {
+  std::string s = "fxcfg " + tag;
+  for (int v : k) s += " " + std::to_string(v);
+  const int f[9] = {c.kernels, c.work_mb, c.a_prefetch, c.b_variant, c.c_variant, c.a_variant, c.nt_hint, c.b_xtile,
+                    c.b_threads};
+  for (int v : f) s += " " + std::to_string(v);
+  for (int a = 0; a < 3; ++a)
+    for (int r = 0; r < 4; ++r) s += " " + std::to_string(c.radix[a][r]);
+  return s;
+}
+
+// Parse one line; false if it is not a configuration line.
+static bool parse_config_line(const char* line, std::string* tag, std::array<int, 5>* k, fx_vx_config* c) {
+  char tg[128];
+  int v[5 + 9 + 12];
+  int used = 0;
+  if (std::sscanf(line, "fxcfg %127s%n", tg, &used) != 1) return false;
+  const char* p = line + used;
+  for (int i = 0; i < 26; ++i) {
+    int adv = 0;
+    if (std::sscanf(p, "%d%n", &v[i], &adv) != 1) return false;
+    p += adv;
+  }
+  *tag = tg;
+  for (int i = 0; i < 5; ++i) (*k)[i] = v[i];
+  int* f[9] = {&c->kernels, &c->work_mb, &c->a_prefetch, &c->b_variant, &c->c_variant, &c->a_variant, &c->nt_hint,
+               &c->b_xtile, &c->b_threads};
+  for (int i = 0; i < 9; ++i) *f[i] = v[5 + i];
+  for (int a = 0; a < 3; ++a)
+    for (int r = 0; r < 4; ++r) c->radix[a][r] = v[14 + 4 * a + r];
+  return true;
+}
+
+fx_status load_configs_impl(fx_ctx* ctx, const char* path, int* n_loaded) {
+  if (n_loaded) *n_loaded = 0;
+  FILE* f = std::fopen(path, "r");
+  if (!f) FX_FAIL(FX_ERR_INVALID, "cannot open configuration file %s", path);
+  const std::string tag = device_tag(ctx->device);
+  char line[1024];
+  int n = 0, lineno = 0;
+  fx_status st = FX_OK;
+  while (std::fgets(line, sizeof line, f)) {
+    ++lineno;
+    if (line[0] == '#' || line[0] == '\n') continue;
+    std::string tg;
+    std::array<int, 5> k;
+    fx_vx_config c{};
+    if (!parse_config_line(line, &tg, &k, &c)) {
+      set_error("%s:%d: not a configuration line", path, lineno);
+      st = FX_ERR_INVALID;
+      break;
+    }
+    if (tg != tag) continue;
+    fx_cell cell{{k[0], k[1], k[2]}, {1.0, 1.0, 1.0}};
+    if (check_cell(&cell) != FX_OK || !is_vx_prec((fx_prec)k[3]) || (k[4] != 0 && k[4] != 1) ||
+        check_config(&cell, c) != FX_OK) {
+      set_error("%s:%d: invalid configuration", path, lineno);
+      st = FX_ERR_INVALID;
+      break;
+    }
+    ctx->vx_tuning[k] = c;
+    ++n;
+  }
+  std::fclose(f);
+  if (n_loaded) *n_loaded = n;
+  return st;
+}
+
+fx_status save_configs_impl(fx_ctx* ctx, const char* path) {
+  const std::string tag = device_tag(ctx->device);
+  // keep the lines of other devices and of shapes this context does not hold
+  std::vector<std::string> keep;
+  if (FILE* f = std::fopen(path, "r")) {
+    char line[1024];
+    while (std::fgets(line, sizeof line, f)) {
+      std::string tg;
+      std::array<int, 5> k;
+      fx_vx_config c{};
+      std::string ln(line);
+      while (!ln.empty() && (ln.back() == '\n' || ln.back() == '\r')) ln.pop_back();
+      if (ln.empty() || ln.rfind("# libfock", 0) == 0) continue;
+      // this device's shapes that the context holds are rewritten; any other
+      // line (other devices, other shapes, foreign text) is kept as it was
+      if (parse_config_line(line, &tg, &k, &c) && tg == tag && ctx->vx_tuning.count(k)) continue;
+      keep.push_back(ln);
+    }
+    std::fclose(f);
+  }
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) FX_FAIL(FX_ERR_INVALID, "cannot write configuration file %s", tmp.c_str());
+  std::fprintf(f, "# libfock V_X launch configurations (fx_vx_save_configs); one per device kind, grid, precision "
+                  "and form\n");
+  for (const auto& ln : keep) std::fprintf(f, "%s\n", ln.c_str());
+  for (const auto& kv : ctx->vx_tuning) std::fprintf(f, "%s\n", config_line(tag, kv.first, kv.second).c_str());
+  const bool ok = std::fclose(f) == 0;
+  if (!ok || std::rename(tmp.c_str(), path) != 0) FX_FAIL(FX_ERR_INVALID, "cannot replace configuration file %s", path);
+  return FX_OK;
+}
 
 // One timed candidate: a warm-up apply (allocations, tables), then the best
 // of two.  Returns +inf when the candidate cannot run (budget, launch shape).
@@ -323,7 +443,30 @@ fx_status fx_vx_autotune(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* kern
   hipStream_t st = (hipStream_t)stream;
   FX_TRY(note_capture(ctx, st));
   if (ctx->capturing) FX_FAIL(FX_ERR_INVALID, "fx_vx_autotune waits on its stream and cannot be captured");
-  return vx_autotune_impl(ctx, cell, kernel, n_psi, n_phi, phi_is_psi != 0, prec, st, best, best_ms_per_kpair);
+  FX_TRY(vx_autotune_impl(ctx, cell, kernel, n_psi, n_phi, phi_is_psi != 0, prec, st, best, best_ms_per_kpair));
+  ctx->cfg_gen++;
+  // FX_TUNE_CACHE: keep the file of tuned configurations up to date
+  if (const char* e = getenv("FX_TUNE_CACHE"))
+    if (*e) FX_TRY(save_configs_impl(ctx, e));
+  return FX_OK;
+}
+
+fx_status fx_vx_load_configs(fx_ctx* ctx, const char* path, int32_t* n_loaded) {
+  clear_error();
+  if (!ctx || !path) FX_FAIL(FX_ERR_INVALID, "NULL argument");
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  int n = 0;
+  const fx_status s = load_configs_impl(ctx, path, &n);
+  if (n_loaded) *n_loaded = n;
+  ctx->cfg_gen++;
+  return s;
+}
+
+fx_status fx_vx_save_configs(fx_ctx* ctx, const char* path) {
+  clear_error();
+  if (!ctx || !path) FX_FAIL(FX_ERR_INVALID, "NULL argument");
+  std::lock_guard<std::recursive_mutex> lk(ctx->mu);
+  return save_configs_impl(ctx, path);
 }
 
 fx_status fx_vx_set_config(fx_ctx* ctx, const fx_cell* cell, fx_prec prec, int32_t phi_is_psi,
@@ -334,6 +477,7 @@ fx_status fx_vx_set_config(fx_ctx* ctx, const fx_cell* cell, fx_prec prec, int32
   if (!is_vx_prec(prec)) FX_FAIL(FX_ERR_UNSUPPORTED, "precision %d is not a V_X precision", prec);
   std::lock_guard<std::recursive_mutex> lk(ctx->mu);
   const auto key = vx_tune_key(cell, prec, phi_is_psi != 0);
+  ctx->cfg_gen++;
   if (!cfg) {
     ctx->vx_tuning.erase(key);
     return FX_OK;

@@ -908,7 +908,13 @@ fx_status fx_apply_vx(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* kernel,
   a.ex_dev = ex_energy_dev;
   hipStream_t st = (hipStream_t)stream;
   FX_TRY(note_capture(ctx, st));
-  return vx_apply(ctx, &ctx->ws, a, st, nullptr);
+  if (ctx->graph_max <= 0) return vx_apply(ctx, &ctx->ws, a, st, nullptr);
+  if (!cell || !kernel) FX_FAIL(FX_ERR_INVALID, "cell and kernel must be non-NULL");
+  KeyBytes k;
+  k.add(0).add(cell->n[0]).add(cell->n[1]).add(cell->n[2]).add(cell->len[0]).add(cell->len[1]).add(cell->len[2]);
+  k.add(kernel->kind).add(kernel->omega).add(kernel->scale).add(psi).add(n_psi).add(ld_psi).add(phi).add(n_phi);
+  k.add(ld_phi).add(out).add(ld_out).add(in_dtype).add(out_dtype).add(prec).add(ex_energy_dev);
+  return graph_call(ctx, k.b, st, [&](hipStream_t s) { return vx_apply(ctx, &ctx->ws, a, s, nullptr); });
 }
 
 fx_status fx_debug_host_pair_plan(const fx_cell* cell, const fx_kernel* kernel, int prec, const int32_t* radix,

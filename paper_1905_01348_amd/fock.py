@@ -115,6 +115,11 @@ _SIGS = {
                            C.POINTER(C.c_double), C.POINTER(FxServeReport)]),
     "fx_serve_destroy": (C.c_int, [C.c_void_p]),
     "fx_serve_cancel": (C.c_int, [C.c_void_p, C.c_int32]),
+    "fx_vx_load_configs": (C.c_int, [C.c_void_p, C.c_char_p, C.POINTER(C.c_int32)]),
+    "fx_vx_save_configs": (C.c_int, [C.c_void_p, C.c_char_p]),
+    "fx_graph_cache": (C.c_int, [C.c_void_p, C.c_int32]),
+    "fx_graph_cache_stats": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                       C.POINTER(C.c_int32)]),
     "fx_prof_enable": (C.c_int, [C.c_void_p, C.c_int]),
     "fx_prof_read": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double),
                                C.POINTER(C.c_double)]),
@@ -433,6 +438,27 @@ class Context:
         _check(load().fx_vx_get_config(self.h, C.byref(cell), PREC[prec], 1 if phi_is_psi else 0, C.byref(c),
                                        C.byref(is_set)))
         return config_to_dict(c), bool(is_set.value)
+
+    def load_configs(self, path):
+        """Load the launch configurations of this kind of device from a file; returns how many."""
+        n = C.c_int32()
+        _check(load().fx_vx_load_configs(self.h, os.fsencode(path), C.byref(n)))
+        return n.value
+
+    def save_configs(self, path):
+        """Save the context's launch configurations to a file (other devices' lines are kept)."""
+        _check(load().fx_vx_save_configs(self.h, os.fsencode(path)))
+
+    # -- replay cache ------------------------------------------------------------
+    def graph_cache(self, max_entries):
+        """Replay cache of apply_vx / Ace.apply calls (0 turns it off)."""
+        _check(load().fx_graph_cache(self.h, int(max_entries)))
+
+    def graph_cache_stats(self):
+        """(hits, misses, entries) of the replay cache."""
+        h, m, e = C.c_int64(), C.c_int64(), C.c_int32()
+        _check(load().fx_graph_cache_stats(self.h, C.byref(h), C.byref(m), C.byref(e)))
+        return h.value, m.value, e.value
 
     # -- ACE ------------------------------------------------------------------
     def build_ace(self, psi, *, n, L, kernel="hse", omega=0.106, scale=1.0, vx_prec="fp64",

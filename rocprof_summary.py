@@ -1,23 +1,23 @@
 """Summaries of rocprofv3 output for the profiles/ directory.
 
-    python -m paper_1905_01348_amd.rocprof_summary stats <kernel_stats.csv> [--title T] [--command C]
+    python rocprof_summary.py stats <kernel_stats.csv> [--title T] [--command C]
         -> a Markdown table of per-kernel calls and durations.
 
-    python -m paper_1905_01348_amd.rocprof_summary traffic --fetch <dir> --write <dir>
+    python rocprof_summary.py traffic --fetch <dir> --write <dir>
            --copy-fetch <dir> --copy-write <dir> --kernels a,b,c [--durations <kernel_stats.csv>]
         -> a Markdown table of calibrated DRAM bytes per dispatch for several kernels.
 
-    python -m paper_1905_01348_amd.rocprof_summary counters --fetch <dir> --write <dir>
+    python rocprof_summary.py counters --fetch <dir> --write <dir>
            --copy-fetch <dir> --copy-write <dir> --kernels a,b --names id_a,id_b --prec <p> --source-hash <h>
            [--out profiles/vx_counters.json] [--command C]
         -> HBM traffic per launch of each kernel from FETCH_SIZE and WRITE_SIZE
            (KiB per dispatch), each scaled by the factor that makes a plain
            1 GiB device copy read and write exactly 1 GiB.
 
-    python -m paper_1905_01348_amd.rocprof_summary table <dir> [<dir> ...] --kernels a,b,c
+    python rocprof_summary.py table <dir> [<dir> ...] --kernels a,b,c
         -> a Markdown table of the mean of every counter per dispatch for each kernel.
 
-    python -m paper_1905_01348_amd.rocprof_summary mfma <dir> [--kernel k_tn_mfma]
+    python rocprof_summary.py mfma <dir> [--kernel k_tn_mfma]
         -> executed MFMA TFLOP/s, fraction of the dense peak and matrix-core busy
            fraction of each matrix-core kernel instantiation.
 

@@ -144,3 +144,67 @@ def test_apply_ace_graph_replays_match_eager(ctx, prec):
         torch.cuda.synchronize()
     del g
     ace.free()
+
+
+@pytest.mark.parametrize("prec", ["fp32acc64", "fp64"])
+def test_library_replay_cache(prec):
+    """fx_graph_cache: the first call of a set of arguments runs eagerly and is captured; later
+    calls with the same arguments replay the graph. Every replay equals the eager result bitwise
+    (with eager work and host waits of the program's own in between); new values in the same input
+    buffer give the new result; another output buffer or a new launch configuration is a miss."""
+    import torch
+    from paper_1905_01348_amd import Context
+
+    n, L, N = 24, 10.26, 16
+    p_np = synth.make_orbitals(0, n, L, N, dtype=np.complex64 if prec == "fp32acc64" else np.complex128)
+    ref_ctx = Context(0)
+    psi = dev(p_np)
+    phi = psi[:5].clone()
+    ref = host(ref_ctx.apply_vx(psi, phi, n=n, L=L, prec=prec))
+    c = Context(0)
+    c.graph_cache(8)
+    out = torch.full((5, n, n, n), complex(3.0, 3.0), dtype=torch.complex128, device="cuda")
+    for rep in range(4):
+        out.fill_(complex(3.0, 3.0))
+        c.apply_vx(psi, phi, n=n, L=L, prec=prec, out=out)
+        torch.cuda.synchronize()
+        assert np.array_equal(_bits(host(out)), _bits(ref)), f"call {rep}"
+        ref_ctx.apply_vx(psi, phi, n=n, L=L, prec=prec)  # other work between replays
+        torch.cuda.synchronize()
+    hits, misses, entries = c.graph_cache_stats()
+    say("replay cache", prec, hits, misses, entries)
+    assert (hits, misses, entries) == (3, 1, 1)
+    # new values in the same buffers: the replay reads them
+    phi.copy_(psi[5:10])
+    c.apply_vx(psi, phi, n=n, L=L, prec=prec, out=out)
+    torch.cuda.synchronize()
+    ref2 = host(ref_ctx.apply_vx(psi, psi[5:10].clone(), n=n, L=L, prec=prec))
+    assert np.array_equal(_bits(host(out)), _bits(ref2))
+    assert c.graph_cache_stats()[:2] == (4, 1)
+    # another output buffer: a new entry
+    out2 = torch.empty_like(out)
+    c.apply_vx(psi, phi, n=n, L=L, prec=prec, out=out2)
+    torch.cuda.synchronize()
+    assert np.array_equal(_bits(host(out2)), _bits(ref2))
+    assert c.graph_cache_stats() == (4, 2, 2)
+    # a changed launch configuration makes the stored graphs stale
+    cfg, _ = c.get_vx_config(n=n, prec=prec, phi_is_psi=False)
+    cfg["work_mb"] = 64
+    c.set_vx_config(cfg, n=n, prec=prec, phi_is_psi=False)
+    c.apply_vx(psi, phi, n=n, L=L, prec=prec, out=out)
+    torch.cuda.synchronize()
+    assert np.array_equal(_bits(host(out)), _bits(ref2))
+    assert c.graph_cache_stats()[:2] == (4, 3)
+    # ACE through the cache
+    ace = c.build_ace(psi, n=n, L=L, kernel="hse", omega=0.106)
+    y_e = host(ace.apply(phi, prec="ace_fp32r"))
+    y = torch.empty_like(phi)
+    for rep in range(3):
+        ace.apply(phi, prec="ace_fp32r", out=y)
+        torch.cuda.synchronize()
+        assert np.array_equal(_bits(host(y)), _bits(y_e)), f"ace call {rep}"
+    c.graph_cache(0)
+    assert c.graph_cache_stats() == (0, 0, 0)
+    ace.free()
+    c.close()
+    ref_ctx.close()

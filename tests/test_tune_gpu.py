@@ -144,3 +144,38 @@ def test_autotune_stores_a_config_that_applies_use(ctx, case):
     got = host(ctx.apply_vx(P, None if square else dev(ref_phi), n=n3, L=L3, kernel="hse", prec=prec))
     assert rel_err(got, ref) <= TOL[prec]
     ctx.set_vx_config(None, n=n3, prec=prec, phi_is_psi=square)
+
+
+def test_configurations_saved_and_loaded(tmp_path, monkeypatch):
+    """Tuned configurations survive the context: saved to a file and loaded by a new context
+    (explicitly, or at fx_init through FX_TUNE_CACHE, which fx_vx_autotune also writes)."""
+    from paper_1905_01348_amd import Context
+
+    path = str(tmp_path / "tune.txt")
+    monkeypatch.setenv("FX_TUNE_CACHE", path)
+    c = Context(0)
+    cfg, ms = c.vx_autotune(n=24, L=10.26, n_psi=16, n_phi=4, prec="fp32acc64")
+    c.close()
+    text = open(path).read()
+    say("tune cache file:", text)
+    assert "fxcfg gfx950/" in text
+    c2 = Context(0)  # loads FX_TUNE_CACHE at init
+    got, is_set = c2.get_vx_config(n=24, prec="fp32acc64", phi_is_psi=False)
+    assert is_set and got == cfg
+    c2.close()
+    monkeypatch.delenv("FX_TUNE_CACHE")
+    c3 = Context(0)
+    assert not c3.get_vx_config(n=24, prec="fp32acc64", phi_is_psi=False)[1]
+    assert c3.load_configs(path) >= 1
+    assert c3.get_vx_config(n=24, prec="fp32acc64", phi_is_psi=False) == (cfg, True)
+    # saving keeps lines of other devices
+    with open(path, "a") as f:
+        f.write("fxcfg gfx000/1 24 24 24 2 0 1 0 0 1 1 1 1 0 0 0 0 0 0 0 0 0 0 0 0 0 0\n")
+    c3.save_configs(path)
+    assert "gfx000/1" in open(path).read()
+    with open(path, "a") as f:
+        f.write("not a configuration\n")
+    from paper_1905_01348_amd import FockError
+    with pytest.raises(FockError):
+        c3.load_configs(path)
+    c3.close()
