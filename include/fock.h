@@ -221,8 +221,10 @@ typedef struct fx_vx_config {
                           2 a larger count (fewer accumulators per thread, more waves),
                           3 and 4: 2 and 1 with the next work plane copied into LDS
                           while the current one is transformed (where two planes fit
-                          the LDS: not FP64 at 72 and 96, which run 2 and 1 instead);
-                          0 automatic (2 at edges 96 and 72, else 1) */
+                          the LDS: not FP64 at 72 and 96, which run 2 and 1 instead),
+                          5: 2 with the inverse x transform across the lanes of a
+                          wave (FP32 at edges 72 and 96; elsewhere 2);
+                          0 automatic (5 at edges 96 and 72, else 1) */
   int32_t a_variant;   /* specialised plane-forward pass threads: 1 the edge's default,
                           2 a count that divides the butterflies evenly; 0 automatic (1) */
   int32_t nt_hint;     /* specialised kernels: 1 read and write the pair volume with

@@ -256,6 +256,117 @@ __device__ inline void ct_conv(cpx<T>* s, const cpx<T>* tw, KF kf, int tid) {
   __syncthreads();
 }
 
+// The stage over whole rows (radix R0, span N / R0) of a plane of N rows of
+// N, with butterfly b on row row(b / SPAN) and offset i2 = b % SPAN: the SPAN
+// lanes of a row hold the consecutive positions i2 + SPAN m of the row, so
+// global data at those plane positions is read or written in runs of SPAN
+// consecutive values.  The last inverse stage of the row transform leaves its
+// outputs in registers (inv_from_lds), which saves an LDS round trip of the
+// plane and a barrier.  x[it][m] is value m of butterfly it, at plane position
+// pos(tid, it, m).
+template <typename T, int N, int NT>
+struct RowStage {
+  static constexpr int R = Plan2<N>::R0, SPAN = N / R, TOTAL = N * SPAN;
+  static constexpr int IT = (TOTAL + NT - 1) / NT;  // butterflies per thread
+  // With rows of N + 1 values in LDS the value at offset i2 of row f sits in
+  // bank (f + i2) mod 32 at edges 72 and 96 (N + 1 = 1 or 9 mod 32, and 9 f
+  // runs over the same residues as f when f steps by 8): the four rows of a
+  // 32-lane group are taken 8 apart, so that their accesses hit distinct banks.
+  FX_HD static int row(int r) {
+    if (SPAN == 8 && r < N / 32 * 32) return (r & ~31) + 8 * (r & 3) + ((r >> 2) & 7);
+    return r;
+  }
+  FX_HD static bool owns(int tid, int it) { return TOTAL % NT == 0 || tid + it * NT < TOTAL; }
+  FX_HD static int pos(int tid, int it, int m) {
+    const int b = tid + it * NT;
+    const int r = b / SPAN, i2 = b - r * SPAN;
+    return row(r) * N + i2 + m * SPAN;
+  }
+  // ---- wave-level inverse row transform (both stages, edges 72 and 96) ----
+  // With R1 = SPAN = 8, the 8 lanes holding one row's positions i2 + 8 m hold
+  // value i2 of each radix-8 block m of the row's first inverse stage, so that
+  // stage can run across those lanes instead of through LDS: each lane reads
+  // its R values of the row transform's input, the radix-8 DFTs run as three
+  // radix-2 steps between lanes whose DFT indices differ in one bit (the
+  // partner's value arrives by a DPP move, both lanes of a pair compute their
+  // own half of the butterfly), and the lane is then the butterfly i2 =
+  // bitrev3(DFT index) of the radix-R stage, done in registers as in
+  // inv_from_lds.  DFT index bits 0 and 1 sit on lane bits 0 and 1 and bit 2
+  // on lane bit 3, so the partners are lane ^ 1 and lane ^ 2 (quad
+  // permutations) and lane ^ 8 (rotation by 8 within a row of 16 lanes); lane
+  // bits 2 and 4 and the wave index select the row, whose LDS reads stay on
+  // distinct banks (four rows 8 apart per 32 lanes, as row() arranges).
+  static constexpr bool kWave = Plan2<N>::R1 == 8 && SPAN == 8 && TOTAL == NT;
+  // row and DFT index of thread tid
+  FX_HD static void wave_lane(int tid, int* f, int* l) {
+    *l = (tid & 3) | (((tid >> 3) & 1) << 2);
+    *f = row((tid >> 5) * 4 + (((tid >> 2) & 1) | (((tid >> 4) & 1) << 1)));
+  }
+  FX_HD static int bitrev3(int l) { return ((l & 1) << 2) | (l & 2) | ((l >> 2) & 1); }
+  // plane position of value m of thread tid after inv_x_wave
+  FX_HD static int wave_pos(int tid, int m) {
+    int f, l;
+    wave_lane(tid, &f, &l);
+    return f * N + bitrev3(l) + m * SPAN;
+  }
+  // the value of the lane whose DFT index is this lane's ^ H
+  template <int H>
+  __device__ static T partner(T v) {
+    static_assert(sizeof(T) == 4, "32-bit lane exchange");
+    constexpr int ctrl = H == 1 ? 0xB1 : (H == 2 ? 0x4E : 0x128);  // quad_perm [1,0,3,2], [2,3,0,1]; row_ror:8
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), ctrl, 0xF, 0xF, false));
+  }
+  template <int SX>
+  __device__ static void inv_x_wave(const cpx<T>* s, const cpx<T>* tw, int tid, cpx<T> (&x)[R]) {
+    static_assert(kWave, "wave-level row transform needs R1 = N / R0 = 8 and one butterfly per thread");
+    int f, l;
+    wave_lane(tid, &f, &l);
+#pragma unroll
+    for (int m = 0; m < R; ++m) x[m] = s[f * SX + l + m * SPAN];
+    // radix-8 inverse DFT across the lanes, decimation in frequency: at index
+    // distance H the lower lane keeps a + b, the upper one (a - b) w^(l mod H)
+    // with w = exp(2 pi i H' / 8), H' = 4 / H
+    const T c = (T)0.70710678118654752440084436210484903928;
+    const bool h4 = l & 4, h2 = l & 2, h1 = l & 1;
+    // twiddles of the first step: exp(2 pi i (l mod 4) / 8) on the upper lanes
+    const int e = l & 3;
+    const T wr = !h4 ? (T)1 : (e == 0 ? (T)1 : (e == 1 ? c : (e == 2 ? (T)0 : -c)));
+    const T wi = !h4 ? (T)0 : (e == 0 ? (T)0 : (e == 2 ? (T)1 : c));
+    const T s4 = h4 ? (T)-1 : (T)1, s2 = h2 ? (T)-1 : (T)1, s1 = h1 ? (T)-1 : (T)1;
+    const bool rot = h2 && h1;  // second step: times i on the upper lanes of odd index
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      cpx<T> v = x[m];
+      cpx<T> t{partner<4>(v.x) + s4 * v.x, partner<4>(v.y) + s4 * v.y};
+      v = cpx<T>{t.x * wr - t.y * wi, t.x * wi + t.y * wr};
+      t = cpx<T>{partner<2>(v.x) + s2 * v.x, partner<2>(v.y) + s2 * v.y};
+      v = rot ? cpx<T>{-t.y, t.x} : t;
+      x[m] = cpx<T>{partner<1>(v.x) + s1 * v.x, partner<1>(v.y) + s1 * v.y};
+    }
+    const int i2 = bitrev3(l);
+#pragma unroll
+    for (int k = 1; k < R; ++k) x[k] = cmulc(x[k], tw[i2 * k]);
+    Dft<R, 1, T>::run(x);
+  }
+  // inverse stage (twiddles, then butterfly) from LDS rows of stride SX into x
+  template <int SX>
+  __device__ static void inv_from_lds(const cpx<T>* s, const cpx<T>* tw, int tid, cpx<T> (&x)[IT][R]) {
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+      if (!owns(tid, it)) continue;
+      const int b = tid + it * NT;
+      const int r = b / SPAN, i2 = b - r * SPAN, f = row(r);
+#pragma unroll
+      for (int m = 0; m < R; ++m) x[it][m] = s[f * SX + i2 + m * SPAN];
+      if (SPAN > 1) {
+#pragma unroll
+        for (int k = 1; k < R; ++k) x[it][k] = cmulc(x[it][k], tw[i2 * k]);
+      }
+      Dft<R, 1, T>::run(x[it]);
+    }
+  }
+};
+
 // Launch shapes per edge: plane passes (threads), pencil pass (x tile,
 // threads), second and third pencil-pass shapes (half the x tile; whole x
 // rows, the longest contiguous runs in HBM), a second thread

@@ -42,7 +42,7 @@ static fx_status check_config(const fx_cell* cell, const fx_vx_config& c) {
   if (c.work_mb < 0 || c.work_mb > (1 << 20)) FX_FAIL(FX_ERR_INVALID, "work_mb = %d out of range", c.work_mb);
   if (c.a_prefetch < -1 || c.a_prefetch > 1) FX_FAIL(FX_ERR_INVALID, "a_prefetch = %d not in {-1, 0, 1}", c.a_prefetch);
   if (c.b_variant < 0 || c.b_variant > 4) FX_FAIL(FX_ERR_INVALID, "b_variant = %d not in {0, ..., 4}", c.b_variant);
-  if (c.c_variant < 0 || c.c_variant > 4) FX_FAIL(FX_ERR_INVALID, "c_variant = %d not in {0, ..., 4}", c.c_variant);
+  if (c.c_variant < 0 || c.c_variant > 5) FX_FAIL(FX_ERR_INVALID, "c_variant = %d not in {0, ..., 5}", c.c_variant);
   if (c.a_variant < 0 || c.a_variant > 2) FX_FAIL(FX_ERR_INVALID, "a_variant = %d not in {0, 1, 2}", c.a_variant);
   if (c.nt_hint < -1 || c.nt_hint > 1) FX_FAIL(FX_ERR_INVALID, "nt_hint = %d not in {-1, 0, 1}", c.nt_hint);
   if (c.b_xtile < 0 || c.b_xtile > cell->n[0]) FX_FAIL(FX_ERR_INVALID, "b_xtile = %d not in [0, n_x]", c.b_xtile);
@@ -310,7 +310,7 @@ static fx_status autotune(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* ker
   cur.kernels = spec ? 1 : 2;
   cur.a_prefetch = 0;
   cur.b_variant = spec ? (cell->n[0] == 96 ? 4 : (cell->n[0] == 72 ? 3 : 1)) : 0;
-  cur.c_variant = spec ? (cell->n[0] == 96 || cell->n[0] == 72 ? 2 : 1) : 0;
+  cur.c_variant = spec ? (cell->n[0] == 96 || cell->n[0] == 72 ? 5 : 1) : 0;
   cur.a_variant = spec ? 1 : 0;
   cur.nt_hint = spec ? 1 : 0;
   rs = trial(cur);
@@ -340,7 +340,7 @@ static fx_status autotune(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* ker
       rs = trial(c);
     }
     const fx_vx_config cstart = cur;
-    for (int cv = 1; cv <= 4 && rs == FX_OK; ++cv) {
+    for (int cv = 1; cv <= 5 && rs == FX_OK; ++cv) {
       if (cv == cstart.c_variant) continue;
       fx_vx_config c = cstart;
       c.c_variant = cv;

@@ -322,13 +322,15 @@ __global__ void __launch_bounds__(NT) k_pass_b_pt(cpx<T>* __restrict__ work, con
 // runs over its k in ascending order, adding psi_{m0+kk} * conj(v_{jk}),
 // which is v_{kj} since the kernel is real and even.  On a diagonal batch
 // (tri) role 0 takes jj <= kk and role 1 kk > jj.
-// STG: the next work plane (this item's next term, or the next item's first)
+// FORM 0: the plain form; 1 (STG): the next work plane (this item's next
+// term, or the next item's first)
 // is copied into a second LDS buffer while the current one is transformed, so
 // the first inverse stage reads LDS instead of waiting on HBM with the whole
 // workgroup (one workgroup per CU at 96^2, where the registers of the
 // accumulators leave LDS to spare).  At 96^3 it measured slightly slower than
-// the plain form (3.19 vs 3.13 ms per launch): a tuner candidate.
-template <typename T, typename A, int N, bool CONJ, int NT, bool NTS, bool STG>
+// the plain form (3.19 vs 3.13 ms per launch): a tuner candidate.  FORM 2
+// (WX): the inverse x transform across the lanes of a wave (RowStage).
+template <typename T, typename A, int N, bool CONJ, int NT, bool NTS, int FORM>
 __global__ void __launch_bounds__(NT) k_pass_c_ct(const cpx<T>* __restrict__ mult, int64_t ld_mult,
                                                                   const cpx<T>* __restrict__ work, int nj, int nk,
                                                                   int tri, int m0, int t0, int nitems, cpx<A>* acc,
@@ -337,6 +339,7 @@ __global__ void __launch_bounds__(NT) k_pass_c_ct(const cpx<T>* __restrict__ mul
                                                                   int zsplit, TrajSegs segs) {
   constexpr int NXY = N * N, SX = N + 1, EPT = CeilDiv<NXY, NT>::value;
   constexpr size_t NR = (size_t)NXY * N;
+  constexpr bool STG = FORM == 1, WX = FORM == 2;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* s = reinterpret_cast<cpx<T>*>(smem_raw);
   cpx<T>* tw = s + N * SX;
@@ -359,10 +362,86 @@ __global__ void __launch_bounds__(NT) k_pass_c_ct(const cpx<T>* __restrict__ mul
   // its registers are not live through the y stages beside the accumulators
   // (loaded early it spills at 96^2)
   constexpr bool kLateOrbital = sizeof(T) == 8;
+  // FP32 plain form with one last-stage butterfly per thread (96^2 at 768
+  // threads, 72^2 at 576): the last inverse x stage accumulates from its
+  // registers (RowStage), and the sums are held at the plane positions that
+  // stage leaves in each thread.  At 96^3 this took the pass from 3.06 to
+  // 2.79 ms per launch.  With more butterflies than threads, or idle threads,
+  // the extra accumulators cost more registers than the saved LDS round trip
+  // and barrier are worth.
+  // WX: the whole inverse x transform in registers and across lanes
+  // (RowStage::inv_x_wave): one LDS pass and one barrier fewer again.
+  using LX = RowStage<T, N, NT>;
+  constexpr bool kRegX = sizeof(T) == 4 && !STG && LX::TOTAL == NT;
+  static_assert(!WX || (kRegX && LX::kWave), "wave-level form: FP32, 72^2 or 96^2, one butterfly per thread");
+  // plane position of value m of butterfly it of this thread in the register form
+  auto rpos = [&](int it, int m) __attribute__((always_inline)) {
+    return WX ? LX::wave_pos(tid, m) : LX::pos(tid, it, m);
+  };
   for (int li = im.first; li < im.total; li += im.step) {
     int tt, z;
     im.at(li, &tt, &z);
     const int t = t0 + tt;
+    if constexpr (kRegX) {
+      cpx<A> a[LX::IT][LX::R];
+      cpx<T> vp[LX::IT][LX::R];
+#pragma unroll
+      for (int it = 0; it < LX::IT; ++it)
+#pragma unroll
+        for (int m = 0; m < LX::R; ++m) {
+          a[it][m] = cpx<A>{0, 0};
+          if (!first && LX::owns(tid, it)) a[it][m] = acc[t * ld_acc + (size_t)z * NXY + rpos(it, m)];
+        }
+      int lo, hi;
+      range(tt, &lo, &hi);
+      for (int l = lo; l < hi; ++l) {
+        const cpx<T>* pm = seg_psi<T>(segs, mult, t) + (int64_t)(m0 + l) * ld_mult + (size_t)z * NXY;
+        constexpr int R0 = Plan2<N>::R0, R1 = Plan2<N>::R1;
+        ct_stage_io<R1, false, T, N, R1, N, SX, 1, NT, true, false, N, 1, NTS>(s, plane_ptr(tt, l, z), nullptr, tw,
+                                                                              tid);
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < LX::IT; ++it)
+#pragma unroll
+          for (int m = 0; m < LX::R; ++m)
+            if (LX::owns(tid, it)) vp[it][m] = pm[rpos(it, m)];
+        ct_stage<R0, false, T, N, N, N, SX, 1, NT>(s, tw, tid);
+        __syncthreads();
+        cpx<T> x[LX::IT][LX::R];
+        if constexpr (WX) {
+          LX::template inv_x_wave<SX>(s, tw, tid, x[0]);
+        } else {
+          ct_stage<R1, false, T, N, R1, N, 1, SX, NT>(s, tw, tid);
+          __syncthreads();
+          LX::template inv_from_lds<SX>(s, tw, tid, x);
+        }
+#pragma unroll
+        for (int it = 0; it < LX::IT; ++it)
+#pragma unroll
+          for (int m = 0; m < LX::R; ++m)
+            if (LX::owns(tid, it)) {
+              const cpx<A> va{(A)x[it][m].x, CONJ ? -(A)x[it][m].y : (A)x[it][m].y};
+              a[it][m] = cfma(a[it][m], cpx<A>{(A)vp[it][m].x, (A)vp[it][m].y}, va);
+            }
+        __syncthreads();  // the last stage's reads before the next term's writes of s
+      }
+#pragma unroll
+      for (int it = 0; it < LX::IT; ++it)
+#pragma unroll
+        for (int m = 0; m < LX::R; ++m) {
+          if (!LX::owns(tid, it)) continue;
+          const size_t off = (size_t)z * NXY + rpos(it, m);
+          if (last) {
+            if (out_c64)
+              reinterpret_cast<cpx<float>*>(out)[t * ld_out + off] = cpx<float>{(float)a[it][m].x, (float)a[it][m].y};
+            else
+              reinterpret_cast<cpx<double>*>(out)[t * ld_out + off] = cpx<double>{(double)a[it][m].x, (double)a[it][m].y};
+          } else {
+            acc[t * ld_acc + off] = a[it][m];
+          }
+        }
+      continue;
+    }
     cpx<A> a[EPT];
     cpx<T> vp[EPT];
 #pragma unroll
@@ -582,12 +661,12 @@ constexpr size_t pass_c_lds(bool stg) {
   return ((size_t)N * (N + 1) + N + (stg ? (size_t)N * N : 0)) * sizeof(cpx<T>);
 }
 
-template <typename T, typename A, int N, int NT, bool STG>
+template <typename T, typename A, int N, int NT, int FORM>
 static fx_status pass_c_shape(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b, const CtAcc<A>& c, int role) {
-  const size_t lds = pass_c_lds<T, N>(STG);
+  const size_t lds = pass_c_lds<T, N>(FORM == 1);
   const int items = (role ? b.nj : b.nk) * N;
-  auto kern = role ? (b.nts ? k_pass_c_ct<T, A, N, true, NT, true, STG> : k_pass_c_ct<T, A, N, true, NT, false, STG>)
-                   : (b.nts ? k_pass_c_ct<T, A, N, false, NT, true, STG> : k_pass_c_ct<T, A, N, false, NT, false, STG>);
+  auto kern = role ? (b.nts ? k_pass_c_ct<T, A, N, true, NT, true, FORM> : k_pass_c_ct<T, A, N, true, NT, false, FORM>)
+                   : (b.nts ? k_pass_c_ct<T, A, N, false, NT, true, FORM> : k_pass_c_ct<T, A, N, false, NT, false, FORM>);
   int grid = 0;
   FX_TRY(ct_prepare(ctx, kern, NT, lds, items, true, &grid));
   if (role)
@@ -607,10 +686,14 @@ static fx_status pass_c_n(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b, cons
   using S = CubeShape<N>;
   // the staged forms where the second plane fits the LDS (not FP64 at 72 and 96)
   constexpr bool kStg = pass_c_lds<T, N>(true) <= kLdsPerCu;
-  if (b.c_var == 3 && kStg) return pass_c_shape<T, A, N, S::NT_C2, kStg>(ctx, st, b, c, role);
-  if (b.c_var == 4 && kStg) return pass_c_shape<T, A, N, S::NT_P, kStg>(ctx, st, b, c, role);
-  if (b.c_var == 2 || b.c_var == 3) return pass_c_shape<T, A, N, S::NT_C2, false>(ctx, st, b, c, role);
-  return pass_c_shape<T, A, N, S::NT_P, false>(ctx, st, b, c, role);
+  // the wave-level form: FP32 at 72 and 96, with the larger thread count
+  constexpr bool kWx = sizeof(T) == 4 && RowStage<T, N, S::NT_C2>::kWave;
+  if constexpr (kWx)
+    if (b.c_var == 5) return pass_c_shape<T, A, N, S::NT_C2, 2>(ctx, st, b, c, role);
+  if (b.c_var == 3 && kStg) return pass_c_shape<T, A, N, S::NT_C2, kStg ? 1 : 0>(ctx, st, b, c, role);
+  if (b.c_var == 4 && kStg) return pass_c_shape<T, A, N, S::NT_P, kStg ? 1 : 0>(ctx, st, b, c, role);
+  if (b.c_var == 2 || b.c_var == 3 || b.c_var == 5) return pass_c_shape<T, A, N, S::NT_C2, 0>(ctx, st, b, c, role);
+  return pass_c_shape<T, A, N, S::NT_P, 0>(ctx, st, b, c, role);
 }
 
 template <typename T>
