@@ -316,6 +316,31 @@ struct RowStage {
     constexpr int ctrl = H == 1 ? 0xB1 : (H == 2 ? 0x4E : 0x128);  // quad_perm [1,0,3,2], [2,3,0,1]; row_ror:8
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), ctrl, 0xF, 0xF, false));
   }
+  // Radix-8 DFTs (sign S) across the 8 lanes of each row, one per value of
+  // x, decimation in frequency: lane l holds input l of each DFT and ends with
+  // output bitrev3(l).  At index distance H the lower lane of a pair keeps
+  // a + b and the upper one (a - b) w^((l mod H) 4 / H), w = exp(S 2 pi i / 8).
+  template <int S>
+  __device__ static void lane_dft8(cpx<T> (&x)[R], int l) {
+    const T c = (T)0.70710678118654752440084436210484903928;
+    const bool h4 = l & 4, h2 = l & 2, h1 = l & 1;
+    // twiddles of the first step: w^(l mod 4) on the upper lanes
+    const int e = l & 3;
+    const T wr = !h4 ? (T)1 : (e == 0 ? (T)1 : (e == 1 ? c : (e == 2 ? (T)0 : -c)));
+    const T wi = !h4 ? (T)0 : (e == 0 ? (T)0 : (e == 2 ? (T)S : (T)S * c));
+    const T s4 = h4 ? (T)-1 : (T)1, s2 = h2 ? (T)-1 : (T)1, s1 = h1 ? (T)-1 : (T)1;
+    const bool rot = h2 && h1;  // second step: times w^2 = S i on the upper lanes of odd index
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+      cpx<T> v = x[m];
+      cpx<T> t{partner<4>(v.x) + s4 * v.x, partner<4>(v.y) + s4 * v.y};
+      v = cpx<T>{t.x * wr - t.y * wi, t.x * wi + t.y * wr};
+      t = cpx<T>{partner<2>(v.x) + s2 * v.x, partner<2>(v.y) + s2 * v.y};
+      v = rot ? (S > 0 ? cpx<T>{-t.y, t.x} : cpx<T>{t.y, -t.x}) : t;
+      x[m] = cpx<T>{partner<1>(v.x) + s1 * v.x, partner<1>(v.y) + s1 * v.y};
+    }
+  }
+  // inverse row transform: LDS rows of stride SX -> x at wave_pos(tid, m)
   template <int SX>
   __device__ static void inv_x_wave(const cpx<T>* s, const cpx<T>* tw, int tid, cpx<T> (&x)[R]) {
     static_assert(kWave, "wave-level row transform needs R1 = N / R0 = 8 and one butterfly per thread");
@@ -323,30 +348,31 @@ struct RowStage {
     wave_lane(tid, &f, &l);
 #pragma unroll
     for (int m = 0; m < R; ++m) x[m] = s[f * SX + l + m * SPAN];
-    // radix-8 inverse DFT across the lanes, decimation in frequency: at index
-    // distance H the lower lane keeps a + b, the upper one (a - b) w^(l mod H)
-    // with w = exp(2 pi i H' / 8), H' = 4 / H
-    const T c = (T)0.70710678118654752440084436210484903928;
-    const bool h4 = l & 4, h2 = l & 2, h1 = l & 1;
-    // twiddles of the first step: exp(2 pi i (l mod 4) / 8) on the upper lanes
-    const int e = l & 3;
-    const T wr = !h4 ? (T)1 : (e == 0 ? (T)1 : (e == 1 ? c : (e == 2 ? (T)0 : -c)));
-    const T wi = !h4 ? (T)0 : (e == 0 ? (T)0 : (e == 2 ? (T)1 : c));
-    const T s4 = h4 ? (T)-1 : (T)1, s2 = h2 ? (T)-1 : (T)1, s1 = h1 ? (T)-1 : (T)1;
-    const bool rot = h2 && h1;  // second step: times i on the upper lanes of odd index
-#pragma unroll
-    for (int m = 0; m < R; ++m) {
-      cpx<T> v = x[m];
-      cpx<T> t{partner<4>(v.x) + s4 * v.x, partner<4>(v.y) + s4 * v.y};
-      v = cpx<T>{t.x * wr - t.y * wi, t.x * wi + t.y * wr};
-      t = cpx<T>{partner<2>(v.x) + s2 * v.x, partner<2>(v.y) + s2 * v.y};
-      v = rot ? cpx<T>{-t.y, t.x} : t;
-      x[m] = cpx<T>{partner<1>(v.x) + s1 * v.x, partner<1>(v.y) + s1 * v.y};
-    }
+    lane_dft8<1>(x, l);
     const int i2 = bitrev3(l);
 #pragma unroll
     for (int k = 1; k < R; ++k) x[k] = cmulc(x[k], tw[i2 * k]);
     Dft<R, 1, T>::run(x);
+  }
+  // forward row transform: x, the row's values at fwd_pos(tid, m), -> LDS rows
+  // of stride SX (the same digit-reversed order as the two LDS stages)
+  FX_HD static int fwd_pos(int tid, int m) {
+    int f, l;
+    wave_lane(tid, &f, &l);
+    return f * N + l + m * SPAN;
+  }
+  template <int SX>
+  __device__ static void fwd_x_wave(cpx<T> (&x)[R], cpx<T>* s, const cpx<T>* tw, int tid) {
+    static_assert(kWave, "wave-level row transform needs R1 = N / R0 = 8 and one butterfly per thread");
+    int f, l;
+    wave_lane(tid, &f, &l);
+    Dft<R, -1, T>::run(x);
+#pragma unroll
+    for (int k = 1; k < R; ++k) x[k] = cmul(x[k], tw[l * k]);
+    lane_dft8<-1>(x, l);
+    const int j = bitrev3(l);
+#pragma unroll
+    for (int m = 0; m < R; ++m) s[f * SX + 8 * m + j] = x[m];
   }
   // inverse stage (twiddles, then butterfly) from LDS rows of stride SX into x
   template <int SX>

@@ -43,7 +43,7 @@ static fx_status check_config(const fx_cell* cell, const fx_vx_config& c) {
   if (c.a_prefetch < -1 || c.a_prefetch > 1) FX_FAIL(FX_ERR_INVALID, "a_prefetch = %d not in {-1, 0, 1}", c.a_prefetch);
   if (c.b_variant < 0 || c.b_variant > 4) FX_FAIL(FX_ERR_INVALID, "b_variant = %d not in {0, ..., 4}", c.b_variant);
   if (c.c_variant < 0 || c.c_variant > 5) FX_FAIL(FX_ERR_INVALID, "c_variant = %d not in {0, ..., 5}", c.c_variant);
-  if (c.a_variant < 0 || c.a_variant > 2) FX_FAIL(FX_ERR_INVALID, "a_variant = %d not in {0, 1, 2}", c.a_variant);
+  if (c.a_variant < 0 || c.a_variant > 3) FX_FAIL(FX_ERR_INVALID, "a_variant = %d not in {0, ..., 3}", c.a_variant);
   if (c.nt_hint < -1 || c.nt_hint > 1) FX_FAIL(FX_ERR_INVALID, "nt_hint = %d not in {-1, 0, 1}", c.nt_hint);
   if (c.b_xtile < 0 || c.b_xtile > cell->n[0]) FX_FAIL(FX_ERR_INVALID, "b_xtile = %d not in [0, n_x]", c.b_xtile);
   if (c.b_threads != 0 && (c.b_threads < 64 || c.b_threads > 256 || c.b_threads % 64))
@@ -346,9 +346,9 @@ static fx_status autotune(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* ker
       c.c_variant = cv;
       rs = trial(c);
     }
-    if (rs == FX_OK) {
+    for (int av = 2; av <= 3 && rs == FX_OK; ++av) {
       fx_vx_config c = cur;
-      c.a_variant = 2;
+      c.a_variant = av;
       rs = trial(c);
     }
     if (rs == FX_OK) {

@@ -57,7 +57,8 @@ struct VxArgs {
   int b_var = 0;    // specialised z pass tile: 1 default, 2 half, 3 whole rows, 4 persistent, 0 automatic
   int c_var = 0;    // specialised plane-inverse form: 1 default, 2 second thread count, 3/4 those with the
                     // next plane staged in LDS, 0 automatic
-  int a_var = 0;    // specialised plane-forward threads: 1 default, 2 second count, 0 automatic
+  int a_var = 0;    // specialised plane-forward threads: 1 default, 2 second count, 3 that with the
+                    // wave-level x transform (FP32 at 72 and 96), 0 automatic
   int nt_hint = -1;  // specialised kernels: non-temporal hints on the pair volume (1, 0, -1 automatic = 1)
   bool plans_set = false;  // generic kernels: radix schedules in `plans`
   PlanSet plans;
@@ -107,7 +108,7 @@ struct CtBatch {
   int a_pipe;       // plane-forward pass: register prefetch of the next plane
   int b_var;        // z pass: 1 default x tile, 2 half tile, 3 whole x rows, 4 persistent (default tile)
   int c_var;        // plane-inverse pass: 1 default threads, 2 the second thread count, 3/4 staged
-  int a_var;        // plane-forward pass: 1 default threads, 2 the second thread count
+  int a_var;        // plane-forward pass: 1 default threads, 2 the second thread count, 3 wave-level x
   int nts;          // the pair volume is read and written with non-temporal hints
   int zsplit = 0;   // plane passes split over the XCDs by z (bit 0: forward, bit 1: inverse) or by unit
   TrajSegs segs;    // per-target orbital blocks (multi-trajectory launches; n == 0: psi for all)

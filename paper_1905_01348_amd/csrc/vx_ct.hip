@@ -90,7 +90,10 @@ struct PassAWaves {
   static constexpr int value = (sizeof(T) == 4 && !PIPE) ? (NT > 512 ? 6 : 4) : 1;
 };
 
-template <typename T, int N, bool PIPE, int NT, bool NTS>
+// WX: the product formed in the registers of a wave-level forward x
+// transform (RowStage::fwd_x_wave; FP32 at 72^2 and 96^2 with one row
+// butterfly per thread), whose results go to LDS once for the y transform.
+template <typename T, int N, bool PIPE, int NT, bool NTS, bool WX = false>
 __global__ void __launch_bounds__(NT, (PassAWaves<T, PIPE, NT>::value)) k_pass_a_ct(const cpx<T>* __restrict__ psi, int64_t ld_psi,
                                                                   const cpx<T>* __restrict__ phi, int64_t ld_phi,
                                                                   cpx<T>* __restrict__ work, int j0, int nj, int k0,
@@ -124,6 +127,34 @@ __global__ void __launch_bounds__(NT, (PassAWaves<T, PIPE, NT>::value)) k_pass_a
   };
   constexpr bool kPipe = PIPE;
   int li = im.first;
+  if constexpr (WX) {
+    using RS = RowStage<T, N, NT>;
+    static_assert(RS::kWave && sizeof(T) == 4 && !PIPE, "wave-level form: FP32, 72^2 or 96^2, one butterfly per thread");
+    __syncthreads();  // twiddles
+    for (; li < im.total; li += im.step) {
+      int p, z;
+      im.at(li, &p, &z);
+      int jj, kk;
+      pair_of(p, nj, tri, &jj, &kk);
+      const cpx<T>* a = seg_psi<T>(segs, psi, k0 + kk) + (int64_t)(j0 + jj) * ld_psi + (size_t)z * NXY;
+      const cpx<T>* b = phi + (int64_t)(k0 + kk) * ld_phi + (size_t)z * NXY;
+      cpx<T> x[RS::R];
+#pragma unroll
+      for (int m = 0; m < RS::R; ++m) {
+        const int e = RS::fwd_pos(tid, m);
+        x[m] = cconjmul(a[e], b[e]);
+      }
+      RS::template fwd_x_wave<SX>(x, s, tw, tid);
+      __syncthreads();
+      constexpr int R0 = Plan2<N>::R0, R1 = Plan2<N>::R1;
+      ct_stage<R0, true, T, N, N, N, SX, 1, NT>(s, tw, tid);
+      __syncthreads();
+      cpx<T>* o = work + p * NR + (size_t)z * NXY;
+      ct_stage_io<R1, true, T, N, R1, N, SX, 1, NT, false, true, N, 1, NTS>(s, nullptr, o, tw, tid);
+      __syncthreads();
+    }
+    return;
+  }
   if (kPipe) fetch(li);
   for (; li < im.total; li += im.step) {
     if (!kPipe) fetch(li);
@@ -578,13 +609,14 @@ static fx_status ct_prepare(fx_ctx* ctx, K kernel, int nthr, size_t lds, int ite
   return FX_OK;
 }
 
-template <typename T, int N, int NT>
+template <typename T, int N, int NT, bool WX = false>
 static fx_status pass_a_shape(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b) {
   const size_t lds = ((size_t)N * (N + 1) + N) * sizeof(cpx<T>);
   // the prefetching form exists for FP32 only (FP64 has no registers to spare)
-  const bool pipe = sizeof(T) == 4 && b.a_pipe;
-  auto kern = pipe ? (b.nts ? k_pass_a_ct<T, N, sizeof(T) == 4, NT, true> : k_pass_a_ct<T, N, sizeof(T) == 4, NT, false>)
-                   : (b.nts ? k_pass_a_ct<T, N, false, NT, true> : k_pass_a_ct<T, N, false, NT, false>);
+  const bool pipe = sizeof(T) == 4 && b.a_pipe && !WX;
+  auto kern = WX ? (b.nts ? k_pass_a_ct<T, N, false, NT, true, WX> : k_pass_a_ct<T, N, false, NT, false, WX>)
+              : pipe ? (b.nts ? k_pass_a_ct<T, N, sizeof(T) == 4, NT, true> : k_pass_a_ct<T, N, sizeof(T) == 4, NT, false>)
+                     : (b.nts ? k_pass_a_ct<T, N, false, NT, true> : k_pass_a_ct<T, N, false, NT, false>);
   const int items = b.npairs * N;
   int grid = 0;
   FX_TRY(ct_prepare(ctx, kern, NT, lds, items, true, &grid));
@@ -597,7 +629,10 @@ static fx_status pass_a_shape(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b) 
 template <typename T, int N>
 static fx_status pass_a_n(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b) {
   using S = CubeShape<N>;
-  if (b.a_var == 2) return pass_a_shape<T, N, S::NT_A2>(ctx, st, b);
+  // the wave-level form: FP32 at 72 and 96, with the second thread count
+  if constexpr (sizeof(T) == 4 && RowStage<T, N, S::NT_A2>::kWave)
+    if (b.a_var == 3) return pass_a_shape<T, N, S::NT_A2, true>(ctx, st, b);
+  if (b.a_var == 2 || b.a_var == 3) return pass_a_shape<T, N, S::NT_A2>(ctx, st, b);
   return pass_a_shape<T, N, S::NT_P>(ctx, st, b);
 }
 

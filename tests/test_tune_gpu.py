@@ -71,7 +71,7 @@ def test_specialised_variants_match(ctx, n):
     P, Q = dev(psi), dev(phi)
     refs = {False: oracle.apply_vx(psi, phi, n, L, "hse", 0.106), True: oracle.apply_vx(psi, psi, n, L, "hse", 0.106)}
     shapes = [{"a_prefetch": 1}, {"b_variant": 2}, {"b_variant": 3}, {"b_variant": 4}, {"c_variant": 1}, {"c_variant": 2}, {"c_variant": 3}, {"c_variant": 4},
-              {"c_variant": 5}, {"a_variant": 2},
+              {"c_variant": 5}, {"a_variant": 2}, {"a_variant": 3},
               {"nt_hint": 1},
               {"a_prefetch": 1, "a_variant": 2, "b_variant": 2, "c_variant": 2}]
     close = {"fp64": 1e-13, "fp32acc64": 1e-6, "fp32": 1e-6}
