@@ -393,6 +393,10 @@ __global__ void __launch_bounds__(NT) k_pass_c_ct(const cpx<T>* __restrict__ mul
   // its registers are not live through the y stages beside the accumulators
   // (loaded early it spills at 96^2)
   constexpr bool kLateOrbital = sizeof(T) == 8;
+  // of those, the values loaded before the last x stage: half, the other half
+  // once the stage's registers are free (all of them beside the stage spilled
+  // 164 bytes per lane at 96^2, half of them 132; 2.73 -> 2.51 ms per launch)
+  constexpr int kEarly = (kLateOrbital && !STG) ? (EPT + 1) / 2 : EPT;
   // FP32 plain form with one last-stage butterfly per thread (96^2 at 768
   // threads, 72^2 at 576): the last inverse x stage accumulates from its
   // registers (RowStage), and the sums are held at the plane positions that
@@ -536,7 +540,7 @@ __global__ void __launch_bounds__(NT) k_pass_c_ct(const cpx<T>* __restrict__ mul
       __syncthreads();
       if (!STG && kLateOrbital) {
 #pragma unroll
-        for (int i = 0; i < EPT; ++i) {
+        for (int i = 0; i < kEarly; ++i) {
           const int e = tid + i * NT;
           if (NXY % NT == 0 || e < NXY) vp[i] = pm[e];
         }
@@ -546,6 +550,15 @@ __global__ void __launch_bounds__(NT) k_pass_c_ct(const cpx<T>* __restrict__ mul
 #pragma unroll
       for (int i = 0; i < EPT; ++i) {
         const int e = tid + i * NT;
+        // FP64: the second half of the orbital values, once the last stage's
+        // registers are free
+        if (!STG && kLateOrbital && i == kEarly) {
+#pragma unroll
+          for (int i2 = kEarly; i2 < EPT; ++i2) {
+            const int e2 = tid + i2 * NT;
+            if (NXY % NT == 0 || e2 < NXY) vp[i2] = pm[e2];
+          }
+        }
         if (NXY % NT == 0 || e < NXY) {
           const cpx<T> v = s[(e / N) * SX + e % N];
           const cpx<A> va{(A)v.x, CONJ ? -(A)v.y : (A)v.y};
