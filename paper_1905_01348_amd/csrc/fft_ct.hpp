@@ -206,6 +206,69 @@ FX_HD void ct_stage_io(cpx<T>* s, const cpx<T>* gin, cpx<T>* gout, const cpx<T>*
   ct_bfly_store<R, T, N, L, COUNT, NTHR, TO_G, GES, GFS, ES, FS, NTS>(x, TO_G ? gout : s, tid);
 }
 
+// ct_stage_io for a stage of span 1 (L = R) over COUNT transforms that are
+// adjacent columns (transform f at offset f, GFS = FS = 1), FP32: a thread
+// takes the butterflies of two adjacent transforms f, f + 1 and moves their
+// global values in 16-byte accesses (the global rows must be 16-byte
+// aligned, GES even).  The arithmetic is that of ct_stage_io.  kFits: one
+// pair of butterflies per thread at most, so the stage is no longer than the
+// unpaired one (which deals COUNT N / R butterflies over NTHR threads).
+template <typename T>
+struct Vec4;
+template <>
+struct Vec4<float> {
+  typedef float type __attribute__((ext_vector_type(4)));
+};
+template <int R, int N, int COUNT, int NTHR>
+struct PairIO {
+  static constexpr int HALF = COUNT / 2, TOTAL = HALF * (N / R);
+  static constexpr bool kFits = COUNT % 2 == 0 && TOTAL <= NTHR;
+};
+template <int R, bool FWD, typename T, int N, int COUNT, int ES, int NTHR, bool FROM_G, bool TO_G, int GES, bool NTS>
+FX_HD void ct_stage_io_pair(cpx<T>* s, const cpx<T>* gin, cpx<T>* gout, int tid) {
+  using P = PairIO<R, N, COUNT, NTHR>;
+  static_assert(sizeof(T) == 4 && P::kFits && GES % 2 == 0, "paired stage: FP32, even count, one pair per thread");
+  typedef typename Vec4<T>::type V;
+  const int b = tid;
+  if (P::TOTAL % NTHR != 0 && b >= P::TOTAL) return;
+  const int f = 2 * (b % P::HALF), blk = b / P::HALF;
+  cpx<T> x0[R], x1[R];
+#pragma unroll
+  for (int m = 0; m < R; ++m) {
+    const int pos = blk * R + m;
+    if (FROM_G) {
+      const V* p = reinterpret_cast<const V*>(gin + f + pos * GES);
+      const V v = NTS ? __builtin_nontemporal_load(p) : *p;
+      x0[m] = cpx<T>{v.x, v.y};
+      x1[m] = cpx<T>{v.z, v.w};
+    } else {
+      x0[m] = s[f + pos * ES];
+      x1[m] = s[f + 1 + pos * ES];
+    }
+  }
+  Dft<R, FWD ? -1 : 1, T>::run(x0);
+  Dft<R, FWD ? -1 : 1, T>::run(x1);
+#pragma unroll
+  for (int m = 0; m < R; ++m) {
+    const int pos = blk * R + m;
+    if (TO_G) {
+      V v;
+      v.x = x0[m].x;
+      v.y = x0[m].y;
+      v.z = x1[m].x;
+      v.w = x1[m].y;
+      V* p = reinterpret_cast<V*>(gout + f + pos * GES);
+      if (NTS)
+        __builtin_nontemporal_store(v, p);
+      else
+        *p = v;
+    } else {
+      s[f + pos * ES] = x0[m];
+      s[f + 1 + pos * ES] = x1[m];
+    }
+  }
+}
+
 // Full forward or inverse transform along one axis (two stages + barriers).
 template <bool FWD, typename T, int N, int COUNT, int ES, int FS, int NTHR>
 __device__ inline void ct_fft(cpx<T>* s, const cpx<T>* tw, int tid) {

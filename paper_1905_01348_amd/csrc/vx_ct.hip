@@ -93,7 +93,9 @@ struct PassAWaves {
 // WX: the product formed in the registers of a wave-level forward x
 // transform (RowStage::fwd_x_wave; FP32 at 72^2 and 96^2 with one row
 // butterfly per thread), whose results go to LDS once for the y transform.
-template <typename T, int N, bool PIPE, int NT, bool NTS, bool WX = false>
+// VEC: FP32 inputs 16-byte aligned with even leading dimensions (checked on
+// the host): each thread loads two consecutive plane values at a time.
+template <typename T, int N, bool PIPE, int NT, bool NTS, bool WX = false, bool VEC = false>
 __global__ void __launch_bounds__(NT, (PassAWaves<T, PIPE, NT>::value)) k_pass_a_ct(const cpx<T>* __restrict__ psi, int64_t ld_psi,
                                                                   const cpx<T>* __restrict__ phi, int64_t ld_phi,
                                                                   cpx<T>* __restrict__ work, int j0, int nj, int k0,
@@ -108,6 +110,13 @@ __global__ void __launch_bounds__(NT, (PassAWaves<T, PIPE, NT>::value)) k_pass_a
   for (int i = tid; i < N; i += NT) tw[i] = twg[i];
   cpx<T> va[EPT], vb[EPT];
   const ItemMap im = item_map<N>(nitems / N, zsplit);
+  // VEC with whole pairs of values per thread: each thread takes two
+  // consecutive plane values per load (16-byte loads, half the load
+  // instructions); value i of the thread is plane element elem(i)
+  constexpr bool kVec = VEC && sizeof(T) == 4 && NXY % (2 * NT) == 0;
+  auto elem = [&](int i) __attribute__((always_inline)) {
+    return kVec ? 2 * (tid + (i >> 1) * NT) + (i & 1) : tid + i * NT;
+  };
   auto fetch = [&](int li) __attribute__((always_inline)) {
     if (li >= im.total) return;
     int p, z;
@@ -116,9 +125,21 @@ __global__ void __launch_bounds__(NT, (PassAWaves<T, PIPE, NT>::value)) k_pass_a
     pair_of(p, nj, tri, &jj, &kk);
     const cpx<T>* a = seg_psi<T>(segs, psi, k0 + kk) + (int64_t)(j0 + jj) * ld_psi + (size_t)z * NXY;
     const cpx<T>* b = phi + (int64_t)(k0 + kk) * ld_phi + (size_t)z * NXY;
+    if constexpr (kVec) {
+#pragma unroll
+      for (int i = 0; i < EPT; i += 2) {
+        const float4 u = *reinterpret_cast<const float4*>(a + elem(i));
+        const float4 v = *reinterpret_cast<const float4*>(b + elem(i));
+        va[i] = cpx<T>{(T)u.x, (T)u.y};
+        va[i + 1] = cpx<T>{(T)u.z, (T)u.w};
+        vb[i] = cpx<T>{(T)v.x, (T)v.y};
+        vb[i + 1] = cpx<T>{(T)v.z, (T)v.w};
+      }
+      return;
+    }
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
-      const int e = tid + i * NT;
+      const int e = elem(i);
       if (NXY % NT == 0 || e < NXY) {
         va[i] = a[e];
         vb[i] = b[e];
@@ -150,7 +171,10 @@ __global__ void __launch_bounds__(NT, (PassAWaves<T, PIPE, NT>::value)) k_pass_a
       ct_stage<R0, true, T, N, N, N, SX, 1, NT>(s, tw, tid);
       __syncthreads();
       cpx<T>* o = work + p * NR + (size_t)z * NXY;
-      ct_stage_io<R1, true, T, N, R1, N, SX, 1, NT, false, true, N, 1, NTS>(s, nullptr, o, tw, tid);
+      if constexpr (sizeof(T) == 4 && PairIO<R1, N, N, NT>::kFits)
+        ct_stage_io_pair<R1, true, T, N, N, SX, NT, false, true, N, NTS>(s, nullptr, o, tid);
+      else
+        ct_stage_io<R1, true, T, N, R1, N, SX, 1, NT, false, true, N, 1, NTS>(s, nullptr, o, tw, tid);
       __syncthreads();
     }
     return;
@@ -160,7 +184,7 @@ __global__ void __launch_bounds__(NT, (PassAWaves<T, PIPE, NT>::value)) k_pass_a
     if (!kPipe) fetch(li);
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
-      const int e = tid + i * NT;
+      const int e = elem(i);
       if (NXY % NT == 0 || e < NXY) s[(e / N) * SX + e % N] = cconjmul(va[i], vb[i]);
     }
     __syncthreads();
@@ -173,7 +197,11 @@ __global__ void __launch_bounds__(NT, (PassAWaves<T, PIPE, NT>::value)) k_pass_a
     int p, z;
     im.at(li, &p, &z);
     cpx<T>* o = work + p * NR + (size_t)z * NXY;
-    ct_stage_io<R1, true, T, N, R1, N, SX, 1, NT, false, true, N, 1, NTS>(s, nullptr, o, tw, tid);
+    // FP32 with one pair of columns per thread: 16-byte stores
+    if constexpr (sizeof(T) == 4 && PairIO<R1, N, N, NT>::kFits)
+      ct_stage_io_pair<R1, true, T, N, N, SX, NT, false, true, N, NTS>(s, nullptr, o, tid);
+    else
+      ct_stage_io<R1, true, T, N, R1, N, SX, 1, NT, false, true, N, 1, NTS>(s, nullptr, o, tw, tid);
     __syncthreads();
   }
 }
@@ -432,6 +460,8 @@ __global__ void __launch_bounds__(NT) k_pass_c_ct(const cpx<T>* __restrict__ mul
       for (int l = lo; l < hi; ++l) {
         const cpx<T>* pm = seg_psi<T>(segs, mult, t) + (int64_t)(m0 + l) * ld_mult + (size_t)z * NXY;
         constexpr int R0 = Plan2<N>::R0, R1 = Plan2<N>::R1;
+        // (16-byte paired loads here measured slower: 3.08 against 2.76 ms
+        // per launch at 96^3, with a quarter of the threads idle in this stage)
         ct_stage_io<R1, false, T, N, R1, N, SX, 1, NT, true, false, N, 1, NTS>(s, plane_ptr(tt, l, z), nullptr, tw,
                                                                               tid);
         __syncthreads();
@@ -622,14 +652,29 @@ static fx_status ct_prepare(fx_ctx* ctx, K kernel, int nthr, size_t lds, int ite
   return FX_OK;
 }
 
+// Inputs that allow 16-byte loads of two plane values: FP32, every orbital
+// and target base 16-byte aligned, even leading dimensions (plane offsets are
+// even: N^2 is).
+template <typename T>
+static bool pass_a_vec_ok(const CtBatch<T>& b) {
+  if (sizeof(T) != 4 || (b.ld_psi & 1) || (b.ld_phi & 1)) return false;
+  uintptr_t bits = reinterpret_cast<uintptr_t>(b.psi) | reinterpret_cast<uintptr_t>(b.phi);
+  for (int i = 0; i < b.segs.n; ++i) bits |= reinterpret_cast<uintptr_t>(b.segs.psi[i]);
+  return (bits & 15) == 0;
+}
+
 template <typename T, int N, int NT, bool WX = false>
 static fx_status pass_a_shape(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b) {
   const size_t lds = ((size_t)N * (N + 1) + N) * sizeof(cpx<T>);
   // the prefetching form exists for FP32 only (FP64 has no registers to spare)
-  const bool pipe = sizeof(T) == 4 && b.a_pipe && !WX;
-  auto kern = WX ? (b.nts ? k_pass_a_ct<T, N, false, NT, true, WX> : k_pass_a_ct<T, N, false, NT, false, WX>)
-              : pipe ? (b.nts ? k_pass_a_ct<T, N, sizeof(T) == 4, NT, true> : k_pass_a_ct<T, N, sizeof(T) == 4, NT, false>)
-                     : (b.nts ? k_pass_a_ct<T, N, false, NT, true> : k_pass_a_ct<T, N, false, NT, false>);
+  constexpr bool F32 = sizeof(T) == 4;
+  const bool pipe = F32 && b.a_pipe && !WX;
+  const bool vec = F32 && !WX && pass_a_vec_ok(b);
+  auto kern = WX     ? (b.nts ? k_pass_a_ct<T, N, false, NT, true, WX> : k_pass_a_ct<T, N, false, NT, false, WX>)
+              : pipe ? (vec ? (b.nts ? k_pass_a_ct<T, N, F32, NT, true, false, F32> : k_pass_a_ct<T, N, F32, NT, false, false, F32>)
+                            : (b.nts ? k_pass_a_ct<T, N, F32, NT, true> : k_pass_a_ct<T, N, F32, NT, false>))
+                     : (vec ? (b.nts ? k_pass_a_ct<T, N, false, NT, true, false, F32> : k_pass_a_ct<T, N, false, NT, false, false, F32>)
+                            : (b.nts ? k_pass_a_ct<T, N, false, NT, true> : k_pass_a_ct<T, N, false, NT, false>));
   const int items = b.npairs * N;
   int grid = 0;
   FX_TRY(ct_prepare(ctx, kern, NT, lds, items, true, &grid));
