@@ -342,3 +342,51 @@ def test_empty_blocks_rejected(ctx):
         with pytest.raises(FockError) as ei:
             ctx.apply_vx(a, b, n=24, L=10.26, prec="fp64")
         assert ei.value.status == -1
+
+
+@pytest.mark.parametrize("n", [24, 96])
+def test_fp32_inputs_off_16_byte_alignment(ctx, n):
+    """FP32 orbitals and targets 16-byte aligned with even leading dimensions are read two
+    plane values per load; inputs 8 bytes off that alignment, or with an odd leading
+    dimension, take the 8-byte loads.  Both thread counts of the plane-forward pass (the
+    second one also stores two columns per lane), bitwise equal across the layouts and
+    within the FP32 tolerance of the oracle."""
+    import ctypes as C
+    import torch
+
+    from paper_1905_01348_amd import fock as F
+
+    L = n * 10.26 / 24
+    N, Nt = 3, 2
+    nr = n ** 3
+    psi = synth.make_orbitals(120 + n, n, L, N)
+    phi = synth.random_grid_vectors(121 + n, n, Nt)
+    ref = oracle.apply_vx(psi, phi, n, L, "hse", 0.106).reshape(Nt, nr)
+    p64 = psi.reshape(N, nr).astype(np.complex64)
+    q64 = phi.reshape(Nt, nr).astype(np.complex64)
+    cell, kern = F.make_cell(n, L), F.make_kernel("hse", 0.106)
+    lib = F.load()
+
+    def run(shift, pad):
+        ld = nr + pad
+        P = torch.zeros(N * ld + 2, dtype=torch.complex64, device="cuda")
+        Q = torch.zeros(Nt * ld + 2, dtype=torch.complex64, device="cuda")
+        P[shift:shift + N * ld].view(N, ld)[:, :nr] = dev(p64)
+        Q[shift:shift + Nt * ld].view(Nt, ld)[:, :nr] = dev(q64)
+        O = torch.empty((Nt, nr), dtype=torch.complex128, device="cuda")
+        st = lib.fx_apply_vx(ctx.h, C.byref(cell), C.byref(kern), P[shift:].data_ptr(), N, ld, Q[shift:].data_ptr(),
+                             Nt, ld, O.data_ptr(), nr, F.FX_C64, F.FX_C128, F.PREC["fp32acc64"],
+                             C.c_void_p(torch.cuda.current_stream().cuda_stream), None)
+        assert st == 0, lib.fx_last_error()
+        torch.cuda.synchronize()
+        return host(O)
+
+    for av in (1, 2):
+        ctx.set_vx_config({"kernels": 1, "a_variant": av}, n=n, L=L, prec="fp32acc64")
+        say("edge", n, "a_variant", av)
+        base = run(0, 0)  # aligned, even ld: 16-byte loads
+        assert rel_err(base, ref) <= TOL32
+        for shift, pad in ((1, 0), (0, 1), (1, 1)):  # 8 bytes off; odd ld; both
+            got = run(shift, pad)
+            assert np.array_equal(got.view(np.float64), base.view(np.float64)), (av, shift, pad)
+    ctx.set_vx_config(None, n=n, L=L, prec="fp32acc64")
