@@ -323,18 +323,20 @@ __device__ inline void ct_conv(cpx<T>* s, const cpx<T>* tw, KF kf, int tid) {
 // N, with butterfly b on row row(b / SPAN) and offset i2 = b % SPAN: the SPAN
 // lanes of a row hold the consecutive positions i2 + SPAN m of the row, so
 // global data at those plane positions is read or written in runs of SPAN
-// consecutive values.  The last inverse stage of the row transform leaves its
-// outputs in registers (inv_from_lds), which saves an LDS round trip of the
-// plane and a barrier.  x[it][m] is value m of butterfly it, at plane position
-// pos(tid, it, m).
+// consecutive values.  inv_from_lds: the last inverse stage of the row
+// transform leaves its outputs in registers, which saves an LDS round trip
+// of the plane and a barrier; x[it][m] is value m of butterfly it, at plane
+// position pos(tid, it, m).  inv_x_wave / fwd_x_wave: the whole row
+// transform in registers and across the lanes of a wave (edges 72 and 96).
 template <typename T, int N, int NT>
 struct RowStage {
   static constexpr int R = Plan2<N>::R0, SPAN = N / R, TOTAL = N * SPAN;
   static constexpr int IT = (TOTAL + NT - 1) / NT;  // butterflies per thread
-  // With rows of N + 1 values in LDS the value at offset i2 of row f sits in
-  // bank (f + i2) mod 32 at edges 72 and 96 (N + 1 = 1 or 9 mod 32, and 9 f
-  // runs over the same residues as f when f steps by 8): the four rows of a
-  // 32-lane group are taken 8 apart, so that their accesses hit distinct banks.
+  // LDS rows are N + 1 values long, so row f starts at 8-byte slot f (edge
+  // 96) or 9 f (edge 72) modulo the 32 slots a wave's 8-byte accesses spread
+  // over.  The four rows of a 32-lane group are taken 8 apart: their starts
+  // are then 8 slots apart (9 * 8 = 8 mod 32), and with the 8 offsets i2 of
+  // each row the 32 lanes fall on 32 distinct slots.
   FX_HD static int row(int r) {
     if (SPAN == 8 && r < N / 32 * 32) return (r & ~31) + 8 * (r & 3) + ((r >> 2) & 7);
     return r;
