@@ -102,11 +102,11 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="96cube_1024x32",
-                    choices=["24cube_16", "48cube_128", "96cube_1024x32", "serveC"],
+                    choices=["24cube_16", "48cube_128", "96cube_1024x32", "serveA", "serveB", "serveC"],
                     help="vx leg: 96cube_1024x32 (96^3, 1024 orbitals x 32 targets, the headline), the phi = Psi "
                          "workloads 24cube_16 (24^3, 16 orbitals, Coulomb) and 48cube_128 (48^3, 128 orbitals, HSE), "
-                         "which also time the ACE build and E_X, or serveC (72^3, 432 orbitals x 8 targets: one V_X "
-                         "request of the largest serving class)")
+                         "which also time the ACE build and E_X, or one V_X request of a serving class: serveA "
+                         "(24^3, 16 orbitals x 8 targets), serveB (48^3, 128 x 8), serveC (72^3, 432 x 8)")
     ap.add_argument("--prec", default="fp32acc64", choices=["fp32acc64", "fp32", "fp64"])
     ap.add_argument("--fp64-steps", type=int, default=2, help="timed FP64 steps for the comparison (0 = skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU oracle budget (0 = skip)")

@@ -236,6 +236,13 @@ typedef struct fx_vx_config {
   int32_t radix[3][4]; /* generic: radix schedule of each axis (x, y, z), stages in
                           order, 0-terminated; radices from {2,3,4,6,8,9,12} with
                           product n; an all-zero row is the default schedule */
+  int32_t c_split;     /* specialised plane-inverse pass: S sum groups per target (1, 2,
+                          4 or 8; 0 automatic = 1).  The terms of orbital j go to group
+                          j mod S, each group summed in ascending j, the groups added in
+                          order at the end: S times the pass's work items for calls with
+                          few targets, at S partial sums per target of device memory.
+                          The result depends on S (rounding) but not on the batch size
+                          or on which targets share a launch */
 } fx_vx_config;
 
 /*

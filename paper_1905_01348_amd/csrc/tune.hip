@@ -45,6 +45,8 @@ static fx_status check_config(const fx_cell* cell, const fx_vx_config& c) {
   if (c.c_variant < 0 || c.c_variant > 5) FX_FAIL(FX_ERR_INVALID, "c_variant = %d not in {0, ..., 5}", c.c_variant);
   if (c.a_variant < 0 || c.a_variant > 3) FX_FAIL(FX_ERR_INVALID, "a_variant = %d not in {0, ..., 3}", c.a_variant);
   if (c.nt_hint < -1 || c.nt_hint > 1) FX_FAIL(FX_ERR_INVALID, "nt_hint = %d not in {-1, 0, 1}", c.nt_hint);
+  if (c.c_split != 0 && c.c_split != 1 && c.c_split != 2 && c.c_split != 4 && c.c_split != 8)
+    FX_FAIL(FX_ERR_INVALID, "c_split = %d not in {0, 1, 2, 4, 8}", c.c_split);
   if (c.b_xtile < 0 || c.b_xtile > cell->n[0]) FX_FAIL(FX_ERR_INVALID, "b_xtile = %d not in [0, n_x]", c.b_xtile);
   if (c.b_threads != 0 && (c.b_threads < 64 || c.b_threads > 256 || c.b_threads % 64))
     FX_FAIL(FX_ERR_INVALID, "b_threads = %d must be 0 or a multiple of 64 in [64, 256]", c.b_threads);
@@ -67,6 +69,8 @@ static bool is_vx_prec(fx_prec p) { return p == FX_PREC_FP64 || p == FX_PREC_FP3
 // One configuration per line:
 //   fxcfg <device> <nx> <ny> <nz> <prec> <phi_is_psi> <kernels> <work_mb> <a_prefetch>
 //         <b_variant> <c_variant> <a_variant> <nt_hint> <b_xtile> <b_threads> <12 radix entries>
+//         [<c_split>]
+// (lines without c_split, written before it existed, read it as 0)
 // where <device> is the architecture and CU count ("gfx950/256"): a tuned
 // launch shape holds for that kind of device only.  Lines starting with '#'
 // are comments; lines for other devices are kept when the file is rewritten.
@@ -87,13 +91,14 @@ static std::string config_line(const std::string& tag, const std::array<int, 5>&
   for (int v : f) s += " " + std::to_string(v);
   for (int a = 0; a < 3; ++a)
     for (int r = 0; r < 4; ++r) s += " " + std::to_string(c.radix[a][r]);
+  s += " " + std::to_string(c.c_split);
   return s;
 }
 
 // Parse one line; false if it is not a configuration line.
 static bool parse_config_line(const char* line, std::string* tag, std::array<int, 5>* k, fx_vx_config* c) {
   char tg[128];
-  int v[5 + 9 + 12];
+  int v[5 + 9 + 12 + 1];
   int used = 0;
   if (std::sscanf(line, "fxcfg %127s%n", tg, &used) != 1) return false;
   const char* p = line + used;
@@ -102,6 +107,8 @@ static bool parse_config_line(const char* line, std::string* tag, std::array<int
     if (std::sscanf(p, "%d%n", &v[i], &adv) != 1) return false;
     p += adv;
   }
+  int adv = 0;
+  if (std::sscanf(p, "%d%n", &v[26], &adv) != 1) v[26] = 0;
   *tag = tg;
   for (int i = 0; i < 5; ++i) (*k)[i] = v[i];
   int* f[9] = {&c->kernels, &c->work_mb, &c->a_prefetch, &c->b_variant, &c->c_variant, &c->a_variant, &c->nt_hint,
@@ -109,6 +116,7 @@ static bool parse_config_line(const char* line, std::string* tag, std::array<int
   for (int i = 0; i < 9; ++i) *f[i] = v[5 + i];
   for (int a = 0; a < 3; ++a)
     for (int r = 0; r < 4; ++r) c->radix[a][r] = v[14 + 4 * a + r];
+  c->c_split = v[26];
   return true;
 }
 
@@ -192,6 +200,7 @@ static fx_status time_candidate(fx_ctx* ctx, const VxArgs& base, const fx_vx_con
   a.c_var = c.c_variant;
   a.a_var = c.a_variant;
   a.nt_hint = c.nt_hint;
+  a.c_split = c.c_split;
   a.xtile = c.b_xtile;
   a.nthr_b = c.b_threads;
   bool any = false;
@@ -354,6 +363,13 @@ static fx_status autotune(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* ker
     if (rs == FX_OK) {
       fx_vx_config c = cur;
       c.nt_hint = 1 - cur.nt_hint;
+      rs = trial(c);
+    }
+    // sum groups of the plane-inverse pass (pays where targets are few)
+    const fx_vx_config sstart = cur;
+    for (int sp = 2; sp <= 8 && rs == FX_OK; sp *= 2) {
+      fx_vx_config c = sstart;
+      c.c_split = sp;
       rs = trial(c);
     }
   }

@@ -390,6 +390,47 @@ static int ct_c_variant(const VxArgs& a) {
 // plane once per XCD with the z split instead of once per XCD per chunk of
 // pairs (3.05 -> 2.82 ms per launch of 1170 pairs at 96^3); the plane-inverse
 // pass measured slower with it (3.13 -> 3.30 ms), so it keeps the unit split.
+// Sum groups of the specialised plane-inverse pass: the terms of orbital j
+// go to partial sum j mod S of their target, each in ascending j, and the S
+// partial sums are added in order of the group at the end.  With few targets
+// the pass has few items (targets x planes); S times as many balance the
+// CUs.  The grouping depends on the orbital index only, so a column's result
+// is the same whatever the batch size and whichever targets share a launch.
+// S = 1 (automatic) keeps one running sum per target; the allocation-free
+// form always does.
+static int ct_jsplit(const VxArgs& a) {
+  if (a.no_alloc) return 1;
+  return a.c_split == 2 || a.c_split == 4 || a.c_split == 8 ? a.c_split : 1;
+}
+
+// out[t] = sum over the groups g = 0, 1, ... of acc[g][t] (targets t0 ..
+// t0 + nt - 1), converted to the output type.
+template <typename A>
+__global__ void k_combine_groups(const cpx<A>* __restrict__ acc, int64_t gstride, int64_t ld_acc, int jsplit, int t0,
+                                 int nt, int64_t nr, void* __restrict__ out, int64_t ld_out, int out_c64) {
+  const int64_t total = (int64_t)nt * nr;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t t = t0 + i / nr, e = i % nr;
+    cpx<A> v = acc[t * ld_acc + e];
+    for (int g = 1; g < jsplit; ++g) v = cadd(v, acc[g * gstride + t * ld_acc + e]);
+    if (out_c64)
+      reinterpret_cast<cpx<float>*>(out)[t * ld_out + e] = cpx<float>{(float)v.x, (float)v.y};
+    else
+      reinterpret_cast<cpx<double>*>(out)[t * ld_out + e] = cpx<double>{(double)v.x, (double)v.y};
+  }
+}
+
+template <typename A>
+static fx_status combine_groups(fx_ctx* ctx, hipStream_t st, const cpx<A>* acc, int64_t gstride, int64_t ld_acc,
+                                int jsplit, int t0, int nt, int64_t nr, void* out, int64_t ld_out, int out_c64) {
+  const int64_t total = (int64_t)nt * nr;
+  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((total + 255) / 256, 8 * std::max(ctx->n_cu, 1)));
+  hipLaunchKernelGGL((k_combine_groups<A>), dim3(blocks), dim3(256), 0, st, acc, gstride, ld_acc, jsplit, t0, nt, nr,
+                     out, ld_out, out_c64);
+  FX_LAUNCH_CHECK();
+  return FX_OK;
+}
+
 static int ct_zsplit() {
   const char* e = getenv("FX_VX_ZSPLIT");
   return e ? atoi(e) : 1;
@@ -418,17 +459,19 @@ static fx_status run_halved(fx_ctx* ctx, Workspace* ws, const VxArgs& a, const G
   FX_TRY(ws_get(ctx, ws, "vx_work", (size_t)B * B * pair_bytes, &work));
   const bool out_c64 = a.out_dtype == FX_C64;
   const bool out_is_A = (sizeof(A) == 8) == !out_c64;
+  const int jsplit = ct_jsplit(a);
   // partial sums live between the two roles of every block pair
   cpx<A>* acc = nullptr;
-  int64_t ld_acc = 0;
-  if (out_is_A) {
+  int64_t ld_acc = 0, gstride = 0;
+  if (out_is_A && jsplit == 1) {
     acc = reinterpret_cast<cpx<A>*>(a.out);
     ld_acc = a.ld_out;
   } else {
     void* p = nullptr;
-    FX_TRY(ws_get(ctx, ws, "vx_acc", (size_t)N * nr * sizeof(cpx<A>), &p));
+    FX_TRY(ws_get(ctx, ws, "vx_acc", (size_t)jsplit * N * nr * sizeof(cpx<A>), &p));
     acc = reinterpret_cast<cpx<A>*>(p);
     ld_acc = nr;
+    gstride = (int64_t)N * nr;
   }
   const cpx<T>* tw = reinterpret_cast<const cpx<T>*>(tb->tw[0]);
   const T* kf = reinterpret_cast<const T*>(tb->kfold);
@@ -442,6 +485,7 @@ static fx_status run_halved(fx_ctx* ctx, Workspace* ws, const VxArgs& a, const G
       const int npairs = tri ? jb * (jb + 1) / 2 : jb * kb;
       CtBatch<T> cb{psi, ld_psi, psi, ld_psi, reinterpret_cast<cpx<T>*>(work), j0, jb, k0, kb, npairs, tw, kf,
                     tb->fold[0], tri, a.a_pipe > 0 ? 1 : 0, ct_b_variant(a), ct_c_variant(a), (a.a_var == 2 || a.a_var == 3) ? a.a_var : 1, a.nt_hint != 0 ? 1 : 0, ct_zsplit()};
+      cb.jsplit = jsplit;
       const double vol = (double)npairs * nr * sz;
       int slot;
       FX_TRY(prof_begin(ctx, st, FX_K_VX_PLANE_FWD, 2.0 * vol, &slot));
@@ -453,18 +497,18 @@ static fx_status run_halved(fx_ctx* ctx, Workspace* ws, const VxArgs& a, const G
       // role 0: targets of block K; the first contribution to them is J = 0
       {
         const int first = J == 0;
-        CtAcc<A> ca{acc, ld_acc, first, a.out, a.ld_out, out_c64 ? 1 : 0, 0, -1};
-        const double accb = (double)kb * nr * ((first ? 0.0 : asz) + asz);
+        CtAcc<A> ca{acc, ld_acc, first, a.out, a.ld_out, out_c64 ? 1 : 0, 0, -1, gstride};
+        const double accb = (double)kb * nr * ((first ? 0.0 : asz) + asz) * jsplit;
         FX_TRY(prof_begin(ctx, st, FX_K_VX_PLANE_INV, 2.0 * vol + accb, &slot));
         FX_TRY((ct_pass_c<T, A>(ctx, st, n, cb, ca, 0)));
         FX_TRY(prof_end(ctx, st, slot));
       }
       // role 1: targets of block J; their last contribution is K = nblk - 1
       {
-        const int last = K == nblk - 1;
-        CtAcc<A> ca{acc, ld_acc, 0, a.out, a.ld_out, out_c64 ? 1 : 0, last, -1};
+        const int last = K == nblk - 1 && jsplit == 1;
+        CtAcc<A> ca{acc, ld_acc, 0, a.out, a.ld_out, out_c64 ? 1 : 0, last, -1, gstride};
         const double planes = tri ? (double)(npairs - jb) : (double)npairs;
-        const double accb = (double)jb * nr * (asz + (last ? osz : asz));
+        const double accb = (double)jb * nr * (asz + (last ? osz : asz)) * jsplit;
         FX_TRY(prof_begin(ctx, st, FX_K_VX_PLANE_INV, 2.0 * planes * nr * sz + accb, &slot));
         FX_TRY((ct_pass_c<T, A>(ctx, st, n, cb, ca, 1)));
         FX_TRY(prof_end(ctx, st, slot));
@@ -472,6 +516,13 @@ static fx_status run_halved(fx_ctx* ctx, Workspace* ws, const VxArgs& a, const G
       launches += 4;
       solves += npairs;
     }
+  }
+  if (jsplit > 1) {
+    int slot;
+    FX_TRY(prof_begin(ctx, st, FX_K_REDUCE, (double)N * nr * (jsplit * asz + osz), &slot));
+    FX_TRY(combine_groups<A>(ctx, st, acc, gstride, ld_acc, jsplit, 0, N, nr, a.out, a.ld_out, out_c64 ? 1 : 0));
+    FX_TRY(prof_end(ctx, st, slot));
+    ++launches;
   }
   if (stats) {
     stats->nk = B;
@@ -522,9 +573,17 @@ static fx_status run_batches(fx_ctx* ctx, Workspace* ws, const VxArgs& a, const 
   const bool out_c64 = a.out_dtype == FX_C64;
   const bool out_is_A = (sizeof(A) == 8) == !out_c64;
   const bool multi_j = nj < a.n_psi;
+  const int jsplit = use_ct ? ct_jsplit(a) : 1;
   cpx<A>* acc = nullptr;
-  int64_t ld_acc = 0;
-  if (multi_j) {
+  int64_t ld_acc = 0, gstride = 0;
+  if (jsplit > 1) {
+    // the groups' partial sums, added into out after the last batch
+    void* p = nullptr;
+    FX_TRY(ws_get(ctx, ws, "vx_acc", (size_t)jsplit * a.n_phi * nr * sizeof(cpx<A>), &p));
+    acc = reinterpret_cast<cpx<A>*>(p);
+    ld_acc = nr;
+    gstride = (int64_t)a.n_phi * nr;
+  } else if (multi_j) {
     if (out_is_A) {
       acc = reinterpret_cast<cpx<A>*>(a.out);
       ld_acc = a.ld_out;
@@ -572,8 +631,8 @@ static fx_status run_batches(fx_ctx* ctx, Workspace* ws, const VxArgs& a, const 
       int slot;
       if (use_ct) {
         CtBatch<T> cb{psi, ld_psi, phi, ld_phi, reinterpret_cast<cpx<T>*>(work), j0, jb, k0, kb, npairs, twx, kf,
-                      tb->fold[0], 0, a.a_pipe > 0 ? 1 : 0, ct_b_variant(a), ct_c_variant(a), (a.a_var == 2 || a.a_var == 3) ? a.a_var : 1, a.nt_hint != 0 ? 1 : 0, ct_zsplit(), a.segs};
-        CtAcc<A> ca{acc, ld_acc, first, a.out, a.ld_out, out_c64 ? 1 : 0, last, a.pipe};
+                      tb->fold[0], 0, a.a_pipe > 0 ? 1 : 0, ct_b_variant(a), ct_c_variant(a), (a.a_var == 2 || a.a_var == 3) ? a.a_var : 1, a.nt_hint != 0 ? 1 : 0, ct_zsplit(), a.segs, jsplit};
+        CtAcc<A> ca{acc, ld_acc, first, a.out, a.ld_out, out_c64 ? 1 : 0, jsplit > 1 ? 0 : last, a.pipe, gstride};
         FX_TRY(prof_begin(ctx, st, FX_K_VX_PLANE_FWD, 2.0 * vol, &slot));
         FX_TRY(ct_pass_a<T>(ctx, st, g.nx, cb));
         FX_TRY(prof_end(ctx, st, slot));
@@ -584,6 +643,14 @@ static fx_status run_batches(fx_ctx* ctx, Workspace* ws, const VxArgs& a, const 
         FX_TRY((ct_pass_c<T, A>(ctx, st, g.nx, cb, ca, 0)));
         FX_TRY(prof_end(ctx, st, slot));
         launches += 3;
+        if (jsplit > 1 && last) {
+          const double osz = out_c64 ? 8.0 : 16.0;
+          FX_TRY(prof_begin(ctx, st, FX_K_REDUCE, (double)kb * nr * (jsplit * sizeof(cpx<A>) + osz), &slot));
+          FX_TRY(combine_groups<A>(ctx, st, acc, gstride, ld_acc, jsplit, k0, kb, nr, a.out, a.ld_out,
+                                   out_c64 ? 1 : 0));
+          FX_TRY(prof_end(ctx, st, slot));
+          ++launches;
+        }
         continue;
       }
       FX_TRY(prof_begin(ctx, st, FX_K_VX_PLANE_FWD, 2.0 * vol, &slot));
@@ -713,6 +780,7 @@ void resolve_vx_config(fx_ctx* ctx, VxArgs* a) {
   if (const char* e = getenv("FX_VX_C_VAR")) a->c_var = atoi(e);
   if (const char* e = getenv("FX_VX_A_VAR")) a->a_var = atoi(e);
   if (const char* e = getenv("FX_VX_NT")) a->nt_hint = atoi(e);
+  if (const char* e = getenv("FX_VX_C_SPLIT")) a->c_split = atoi(e);
   if (getenv("FX_VX_GENERIC")) a->kernels = 2;
   if (const char* e = getenv("FX_WORK_MB")) a->work_cap = (size_t)atol(e) << 20;
   if (!ctx) return;
@@ -726,6 +794,7 @@ void resolve_vx_config(fx_ctx* ctx, VxArgs* a) {
   if (!a->c_var) a->c_var = c.c_variant;
   if (!a->a_var) a->a_var = c.a_variant;
   if (a->nt_hint < 0 && c.nt_hint >= 0) a->nt_hint = c.nt_hint;
+  if (!a->c_split) a->c_split = c.c_split;
   if (!a->xtile) a->xtile = c.b_xtile;
   if (!a->nthr_b) a->nthr_b = c.b_threads;
   if (!a->plans_set) {

@@ -60,6 +60,7 @@ struct VxArgs {
   int a_var = 0;    // specialised plane-forward threads: 1 default, 2 second count, 3 that with the
                     // wave-level x transform (FP32 at 72 and 96), 0 automatic
   int nt_hint = -1;  // specialised kernels: non-temporal hints on the pair volume (1, 0, -1 automatic = 1)
+  int c_split = 0;   // specialised plane-inverse pass: j-sum groups (1, 2, 4 or 8; 0 automatic = 1)
   bool plans_set = false;  // generic kernels: radix schedules in `plans`
   PlanSet plans;
   // several trajectories' orbital blocks (specialised kernels, phi != psi);
@@ -112,7 +113,11 @@ struct CtBatch {
   int nts;          // the pair volume is read and written with non-temporal hints
   int zsplit = 0;   // plane passes split over the XCDs by z (bit 0: forward, bit 1: inverse) or by unit
   TrajSegs segs;    // per-target orbital blocks (multi-trajectory launches; n == 0: psi for all)
+  int jsplit = 1;   // plane-inverse pass: terms of orbital j go to sum group j mod jsplit
 };
+// Partial sums of the plane-inverse pass.  With jsplit groups, group g of
+// target t lives at acc + g * gstride + t * ld_acc and `last` is never set:
+// the groups are added afterwards (vx_combine_groups).
 template <typename A>
 struct CtAcc {
   cpx<A>* acc;
@@ -121,6 +126,7 @@ struct CtAcc {
   void* out;
   int64_t ld_out;
   int out_c64, last, pipe;
+  int64_t gstride = 0;
 };
 bool ct_supported(const fx_cell* cell);
 template <typename T>

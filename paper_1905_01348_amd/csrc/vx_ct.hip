@@ -395,7 +395,7 @@ __global__ void __launch_bounds__(NT) k_pass_c_ct(const cpx<T>* __restrict__ mul
                                                                   int tri, int m0, int t0, int nitems, cpx<A>* acc,
                                                                   int64_t ld_acc, int first, void* out, int64_t ld_out,
                                                                   int out_c64, int last, const cpx<T>* __restrict__ twg,
-                                                                  int zsplit, TrajSegs segs) {
+                                                                  int zsplit, TrajSegs segs, int jsplit, int64_t gstride) {
   constexpr int NXY = N * N, SX = N + 1, EPT = CeilDiv<NXY, NT>::value;
   constexpr size_t NR = (size_t)NXY * N;
   constexpr bool STG = FORM == 1, WX = FORM == 2;
@@ -406,11 +406,15 @@ __global__ void __launch_bounds__(NT) k_pass_c_ct(const cpx<T>* __restrict__ mul
   const int tid = threadIdx.x;
   for (int i = tid; i < N; i += NT) tw[i] = twg[i];
   __syncthreads();
+  // units: (target tt, sum group g) as tt * jsplit + g
   const ItemMap im = item_map<N>(nitems / N, zsplit);
-  // terms l in [lo, hi) of target tt
-  auto range = [&](int tt_, int* lo_, int* hi_) __attribute__((always_inline)) {
-    *lo_ = CONJ ? (tri ? tt_ + 1 : 0) : 0;
+  // terms l = lo, lo + jsplit, ... < hi of target tt in group g: the terms
+  // whose orbital m0 + l is g modulo jsplit, in ascending order
+  auto range = [&](int tt_, int g_, int* lo_, int* hi_) __attribute__((always_inline)) {
+    int lo = CONJ ? (tri ? tt_ + 1 : 0) : 0;
     *hi_ = CONJ ? nk : (tri ? tt_ + 1 : nj);
+    const int r = (m0 + lo) % jsplit;
+    *lo_ = lo + (g_ >= r ? g_ - r : g_ - r + jsplit);
   };
   auto plane_ptr = [&](int tt_, int l_, int z_) __attribute__((always_inline)) {
     const int pl = CONJ ? plane_of(tt_, l_, nj, tri) : plane_of(l_, tt_, nj, tri);
@@ -442,9 +446,11 @@ __global__ void __launch_bounds__(NT) k_pass_c_ct(const cpx<T>* __restrict__ mul
     return WX ? LX::wave_pos(tid, m) : LX::pos(tid, it, m);
   };
   for (int li = im.first; li < im.total; li += im.step) {
-    int tt, z;
-    im.at(li, &tt, &z);
+    int u, z;
+    im.at(li, &u, &z);
+    const int tt = u / jsplit, g = u - tt * jsplit;
     const int t = t0 + tt;
+    cpx<A>* accg = acc + g * gstride;  // this group's partial sums
     if constexpr (kRegX) {
       cpx<A> a[LX::IT][LX::R];
       cpx<T> vp[LX::IT][LX::R];
@@ -453,11 +459,11 @@ __global__ void __launch_bounds__(NT) k_pass_c_ct(const cpx<T>* __restrict__ mul
 #pragma unroll
         for (int m = 0; m < LX::R; ++m) {
           a[it][m] = cpx<A>{0, 0};
-          if (!first && LX::owns(tid, it)) a[it][m] = acc[t * ld_acc + (size_t)z * NXY + rpos(it, m)];
+          if (!first && LX::owns(tid, it)) a[it][m] = accg[t * ld_acc + (size_t)z * NXY + rpos(it, m)];
         }
       int lo, hi;
-      range(tt, &lo, &hi);
-      for (int l = lo; l < hi; ++l) {
+      range(tt, g, &lo, &hi);
+      for (int l = lo; l < hi; l += jsplit) {
         const cpx<T>* pm = seg_psi<T>(segs, mult, t) + (int64_t)(m0 + l) * ld_mult + (size_t)z * NXY;
         constexpr int R0 = Plan2<N>::R0, R1 = Plan2<N>::R1;
         // (16-byte paired loads here measured slower: 3.08 against 2.76 ms
@@ -502,7 +508,7 @@ __global__ void __launch_bounds__(NT) k_pass_c_ct(const cpx<T>* __restrict__ mul
             else
               reinterpret_cast<cpx<double>*>(out)[t * ld_out + off] = cpx<double>{(double)a[it][m].x, (double)a[it][m].y};
           } else {
-            acc[t * ld_acc + off] = a[it][m];
+            accg[t * ld_acc + off] = a[it][m];
           }
         }
       continue;
@@ -513,12 +519,12 @@ __global__ void __launch_bounds__(NT) k_pass_c_ct(const cpx<T>* __restrict__ mul
     for (int i = 0; i < EPT; ++i) {
       const int e = tid + i * NT;
       a[i] = cpx<A>{0, 0};
-      if (!first && (NXY % NT == 0 || e < NXY)) a[i] = acc[t * ld_acc + (size_t)z * NXY + e];
+      if (!first && (NXY % NT == 0 || e < NXY)) a[i] = accg[t * ld_acc + (size_t)z * NXY + e];
     }
     constexpr int R0 = Plan2<N>::R0, R1 = Plan2<N>::R1;
     int lo, hi;
-    range(tt, &lo, &hi);
-    for (int l = lo; l < hi; ++l) {
+    range(tt, g, &lo, &hi);
+    for (int l = lo; l < hi; l += jsplit) {
       // (multi-trajectory launches are never halved: role 0, target t's own orbitals)
       const cpx<T>* pm = seg_psi<T>(segs, mult, t) + (int64_t)(m0 + l) * ld_mult + (size_t)z * NXY;
       if (STG) {
@@ -537,13 +543,14 @@ __global__ void __launch_bounds__(NT) k_pass_c_ct(const cpx<T>* __restrict__ mul
         __builtin_amdgcn_sched_barrier(0);
         // start copying the next term: this item's, else the next item's first
         staged = false;
-        if (l + 1 < hi) {
-          plane_to_lds<T, N, NT, NTS>(plane_ptr(tt, l + 1, z), stg, tid);
+        if (l + jsplit < hi) {
+          plane_to_lds<T, N, NT, NTS>(plane_ptr(tt, l + jsplit, z), stg, tid);
           staged = true;
         } else if (li + im.step < im.total) {
-          int tt2, z2, lo2, hi2;
-          im.at(li + im.step, &tt2, &z2);
-          range(tt2, &lo2, &hi2);
+          int u2, z2, lo2, hi2;
+          im.at(li + im.step, &u2, &z2);
+          const int tt2 = u2 / jsplit;
+          range(tt2, u2 - tt2 * jsplit, &lo2, &hi2);
           if (lo2 < hi2) {
             plane_to_lds<T, N, NT, NTS>(plane_ptr(tt2, lo2, z2), stg, tid);
             staged = true;
@@ -615,7 +622,7 @@ __global__ void __launch_bounds__(NT) k_pass_c_ct(const cpx<T>* __restrict__ mul
         else
           reinterpret_cast<cpx<double>*>(out)[t * ld_out + off] = cpx<double>{(double)a[i].x, (double)a[i].y};
       } else {
-        acc[t * ld_acc + off] = a[i];
+        accg[t * ld_acc + off] = a[i];
       }
     }
   }
@@ -757,7 +764,7 @@ constexpr size_t pass_c_lds(bool stg) {
 template <typename T, typename A, int N, int NT, int FORM>
 static fx_status pass_c_shape(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b, const CtAcc<A>& c, int role) {
   const size_t lds = pass_c_lds<T, N>(FORM == 1);
-  const int items = (role ? b.nj : b.nk) * N;
+  const int items = (role ? b.nj : b.nk) * b.jsplit * N;
   auto kern = role ? (b.nts ? k_pass_c_ct<T, A, N, true, NT, true, FORM> : k_pass_c_ct<T, A, N, true, NT, false, FORM>)
                    : (b.nts ? k_pass_c_ct<T, A, N, false, NT, true, FORM> : k_pass_c_ct<T, A, N, false, NT, false, FORM>);
   int grid = 0;
@@ -765,11 +772,11 @@ static fx_status pass_c_shape(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b, 
   if (role)
     hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, st, b.phi, b.ld_phi, (const cpx<T>*)b.work, b.nj, b.nk, b.tri,
                        b.k0, b.j0, items, c.acc, c.ld_acc, c.first, c.out, c.ld_out, c.out_c64, c.last, b.tw, (b.zsplit >> 1) & 1,
-                       TrajSegs{});
+                       TrajSegs{}, b.jsplit, c.gstride);
   else
     hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, st, b.psi, b.ld_psi, (const cpx<T>*)b.work, b.nj, b.nk, b.tri,
                        b.j0, b.k0, items, c.acc, c.ld_acc, c.first, c.out, c.ld_out, c.out_c64, c.last, b.tw, (b.zsplit >> 1) & 1,
-                       b.segs);
+                       b.segs, b.jsplit, c.gstride);
   FX_LAUNCH_CHECK();
   return FX_OK;
 }

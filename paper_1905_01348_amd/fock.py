@@ -65,12 +65,13 @@ class FxVxConfig(C.Structure):
     _fields_ = [("kernels", C.c_int32), ("work_mb", C.c_int32), ("a_prefetch", C.c_int32),
                 ("b_variant", C.c_int32), ("c_variant", C.c_int32), ("a_variant", C.c_int32), ("nt_hint", C.c_int32),
                 ("b_xtile", C.c_int32), ("b_threads", C.c_int32),
-                ("radix", (C.c_int32 * 4) * 3)]
+                ("radix", (C.c_int32 * 4) * 3), ("c_split", C.c_int32)]
 
 
 def config_to_dict(c):
     return {"kernels": c.kernels, "work_mb": c.work_mb, "a_prefetch": c.a_prefetch, "b_variant": c.b_variant,
-            "c_variant": c.c_variant, "a_variant": c.a_variant, "nt_hint": c.nt_hint, "b_xtile": c.b_xtile, "b_threads": c.b_threads, "radix": [list(row) for row in c.radix]}
+            "c_variant": c.c_variant, "a_variant": c.a_variant, "nt_hint": c.nt_hint, "b_xtile": c.b_xtile,
+            "b_threads": c.b_threads, "radix": [list(row) for row in c.radix], "c_split": c.c_split}
 
 
 def config_from_dict(d):
@@ -78,7 +79,7 @@ def config_from_dict(d):
     c.a_prefetch = -1
     c.nt_hint = -1
     for k in ("kernels", "work_mb", "a_prefetch", "b_variant", "c_variant", "a_variant", "nt_hint", "b_xtile",
-              "b_threads"):
+              "b_threads", "c_split"):
         if k in d:
             setattr(c, k, int(d[k]))
     for a, row in enumerate(d.get("radix", [])):

@@ -48,7 +48,7 @@ def test_config_store_roundtrip_and_validation(ctx):
     ctx.set_vx_config(None, n=n, prec="fp64")
     assert not ctx.get_vx_config(n=n, prec="fp64")[1]
     bad = [
-        ({"kernels": 3}, n), ({"a_prefetch": 2}, n), ({"b_variant": 5}, n), ({"c_variant": 6}, n), ({"a_variant": -1}, n), ({"nt_hint": 2}, n), ({"b_xtile": 25}, n),
+        ({"kernels": 3}, n), ({"a_prefetch": 2}, n), ({"b_variant": 5}, n), ({"c_variant": 6}, n), ({"c_split": 3}, n), ({"a_variant": -1}, n), ({"nt_hint": 2}, n), ({"b_xtile": 25}, n),
         ({"b_threads": 100}, n), ({"b_threads": 512}, n), ({"radix": [[5, 5]]}, n), ({"radix": [[6, 2]]}, n),
         ({"kernels": 1}, (18, 16, 12)),  # no specialised kernels off the workload edges
         ({"kernels": 1, "radix": [[4, 6]]}, n),  # specialised kernels run the default schedule only
@@ -72,6 +72,7 @@ def test_specialised_variants_match(ctx, n):
     refs = {False: oracle.apply_vx(psi, phi, n, L, "hse", 0.106), True: oracle.apply_vx(psi, psi, n, L, "hse", 0.106)}
     shapes = [{"a_prefetch": 1}, {"b_variant": 2}, {"b_variant": 3}, {"b_variant": 4}, {"c_variant": 1}, {"c_variant": 2}, {"c_variant": 3}, {"c_variant": 4},
               {"c_variant": 5}, {"a_variant": 2}, {"a_variant": 3},
+              {"c_split": 2}, {"c_split": 4}, {"c_split": 8, "c_variant": 1},
               {"nt_hint": 1},
               {"a_prefetch": 1, "a_variant": 2, "b_variant": 2, "c_variant": 2}]
     close = {"fp64": 1e-13, "fp32acc64": 1e-6, "fp32": 1e-6}

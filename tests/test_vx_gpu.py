@@ -390,3 +390,40 @@ def test_fp32_inputs_off_16_byte_alignment(ctx, n):
             got = run(shift, pad)
             assert np.array_equal(got.view(np.float64), base.view(np.float64)), (av, shift, pad)
     ctx.set_vx_config(None, n=n, L=L, prec="fp32acc64")
+
+
+@pytest.mark.parametrize("n,square", [(48, False), (72, False), (24, True)])
+def test_sum_groups_fixed_order(ctx, n, square):
+    """With the plane-inverse j-sum split into groups by orbital index (c_split), every column
+    is bitwise the same for any batch size and whichever targets share the call (the grouping
+    depends on the orbital index only), it agrees with one running sum to rounding, and with
+    the oracle to the tolerance."""
+    L = n * 10.26 / 24
+    N, Nt = 7, 5
+    psi = synth.make_orbitals(130 + n, n, L, N)
+    phi = psi if square else synth.random_grid_vectors(131 + n, n, Nt)
+    nt = N if square else Nt
+    ref = oracle.apply_vx(psi, phi, n, L, "hse", 0.106)
+    P, Q = dev(psi), (None if square else dev(phi))
+    call = (lambda: ctx.apply_vx(P, n=n, L=L, prec="fp32acc64")) if square else \
+        (lambda q: ctx.apply_vx(P, q, n=n, L=L, prec="fp32acc64"))
+    ctx.set_vx_config({"kernels": 1}, n=n, L=L, prec="fp32acc64", phi_is_psi=square)
+    one = host(call() if square else call(Q))
+    ctx.set_vx_config({"kernels": 1, "c_split": 2}, n=n, L=L, prec="fp32acc64", phi_is_psi=square)
+    base = host(call() if square else call(Q))
+    assert rel_err(base, ref) <= TOL32
+    assert rel_err(base, one) <= 1e-6
+    bits = lambda x: x.view(np.float64)
+    for nj in ("1", "3"):
+        os.environ["FX_VX_NJ"] = nj
+        try:
+            got = host(call() if square else call(Q))
+        finally:
+            os.environ.pop("FX_VX_NJ", None)
+        say("edge", n, "c_split 2, orbitals per batch", nj)
+        assert np.array_equal(bits(got), bits(base)), nj
+    if not square:
+        for sub in ([1], [0, 3, 4]):
+            got = host(call(dev(phi[sub])))
+            assert np.array_equal(bits(got), bits(base[sub])), sub
+    ctx.set_vx_config(None, n=n, L=L, prec="fp32acc64", phi_is_psi=square)
