@@ -250,8 +250,9 @@ typedef struct fx_vx_config {
  * (n_psi orbitals, n_phi targets, phi_is_psi != 0 for the phi == psi form)
  * on synthetic data it allocates itself, by coordinate descent over the
  * fields above (kernel family; for the specialised kernels the prefetch form,
- * the z-pass tile, the plane-inverse and plane-forward threads and the cache
- * hints; for the generic kernels the radix schedule of each
+ * the z-pass tile, the plane-inverse and plane-forward threads and forms, the
+ * cache hints and the plane-inverse sum groups; for the generic kernels the
+ * radix schedule of each
  * axis, the z-pass tile and threads; then the batch volume), and stores the
  * fastest in the context, where every later fx_apply_vx, fx_build_ace and
  * served request of that grid, precision and form uses it.  Each candidate
