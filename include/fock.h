@@ -185,8 +185,9 @@ fx_status fx_apply_vx(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* kernel,
  *   FP32_ACC64, complex64 for FP32) so that partial sums live there.
  * - in_dtype must be the compute type (complex128 for FX_PREC_FP64, complex64
  *   for the FP32 forms): no conversion (FX_ERR_UNSUPPORTED otherwise).
- * - Each pair is solved as (j, k) even when phi == psi (no halving); the
- *   result agrees with fx_apply_vx to rounding.
+ * - Each pair is solved as (j, k) even when phi == psi (no halving), and the
+ *   j-sum of each target is one running sum (no sum groups, whatever the
+ *   configuration's c_split); the result agrees with fx_apply_vx to rounding.
  * - All calls on one device share its region and its contents persist from
  *   call to call; calls that overlap in time on one device (other streams,
  *   threads or contexts) race and must be serialised by the caller.

@@ -237,16 +237,20 @@ def test_workload_classes_oracle_sample():
     ctx.close()
 
 
-def test_same_grid_trajectories_share_a_launch():
+@pytest.mark.parametrize("c_split", [None, 4])
+def test_same_grid_trajectories_share_a_launch(c_split):
     """V_X requests of two trajectories on one grid (same cell, kernel, orbital count and precision)
     run as one launch, each target paired with its own trajectory's orbitals: one batch, results
-    bitwise equal to each request served alone and within 1e-5 of the oracle. ACE requests of the
-    two trajectories stay in separate launches."""
+    bitwise equal to each request served alone and within 1e-5 of the oracle, also with the
+    plane-inverse sums split into groups. ACE requests of the two trajectories stay in separate
+    launches."""
     import torch
     from paper_1905_01348_amd import Context, Server
 
     n3, L, N = (24, 24, 24), 10.26, 16
     ctx = Context(0)
+    if c_split:
+        ctx.set_vx_config({"kernels": 1, "c_split": c_split}, n=24, L=L, prec="fp32acc64")
     srv = Server(ctx, max_slots=1, n_streams=1, max_batch_pairs=1 << 16)
     psis = {}
     for t, seed in ((5, 501), (6, 502)):
