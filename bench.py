@@ -133,6 +133,9 @@ def main():
     ap.add_argument("--extra-warm-requests", type=int, default=300, help="warm-up requests of the extra serving replay")
     ap.add_argument("--serve-work-mb", type=int, default=0,
                     help="serve leg: pair work volume per V_X launch, MiB (0: the library's default)")
+    ap.add_argument("--serve-ace-prec", default="ace_fp16r", choices=["ace_fp64", "ace_fp32r", "ace_bf16r", "ace_fp16r"],
+                    help="serve leg: precision of the trajectories' ACE applies (FP16 with its residual step: "
+                         "1.3e-6 against FP64, and half the operand bytes of FP32's)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -753,7 +756,7 @@ def serve_leg(args, nreq_measured, nreq_warm, autotune):
             psi = torch.from_numpy(synth.make_orbitals(wl["seed"] + t, wl["n"], wl["L"], wl["N"],
                                                        dtype=np.complex64)).to("cuda:0")
             srv.register(tid, psi, n=wl["n"], L=wl["L"], kernel="hse", omega=0.106, vx_prec="fp32acc64",
-                         ace_prec="ace_fp32r")
+                         ace_prec=args.serve_ace_prec)
             del psi
             by_class.setdefault(c, []).append((tid, wl["N"]))
             log(f"[bench-serve] registered {name} traj {tid}")
@@ -796,7 +799,8 @@ def serve_leg(args, nreq_measured, nreq_warm, autotune):
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": "Poisson 200 req/s; 50/35/15% classes 24^3 N=16, 48^3 N=128, 72^3 N=432; "
                                "V_X or ACE on blocks of 8 orbitals; complex64; HSE",
-                   "register_s": t_reg, "vx_work_mb": args.serve_work_mb or "library default"},
+                   "register_s": t_reg, "vx_work_mb": args.serve_work_mb or "library default",
+                   "ace_prec": args.serve_ace_prec},
         "report": rep, "ok": ok, "offered_load": rep["busy_frac"], "by_class": breakdown,
     }
     srv.close()
