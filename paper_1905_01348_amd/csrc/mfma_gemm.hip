@@ -162,6 +162,66 @@ struct MfmaWaves {
   static constexpr int value = 2;
 };
 
+// Epilogue of the TN GEMM kernels: D tile element e of MFMA tile (i, j) of a
+// wave is row i*32 + 8*(e/4) + 4*(lane/32) + e%4, column j*32 + lane%32 of the
+// wave's 64x64 block.  MODE 0 writes FP64 partial sums; MODE 1 turns each
+// 32x32 tile around in the wave's own 32 x 33 doubles of `smem_raw` (the
+// caller's LDS, idle by then) and writes y = -alpha * D along r.
+template <bool REFINE, int MODE>
+__device__ inline void tn_epilogue(floatx16 (&acc)[2][2], floatx16 (&cor)[2][2], unsigned char* smem_raw, int lane,
+                                   int wave, int wm, int wn, int m0, int n0, int M, int N, int split,
+                                   double* __restrict__ partial, void* __restrict__ out, int64_t ldo, int out_c64,
+                                   double alpha, const double* __restrict__ colalpha) {
+  if (MODE == 0) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int n = n0 + wn * 64 + j * 32 + (lane & 31);
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const int m = m0 + wm * 64 + i * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+          if (m >= M || n >= N) continue;
+          partial[((int64_t)split * M + m) * N + n] = (double)acc[i][j][e] + (REFINE ? (double)cor[i][j][e] : 0.0);
+        }
+      }
+    return;
+  }
+  // MODE 1: the output runs along m (r) for each target, the tile along n:
+  // each wave turns its 32x32 tiles around in its own slice of the (now idle)
+  // LDS, then writes 32 consecutive r of one target per half-wave.
+  constexpr int SL = 33;  // padded row of the staged tile (doubles)
+  double* stg = reinterpret_cast<double*>(smem_raw) + wave * 32 * SL;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int ml = 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+        stg[ml * SL + (lane & 31)] = (double)acc[i][j][e] + (REFINE ? (double)cor[i][j][e] : 0.0);
+      }
+      wave_lds_sync();
+      const int ml = lane & 31;
+      const int m = m0 + wm * 64 + i * 32 + ml;
+#pragma unroll
+      for (int it = 0; it < 8; ++it) {
+        const int tl = (lane >> 5) + 2 * it;  // target within the tile's 16
+        const int n = n0 + wn * 64 + j * 32 + 2 * tl;
+        const double re = stg[ml * SL + 2 * tl], im = stg[ml * SL + 2 * tl + 1];
+        if (m < M && n < N) {
+          const int64_t idx = (int64_t)(n >> 1) * ldo + m;
+          const double al = colalpha ? colalpha[n >> 1] : alpha;
+          if (out_c64)
+            reinterpret_cast<float2*>(out)[idx] = make_float2((float)(-al * re), (float)(-al * im));
+          else
+            reinterpret_cast<double2*>(out)[idx] = make_double2(-al * re, -al * im);
+        }
+      }
+      wave_lds_sync();
+    }
+}
+
 template <typename S, bool REFINE, bool BDOUBLE, int MODE>
 __global__ void __launch_bounds__(256, (MfmaWaves<S>::value)) k_tn_mfma(int M, int N, int K, int kchunk, const S* __restrict__ Ap,
                                                  const S* __restrict__ Ar, int64_t lda, const S* __restrict__ Bp,
@@ -357,55 +417,179 @@ __global__ void __launch_bounds__(256, (MfmaWaves<S>::value)) k_tn_mfma(int M, i
     __syncthreads();
   }
 
-  // epilogue: D tile element e of (i, j): row = i*32 + 8*(e/4) + 4*(lane/32) + e%4, col = j*32 + lane%32
-  if (MODE == 0) {
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const int n = n0 + wn * 64 + j * 32 + (lane & 31);
-#pragma unroll
-        for (int e = 0; e < 16; ++e) {
-          const int m = m0 + wm * 64 + i * 32 + 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
-          if (m >= M || n >= N) continue;
-          partial[((int64_t)split * M + m) * N + n] = (double)acc[i][j][e] + (REFINE ? (double)cor[i][j][e] : 0.0);
-        }
-      }
-    return;
-  }
-  // MODE 1: the output runs along m (r) for each target, the tile along n:
-  // each wave turns its 32x32 tiles around in its own slice of the (now idle)
-  // LDS, then writes 32 consecutive r of one target per half-wave.
-  constexpr int SL = 33;  // padded row of the staged tile (doubles)
-  double* stg = reinterpret_cast<double*>(smem_raw) + wave * 32 * SL;
+  tn_epilogue<REFINE, MODE>(acc, cor, smem_raw, lane, wave, wm, wn, m0, n0, M, N, split, partial, out, ldo, out_c64,
+                            alpha, colalpha);
+}
+
+// ---------------------------------------------------------------------------
+// The same TN GEMM for the 2-byte operand types (BF16, FP16) with the operand
+// tiles loaded straight into LDS: 16-byte global_load_lds (no staging
+// registers, no LDS store instructions), two LDS buffers so that the next K
+// step's loads run while the current one is multiplied, one barrier per K
+// step.  K steps of DL_BK = 32 elements: a tile row is 64 bytes (4 chunks of
+// 8 elements), stored without padding; row r keeps global chunk g in slot
+// g ^ ((r >> 2) & 3), so that the 16-byte operand reads of 16 consecutive
+// rows (one pass of the LDS) fall on distinct banks.  With BDOUBLE only the
+// N/2 source rows are stored; an odd B row is its source row times -i, made
+// when the operand is read.  Same results as k_tn_mfma up to the order of
+// the k terms within a step.
+constexpr int DL_BK = 32;
+
+__device__ inline int dl_swz(int row) { return (row >> 2) & 3; }
+
+__device__ inline void dl_load16(const void* g, unsigned char* lds_wave_base) {
+  __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void*)lds_wave_base, 16, 0, 0);
+}
+
+template <typename S, bool BDOUBLE>
+struct DlShape {
+  static constexpr int ROWB = DL_BK * (int)sizeof(S);  // 64 bytes
+  static constexpr int AB = TBM * ROWB;                // one A operand tile
+  static constexpr int BROWS = BDOUBLE ? TBN / 2 : TBN;
+  static constexpr int BB = BROWS * ROWB;              // one B operand tile
+};
+template <typename S, bool REFINE, bool BDOUBLE>
+constexpr size_t dl_stage_bytes() {
+  return (size_t)(REFINE ? 2 : 1) * (DlShape<S, BDOUBLE>::AB + DlShape<S, BDOUBLE>::BB);
+}
+
+template <typename S, bool REFINE, bool BDOUBLE, int MODE>
+__global__ void __launch_bounds__(256, 2) k_tn_mfma_dl(int M, int N, int K, int kchunk, const S* __restrict__ Ap,
+                                                      const S* __restrict__ Ar, int64_t lda, const S* __restrict__ Bp,
+                                                      const S* __restrict__ Br, int64_t ldb, double* __restrict__ partial,
+                                                      void* __restrict__ out, int64_t ldo, int out_c64, double alpha,
+                                                      const double* __restrict__ colalpha, int tiles_m, int tiles_n) {
+  static_assert(sizeof(S) == 2, "2-byte operands");
+  using D = DlShape<S, BDOUBLE>;
+  constexpr int NOPS = REFINE ? 2 : 1;
+  constexpr int STAGE = (int)dl_stage_bytes<S, REFINE, BDOUBLE>();
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+
+  const int nblk = gridDim.x;
+  const int bid = blockIdx.x;
+  const int per_xcd = (nblk + 7) / 8;
+  int lid = (bid % 8) * per_xcd + bid / 8;
+  if (nblk % 8 != 0) lid = bid;
+  const int tn = lid % tiles_n;
+  const int rest = lid / tiles_n;
+  const int tm = rest % tiles_m;
+  const int split = rest / tiles_m;
+  const int m0 = tm * TBM, n0 = tn * TBN;
+  const int kbeg = split * kchunk;
+  const int kend = min(K, kbeg + kchunk);
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+
+  floatx16 acc[2][2], cor[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
+    for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
-        const int ml = 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
-        stg[ml * SL + (lane & 31)] = (double)acc[i][j][e] + (REFINE ? (double)cor[i][j][e] : 0.0);
+        acc[i][j][e] = 0.f;
+        cor[i][j][e] = 0.f;
       }
-      wave_lds_sync();
-      const int ml = lane & 31;
-      const int m = m0 + wm * 64 + i * 32 + ml;
+
+  // loads of the K step at k0 into buffer b: each wave-instruction fills 1 KB
+  // (16 rows); lane l lands in row l / 4, slot l % 4 of it.  Rows past the
+  // edge load a clamped, valid row: they only reach outputs that are not
+  // written.
+  const int lrow = lane >> 2, lslot = lane & 3;
+  auto issue = [&](int k0, int b) __attribute__((always_inline)) {
+    unsigned char* base = smem_raw + b * STAGE;
 #pragma unroll
-      for (int it = 0; it < 8; ++it) {
-        const int tl = (lane >> 5) + 2 * it;  // target within the tile's 16
-        const int n = n0 + wn * 64 + j * 32 + 2 * tl;
-        const double re = stg[ml * SL + 2 * tl], im = stg[ml * SL + 2 * tl + 1];
-        if (m < M && n < N) {
-          const int64_t idx = (int64_t)(n >> 1) * ldo + m;
-          const double al = colalpha ? colalpha[n >> 1] : alpha;
-          if (out_c64)
-            reinterpret_cast<float2*>(out)[idx] = make_float2((float)(-al * re), (float)(-al * im));
-          else
-            reinterpret_cast<double2*>(out)[idx] = make_double2(-al * re, -al * im);
+    for (int q = 0; q < TBM / 64; ++q) {
+      const int ch = wave + 4 * q, row = ch * 16 + lrow;
+      const int m = min(m0 + row, M - 1);
+      const int64_t off = (int64_t)m * lda + k0 + (lslot ^ dl_swz(row)) * 8;
+      dl_load16(Ap + off, base + ch * 1024);
+      if (REFINE) dl_load16(Ar + off, base + D::AB + ch * 1024);
+    }
+    const int nlim = BDOUBLE ? N / 2 : N;
+    const int nb = BDOUBLE ? n0 / 2 : n0;
+#pragma unroll
+    for (int q = 0; q < D::BROWS / 64; ++q) {
+      const int ch = wave + 4 * q, row = ch * 16 + lrow;
+      const int nn = min(nb + row, nlim - 1);
+      const int64_t off = (int64_t)nn * ldb + k0 + (lslot ^ dl_swz(row)) * 8;
+      dl_load16(Bp + off, base + NOPS * D::AB + ch * 1024);
+      if (REFINE) dl_load16(Br + off, base + NOPS * D::AB + D::BB + ch * 1024);
+    }
+  };
+  auto frag = [&](const unsigned char* t, int row, int g) __attribute__((always_inline)) {
+    return *reinterpret_cast<const uint4*>(t + row * D::ROWB + ((g ^ dl_swz(row)) << 4));
+  };
+  auto bfrag = [&](const unsigned char* t, int br, int g) __attribute__((always_inline)) {
+    if (!BDOUBLE) return frag(t, br, g);
+    const uint4 v = frag(t, br >> 1, g);
+    const uint4 w = times_minus_i(v, 2);
+    const bool odd = br & 1;
+    return uint4{odd ? w.x : v.x, odd ? w.y : v.y, odd ? w.z : v.z, odd ? w.w : v.w};
+  };
+
+  const int nsteps = (kend - kbeg) / DL_BK;
+  if (nsteps > 0) issue(kbeg, 0);
+  for (int st = 0; st < nsteps; ++st) {
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's loads of step st have landed
+    __syncthreads();                // ... every wave's; and step st - 1's reads are done
+    const unsigned char* base = smem_raw + (st & 1) * STAGE;
+    const unsigned char* tAp = base;
+    const unsigned char* tAr = base + D::AB;
+    const unsigned char* tBp = base + NOPS * D::AB;
+    const unsigned char* tBr = tBp + D::BB;
+    // every operand of the step is read before the next step's loads are
+    // issued: a read of LDS after those loads would wait for them
+    uint4 a[2][2], b[2][2], a2[2][2], b2[2][2];  // [kk][t]
+#pragma unroll
+    for (int kk = 0; kk < DL_BK / 16; ++kk) {
+      const int g = kk * 2 + (lane >> 5);
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int ar = wm * 64 + (lane & 31) + 32 * t;
+        const int br = wn * 64 + (lane & 31) + 32 * t;
+        a[kk][t] = frag(tAp, ar, g);
+        b[kk][t] = bfrag(tBp, br, g);
+        if (REFINE) {
+          a2[kk][t] = frag(tAr, ar, g);
+          b2[kk][t] = bfrag(tBr, br, g);
         }
       }
-      wave_lds_sync();
     }
+    __builtin_amdgcn_sched_barrier(0);
+    if (st + 1 < nsteps) issue(kbeg + (st + 1) * DL_BK, (st + 1) & 1);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int kk = 0; kk < DL_BK / 16; ++kk)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          if constexpr (std::is_same<S, _Float16>::value) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                __builtin_bit_cast(halfx8, a[kk][i]), __builtin_bit_cast(halfx8, b[kk][j]), acc[i][j], 0, 0, 0);
+            if (REFINE) {
+              cor[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                  __builtin_bit_cast(halfx8, a[kk][i]), __builtin_bit_cast(halfx8, b2[kk][j]), cor[i][j], 0, 0, 0);
+              cor[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                  __builtin_bit_cast(halfx8, a2[kk][i]), __builtin_bit_cast(halfx8, b[kk][j]), cor[i][j], 0, 0, 0);
+            }
+          } else {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                __builtin_bit_cast(bf16x8, a[kk][i]), __builtin_bit_cast(bf16x8, b[kk][j]), acc[i][j], 0, 0, 0);
+            if (REFINE) {
+              cor[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                  __builtin_bit_cast(bf16x8, a[kk][i]), __builtin_bit_cast(bf16x8, b2[kk][j]), cor[i][j], 0, 0, 0);
+              cor[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                  __builtin_bit_cast(bf16x8, a2[kk][i]), __builtin_bit_cast(bf16x8, b[kk][j]), cor[i][j], 0, 0, 0);
+            }
+          }
+        }
+  }
+  __syncthreads();  // the epilogue reuses the LDS
+  tn_epilogue<REFINE, MODE>(acc, cor, smem_raw, lane, wave, wm, wn, m0, n0, M, N, split, partial, out, ldo, out_c64,
+                            alpha, colalpha);
 }
 
 // ---- split kernels ----------------------------------------------------------
@@ -628,6 +812,18 @@ fx_status ace_prepare_split(fx_ace* a, fx_prec prec, hipStream_t st) {
   return FX_OK;
 }
 
+// Which GEMMs of the 2-byte forms run the direct-to-LDS kernel: the output
+// GEMM y = -xi C (measured faster: at 96^3, N = R = 1024, 34 -> 36% of the
+// BF16 matrix peak with the residual step, 25 -> 29% without), not C =
+// xi^H phi, whose -i rows made at read time cost more VALU work than the
+// staged kernel's LDS stores (35 -> 26%).  FX_ACE_DL = 0 uses neither, 2
+// both (for comparison).
+static bool ace_direct_lds(int mode) {
+  const char* e = getenv("FX_ACE_DL");
+  const int v = e ? atoi(e) : 1;
+  return v == 2 || (v == 1 && mode == 1);
+}
+
 template <typename S, bool REFINE>
 static fx_status apply_t(fx_ctx* ctx, Workspace* ws, fx_ace* a, AceSplit* sp, const void* phi, int R, int64_t ld_phi,
                          void* out, int64_t ld_out, fx_dtype in_dtype, fx_dtype out_dtype, hipStream_t st) {
@@ -688,9 +884,16 @@ static fx_status apply_t(fx_ctx* ctx, Workspace* ws, fx_ace* a, AceSplit* sp, co
     void* part = nullptr;
     FX_TRY(ws_get(ctx, ws, "mf_partial", sizeof(double) * (size_t)nsplit * n * 2 * R, &part));
     auto kern = k_tn_mfma<S, REFINE, true, 0>;
-    FX_TRY(allow_lds_mfma(kern, lds));
+    size_t lds_cn = lds;
+    if constexpr (sizeof(S) == 2) {
+      if (ace_direct_lds(0)) {
+        kern = k_tn_mfma_dl<S, REFINE, true, 0>;
+        lds_cn = 2 * dl_stage_bytes<S, REFINE, true>();
+      }
+    }
+    FX_TRY(allow_lds_mfma(kern, lds_cn));
     FX_TRY(prof_begin(ctx, st, FX_K_GEMM_CN, (REFINE ? 3.0 : 1.0) * 2.0 * n * 2.0 * R * (double)sp->kc, &slot));
-    hipLaunchKernelGGL(kern, dim3((unsigned)(tiles * nsplit)), dim3(256), lds, st, n, 2 * R, (int)sp->kc,
+    hipLaunchKernelGGL(kern, dim3((unsigned)(tiles * nsplit)), dim3(256), lds_cn, st, n, 2 * R, (int)sp->kc,
                        (int)kchunk, (const S*)sp->col_p, (const S*)sp->col_r, sp->kc, (const S*)php, (const S*)phr,
                        sp->kc, (double*)part, (void*)nullptr, (int64_t)0, 0, 0.0, (const double*)nullptr, tiles_m,
                        tiles_n);
@@ -728,7 +931,13 @@ static fx_status apply_t(fx_ctx* ctx, Workspace* ws, fx_ace* a, AceSplit* sp, co
     const int tm2 = (int)((nr + TBM - 1) / TBM), tn2 = (2 * R + TBN - 1) / TBN;
     auto kern2 = k_tn_mfma<S, REFINE, false, 1>;
     // the epilogue turns each wave's 32x32 tiles around in 32 x 33 doubles of LDS
-    const size_t lds2 = std::max(lds, (size_t)4 * 32 * 33 * sizeof(double));
+    size_t lds2 = std::max(lds, (size_t)4 * 32 * 33 * sizeof(double));
+    if constexpr (sizeof(S) == 2) {
+      if (ace_direct_lds(1)) {
+        kern2 = k_tn_mfma_dl<S, REFINE, false, 1>;
+        lds2 = std::max(2 * dl_stage_bytes<S, REFINE, false>(), (size_t)4 * 32 * 33 * sizeof(double));
+      }
+    }
     FX_TRY(allow_lds_mfma(kern2, lds2));
     FX_TRY(prof_begin(ctx, st, FX_K_GEMM_NN, (REFINE ? 3.0 : 1.0) * 2.0 * (double)nr * 2.0 * R * (double)sp->kn, &slot));
     hipLaunchKernelGGL(kern2, dim3((unsigned)(tm2 * tn2)), dim3(256), lds2, st, (int)nr, 2 * R, (int)sp->kn,
