@@ -389,6 +389,15 @@ __global__ void __launch_bounds__(NT) k_pass_b_pt(cpx<T>* __restrict__ work, con
 // accumulators leave LDS to spare).  At 96^3 it measured slightly slower than
 // the plain form (3.19 vs 3.13 ms per launch): a tuner candidate.  FORM 2
 // (WX): the inverse x transform across the lanes of a wave (RowStage).
+// FORM 2 at one butterfly per thread with two work planes in LDS: the terms
+// alternate between them, so a term's first stage need not wait for the
+// previous term's last reads (one barrier fewer per term).
+template <typename T, int N, int NT, int FORM>
+struct PassCDouble {
+  static constexpr bool value = FORM == 2 && sizeof(T) == 4 && RowStage<T, N, NT>::kWave &&
+                                (2 * N * (N + 1) + N) * sizeof(cpx<T>) <= 160 * 1024;
+};
+
 template <typename T, typename A, int N, bool CONJ, int NT, bool NTS, int FORM>
 __global__ void __launch_bounds__(NT) k_pass_c_ct(const cpx<T>* __restrict__ mult, int64_t ld_mult,
                                                                   const cpx<T>* __restrict__ work, int nj, int nk,
@@ -399,10 +408,12 @@ __global__ void __launch_bounds__(NT) k_pass_c_ct(const cpx<T>* __restrict__ mul
   constexpr int NXY = N * N, SX = N + 1, EPT = CeilDiv<NXY, NT>::value;
   constexpr size_t NR = (size_t)NXY * N;
   constexpr bool STG = FORM == 1, WX = FORM == 2;
+  constexpr bool kDbl = PassCDouble<T, N, NT, FORM>::value;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   cpx<T>* s = reinterpret_cast<cpx<T>*>(smem_raw);
-  cpx<T>* tw = s + N * SX;
+  cpx<T>* tw = s + (kDbl ? 2 : 1) * N * SX;
   cpx<T>* stg = tw + N;  // STG only: N*N staged work plane, 16-byte aligned
+  int par = 0;           // kDbl: the work plane of the current term
   const int tid = threadIdx.x;
   for (int i = tid; i < N; i += NT) tw[i] = twg[i];
   __syncthreads();
@@ -466,9 +477,10 @@ __global__ void __launch_bounds__(NT) k_pass_c_ct(const cpx<T>* __restrict__ mul
       for (int l = lo; l < hi; l += jsplit) {
         const cpx<T>* pm = seg_psi<T>(segs, mult, t) + (int64_t)(m0 + l) * ld_mult + (size_t)z * NXY;
         constexpr int R0 = Plan2<N>::R0, R1 = Plan2<N>::R1;
+        cpx<T>* sl = s + (kDbl ? par * N * SX : 0);
         // (16-byte paired loads here measured slower: 3.08 against 2.76 ms
         // per launch at 96^3, with a quarter of the threads idle in this stage)
-        ct_stage_io<R1, false, T, N, R1, N, SX, 1, NT, true, false, N, 1, NTS>(s, plane_ptr(tt, l, z), nullptr, tw,
+        ct_stage_io<R1, false, T, N, R1, N, SX, 1, NT, true, false, N, 1, NTS>(sl, plane_ptr(tt, l, z), nullptr, tw,
                                                                               tid);
         __syncthreads();
 #pragma unroll
@@ -476,15 +488,15 @@ __global__ void __launch_bounds__(NT) k_pass_c_ct(const cpx<T>* __restrict__ mul
 #pragma unroll
           for (int m = 0; m < LX::R; ++m)
             if (LX::owns(tid, it)) vp[it][m] = pm[rpos(it, m)];
-        ct_stage<R0, false, T, N, N, N, SX, 1, NT>(s, tw, tid);
+        ct_stage<R0, false, T, N, N, N, SX, 1, NT>(sl, tw, tid);
         __syncthreads();
         cpx<T> x[LX::IT][LX::R];
         if constexpr (WX) {
-          LX::template inv_x_wave<SX>(s, tw, tid, x[0]);
+          LX::template inv_x_wave<SX>(sl, tw, tid, x[0]);
         } else {
-          ct_stage<R1, false, T, N, R1, N, 1, SX, NT>(s, tw, tid);
+          ct_stage<R1, false, T, N, R1, N, 1, SX, NT>(sl, tw, tid);
           __syncthreads();
-          LX::template inv_from_lds<SX>(s, tw, tid, x);
+          LX::template inv_from_lds<SX>(sl, tw, tid, x);
         }
 #pragma unroll
         for (int it = 0; it < LX::IT; ++it)
@@ -494,7 +506,13 @@ __global__ void __launch_bounds__(NT) k_pass_c_ct(const cpx<T>* __restrict__ mul
               const cpx<A> va{(A)x[it][m].x, CONJ ? -(A)x[it][m].y : (A)x[it][m].y};
               a[it][m] = cfma(a[it][m], cpx<A>{(A)vp[it][m].x, (A)vp[it][m].y}, va);
             }
-        __syncthreads();  // the last stage's reads before the next term's writes of s
+        // the last stage's reads before the next term's writes of the plane:
+        // with two planes, the next term writes the other one, and the term
+        // after it waits at that term's barriers
+        if constexpr (kDbl)
+          par ^= 1;
+        else
+          __syncthreads();
       }
 #pragma unroll
       for (int it = 0; it < LX::IT; ++it)
@@ -763,7 +781,8 @@ constexpr size_t pass_c_lds(bool stg) {
 
 template <typename T, typename A, int N, int NT, int FORM>
 static fx_status pass_c_shape(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b, const CtAcc<A>& c, int role) {
-  const size_t lds = pass_c_lds<T, N>(FORM == 1);
+  const size_t lds = PassCDouble<T, N, NT, FORM>::value ? (2 * (size_t)N * (N + 1) + N) * sizeof(cpx<T>)
+                                                         : pass_c_lds<T, N>(FORM == 1);
   const int items = (role ? b.nj : b.nk) * b.jsplit * N;
   auto kern = role ? (b.nts ? k_pass_c_ct<T, A, N, true, NT, true, FORM> : k_pass_c_ct<T, A, N, true, NT, false, FORM>)
                    : (b.nts ? k_pass_c_ct<T, A, N, false, NT, true, FORM> : k_pass_c_ct<T, A, N, false, NT, false, FORM>);
