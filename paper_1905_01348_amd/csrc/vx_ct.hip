@@ -392,10 +392,15 @@ __global__ void __launch_bounds__(NT) k_pass_b_pt(cpx<T>* __restrict__ work, con
 // FORM 2 at one butterfly per thread with two work planes in LDS: the terms
 // alternate between them, so a term's first stage need not wait for the
 // previous term's last reads (one barrier fewer per term).
+// The FP32 plain form (FORM 0) does the same where two planes take at most
+// 40 KB (edges 24 and 48), so that as many workgroups share a CU as with one
+// (48^3 request: 0.333 -> 0.321 ms per launch).  In FP64 at 48^2 the larger
+// planes cost workgroups per CU (halved 48^3 apply 822k -> 711k pairs/s).
 template <typename T, int N, int NT, int FORM>
 struct PassCDouble {
-  static constexpr bool value = FORM == 2 && sizeof(T) == 4 && RowStage<T, N, NT>::kWave &&
-                                (2 * N * (N + 1) + N) * sizeof(cpx<T>) <= 160 * 1024;
+  static constexpr size_t kBytes = (2 * (size_t)N * (N + 1) + N) * sizeof(cpx<T>);
+  static constexpr bool value = sizeof(T) == 4 && ((FORM == 2 && RowStage<T, N, NT>::kWave && kBytes <= 160 * 1024) ||
+                                                   (FORM == 0 && kBytes <= 40 * 1024));
 };
 
 template <typename T, typename A, int N, bool CONJ, int NT, bool NTS, int FORM>
@@ -545,12 +550,13 @@ __global__ void __launch_bounds__(NT) k_pass_c_ct(const cpx<T>* __restrict__ mul
     for (int l = lo; l < hi; l += jsplit) {
       // (multi-trajectory launches are never halved: role 0, target t's own orbitals)
       const cpx<T>* pm = seg_psi<T>(segs, mult, t) + (int64_t)(m0 + l) * ld_mult + (size_t)z * NXY;
+      cpx<T>* sl = s + (kDbl ? par * N * SX : 0);
       if (STG) {
         if (!staged) plane_to_lds<T, N, NT, NTS>(plane_ptr(tt, l, z), stg, tid);
         __builtin_amdgcn_s_waitcnt(0);  // this wave's part of the copy has landed
         __syncthreads();                // ... and every other wave's
         // first inverse y stage from the staged plane
-        ct_stage_io<R1, false, T, N, R1, N, SX, 1, NT, true, false, N, 1, false>(s, stg, nullptr, tw, tid);
+        ct_stage_io<R1, false, T, N, R1, N, SX, 1, NT, true, false, N, 1, false>(sl, stg, nullptr, tw, tid);
         __syncthreads();  // stg is free again
         // orbital plane first: waiting for it must not wait for the copy below
 #pragma unroll
@@ -576,7 +582,7 @@ __global__ void __launch_bounds__(NT) k_pass_c_ct(const cpx<T>* __restrict__ mul
         }
       } else {
         // first inverse y stage straight from the work plane
-        ct_stage_io<R1, false, T, N, R1, N, SX, 1, NT, true, false, N, 1, NTS>(s, plane_ptr(tt, l, z), nullptr, tw,
+        ct_stage_io<R1, false, T, N, R1, N, SX, 1, NT, true, false, N, 1, NTS>(sl, plane_ptr(tt, l, z), nullptr, tw,
                                                                               tid);
         __syncthreads();
         if (!kLateOrbital) {
@@ -587,11 +593,11 @@ __global__ void __launch_bounds__(NT) k_pass_c_ct(const cpx<T>* __restrict__ mul
           }
         }
       }
-      ct_stage<R0, false, T, N, N, N, SX, 1, NT>(s, tw, tid);
+      ct_stage<R0, false, T, N, N, N, SX, 1, NT>(sl, tw, tid);
       __syncthreads();
       // inverse x: its two stages (ct_fft's), the orbital plane loaded between
       // them in FP64
-      ct_stage<R1, false, T, N, R1, N, 1, SX, NT>(s, tw, tid);
+      ct_stage<R1, false, T, N, R1, N, 1, SX, NT>(sl, tw, tid);
       __syncthreads();
       if (!STG && kLateOrbital) {
 #pragma unroll
@@ -600,7 +606,7 @@ __global__ void __launch_bounds__(NT) k_pass_c_ct(const cpx<T>* __restrict__ mul
           if (NXY % NT == 0 || e < NXY) vp[i] = pm[e];
         }
       }
-      ct_stage<R0, false, T, N, N, N, 1, SX, NT>(s, tw, tid);
+      ct_stage<R0, false, T, N, N, N, 1, SX, NT>(sl, tw, tid);
       __syncthreads();
 #pragma unroll
       for (int i = 0; i < EPT; ++i) {
@@ -615,7 +621,7 @@ __global__ void __launch_bounds__(NT) k_pass_c_ct(const cpx<T>* __restrict__ mul
           }
         }
         if (NXY % NT == 0 || e < NXY) {
-          const cpx<T> v = s[(e / N) * SX + e % N];
+          const cpx<T> v = sl[(e / N) * SX + e % N];
           const cpx<A> va{(A)v.x, CONJ ? -(A)v.y : (A)v.y};
           // FP32 transforms: four FMAs per term; FP64: product then sum (the
           // FMA chain costs the FP64 kernel registers it does not have)
@@ -626,8 +632,12 @@ __global__ void __launch_bounds__(NT) k_pass_c_ct(const cpx<T>* __restrict__ mul
         }
       }
       // (STG: the barrier at the top of the next term orders these reads
-      // before the next writes of s)
-      if (!STG) __syncthreads();
+      // before the next writes of s; kDbl: the next term writes the other
+      // plane)
+      if constexpr (kDbl)
+        par ^= 1;
+      else if (!STG)
+        __syncthreads();
     }
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
@@ -781,7 +791,7 @@ constexpr size_t pass_c_lds(bool stg) {
 
 template <typename T, typename A, int N, int NT, int FORM>
 static fx_status pass_c_shape(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b, const CtAcc<A>& c, int role) {
-  const size_t lds = PassCDouble<T, N, NT, FORM>::value ? (2 * (size_t)N * (N + 1) + N) * sizeof(cpx<T>)
+  const size_t lds = PassCDouble<T, N, NT, FORM>::value ? PassCDouble<T, N, NT, FORM>::kBytes
                                                          : pass_c_lds<T, N>(FORM == 1);
   const int items = (role ? b.nj : b.nk) * b.jsplit * N;
   auto kern = role ? (b.nts ? k_pass_c_ct<T, A, N, true, NT, true, FORM> : k_pass_c_ct<T, A, N, true, NT, false, FORM>)
