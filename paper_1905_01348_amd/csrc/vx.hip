@@ -431,9 +431,14 @@ static fx_status combine_groups(fx_ctx* ctx, hipStream_t st, const cpx<A>* acc, 
   return FX_OK;
 }
 
+// Work order of the specialised plane passes: bit 0 splits the plane-forward
+// pass over the XCDs by z, bit 1 the plane-inverse pass (slower: 2.76 against
+// 2.71 ms per launch at 96^3), bit 2 walks the plane-forward pass's pairs in
+// blocks of 8 orbitals x 8 targets (unit_plane).  Only the order changes,
+// never a result.
 static int ct_zsplit() {
   const char* e = getenv("FX_VX_ZSPLIT");
-  return e ? atoi(e) : 1;
+  return e ? atoi(e) : 5;
 }
 
 // Halved apply for phi == psi (all N targets): each unordered pair {j, k} is

@@ -34,6 +34,23 @@ FX_HD void pair_of(int p, int nj, int tri, int* jj, int* kk) {
 
 FX_HD int plane_of(int jj, int kk, int nj, int tri) { return tri ? kk * (kk + 1) / 2 + jj : kk * nj + jj; }
 
+// Work plane of traversal unit u of the plane-forward pass.  In the plain
+// order u is the plane itself.  In the blocked order (rectangular batches)
+// the units walk blocks of up to 8 orbitals x 8 targets, blocks target-minor
+// within each row of 8 orbitals, so that the workgroups of an XCD, which take
+// consecutive units at the same z, share 16 input planes at a time instead of
+// all the batch's orbital planes.
+FX_HD int unit_plane(int u, int units, int nj, int tri, bool blocked) {
+  if (tri || !blocked) return u;
+  constexpr int B = 8;
+  const int nk = units / nj;
+  const int jb = u / (B * nk), r = u - jb * B * nk;
+  const int bj = min(B, nj - jb * B);
+  const int kb = r / (B * bj), w = r - kb * B * bj;
+  const int jj = jb * B + w % bj, kk = kb * B + w / bj;
+  return kk * nj + jj;
+}
+
 // Work of a persistent plane kernel: `units` (pairs, or targets) x N planes.
 // Workgroups are dispatched round-robin over the XCDs, so with a grid that is
 // a multiple of the XCD count workgroup b runs on XCD b % kXcds.  Each XCD
@@ -109,7 +126,8 @@ __global__ void __launch_bounds__(NT, (PassAWaves<T, PIPE, NT>::value)) k_pass_a
   const int tid = threadIdx.x;
   for (int i = tid; i < N; i += NT) tw[i] = twg[i];
   cpx<T> va[EPT], vb[EPT];
-  const ItemMap im = item_map<N>(nitems / N, zsplit);
+  const ItemMap im = item_map<N>(nitems / N, zsplit & 1);
+  const bool kBlocked = (zsplit >> 2) & 1;
   // VEC with whole pairs of values per thread: each thread takes two
   // consecutive plane values per load (16-byte loads, half the load
   // instructions); value i of the thread is plane element elem(i)
@@ -121,6 +139,7 @@ __global__ void __launch_bounds__(NT, (PassAWaves<T, PIPE, NT>::value)) k_pass_a
     if (li >= im.total) return;
     int p, z;
     im.at(li, &p, &z);
+    p = unit_plane(p, nitems / N, nj, tri, kBlocked);
     int jj, kk;
     pair_of(p, nj, tri, &jj, &kk);
     const cpx<T>* a = seg_psi<T>(segs, psi, k0 + kk) + (int64_t)(j0 + jj) * ld_psi + (size_t)z * NXY;
@@ -155,6 +174,7 @@ __global__ void __launch_bounds__(NT, (PassAWaves<T, PIPE, NT>::value)) k_pass_a
     for (; li < im.total; li += im.step) {
       int p, z;
       im.at(li, &p, &z);
+      p = unit_plane(p, nitems / N, nj, tri, kBlocked);
       int jj, kk;
       pair_of(p, nj, tri, &jj, &kk);
       const cpx<T>* a = seg_psi<T>(segs, psi, k0 + kk) + (int64_t)(j0 + jj) * ld_psi + (size_t)z * NXY;
@@ -196,6 +216,7 @@ __global__ void __launch_bounds__(NT, (PassAWaves<T, PIPE, NT>::value)) k_pass_a
     __syncthreads();
     int p, z;
     im.at(li, &p, &z);
+    p = unit_plane(p, nitems / N, nj, tri, kBlocked);
     cpx<T>* o = work + p * NR + (size_t)z * NXY;
     // FP32 with one pair of columns per thread: 16-byte stores
     if constexpr (sizeof(T) == 4 && PairIO<R1, N, N, NT>::kFits)
@@ -714,7 +735,7 @@ static fx_status pass_a_shape(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b) 
   int grid = 0;
   FX_TRY(ct_prepare(ctx, kern, NT, lds, items, true, &grid));
   hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, st, b.psi, b.ld_psi, b.phi, b.ld_phi, b.work, b.j0, b.nj, b.k0,
-                     b.tri, items, b.tw, b.zsplit & 1, b.segs);
+                     b.tri, items, b.tw, b.zsplit & 5, b.segs);
   FX_LAUNCH_CHECK();
   return FX_OK;
 }
