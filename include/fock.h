@@ -228,8 +228,9 @@ typedef struct fx_vx_config {
                           0 automatic (5 at edges 96 and 72, else 1) */
   int32_t a_variant;   /* specialised plane-forward pass threads: 1 the edge's default,
                           2 a count that divides the butterflies evenly, 3: 2 with the
-                          product formed in a wave-level x transform (FP32 at edges 72
-                          and 96; elsewhere 2); 0 automatic (1) */
+                          product formed in a wave-level x transform (edges 72 and 96;
+                          elsewhere 2); 0 automatic (3 for FP64 at edges 72 and 96,
+                          else 1) */
   int32_t nt_hint;     /* specialised kernels: 1 read and write the pair volume with
                           non-temporal cache hints, 0 plain accesses, -1 automatic (1) */
   int32_t b_xtile;     /* generic z pass: x columns per workgroup */

@@ -375,11 +375,18 @@ struct RowStage {
     return f * N + bitrev3(l) + m * SPAN;
   }
   // the value of the lane whose DFT index is this lane's ^ H
+  // (a 64-bit value moves as its two 32-bit halves)
   template <int H>
   __device__ static T partner(T v) {
-    static_assert(sizeof(T) == 4, "32-bit lane exchange");
     constexpr int ctrl = H == 1 ? 0xB1 : (H == 2 ? 0x4E : 0x128);  // quad_perm [1,0,3,2], [2,3,0,1]; row_ror:8
-    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), ctrl, 0xF, 0xF, false));
+    if constexpr (sizeof(T) == 4) {
+      return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), ctrl, 0xF, 0xF, false));
+    } else {
+      const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+      const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)u, ctrl, 0xF, 0xF, false);
+      const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), ctrl, 0xF, 0xF, false);
+      return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+    }
   }
   // Radix-8 DFTs (sign S) across the 8 lanes of each row, one per value of
   // x, decimation in frequency: lane l holds input l of each DFT and ends with

@@ -320,7 +320,7 @@ static fx_status autotune(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* ker
   cur.a_prefetch = 0;
   cur.b_variant = spec ? (cell->n[0] == 96 ? 4 : (cell->n[0] == 72 ? 3 : 1)) : 0;
   cur.c_variant = spec ? (cell->n[0] == 96 || cell->n[0] == 72 ? 5 : 1) : 0;
-  cur.a_variant = spec ? 1 : 0;
+  cur.a_variant = spec ? (t64 && (cell->n[0] == 96 || cell->n[0] == 72) ? 3 : 1) : 0;
   cur.nt_hint = spec ? 1 : 0;
   rs = trial(cur);
   if (rs == FX_OK && best == std::numeric_limits<double>::infinity()) {
@@ -355,7 +355,9 @@ static fx_status autotune(fx_ctx* ctx, const fx_cell* cell, const fx_kernel* ker
       c.c_variant = cv;
       rs = trial(c);
     }
-    for (int av = 2; av <= 3 && rs == FX_OK; ++av) {
+    const int astart = cur.a_variant;
+    for (int av = 1; av <= 3 && rs == FX_OK; ++av) {
+      if (av == astart) continue;
       fx_vx_config c = cur;
       c.a_variant = av;
       rs = trial(c);

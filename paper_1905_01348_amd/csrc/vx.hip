@@ -489,7 +489,7 @@ static fx_status run_halved(fx_ctx* ctx, Workspace* ws, const VxArgs& a, const G
       const int tri = J == K;
       const int npairs = tri ? jb * (jb + 1) / 2 : jb * kb;
       CtBatch<T> cb{psi, ld_psi, psi, ld_psi, reinterpret_cast<cpx<T>*>(work), j0, jb, k0, kb, npairs, tw, kf,
-                    tb->fold[0], tri, a.a_pipe > 0 ? 1 : 0, ct_b_variant(a), ct_c_variant(a), (a.a_var == 2 || a.a_var == 3) ? a.a_var : 1, a.nt_hint != 0 ? 1 : 0, ct_zsplit()};
+                    tb->fold[0], tri, a.a_pipe > 0 ? 1 : 0, ct_b_variant(a), ct_c_variant(a), (a.a_var >= 1 && a.a_var <= 3) ? a.a_var : 0, a.nt_hint != 0 ? 1 : 0, ct_zsplit()};
       cb.jsplit = jsplit;
       const double vol = (double)npairs * nr * sz;
       int slot;
@@ -636,7 +636,7 @@ static fx_status run_batches(fx_ctx* ctx, Workspace* ws, const VxArgs& a, const 
       int slot;
       if (use_ct) {
         CtBatch<T> cb{psi, ld_psi, phi, ld_phi, reinterpret_cast<cpx<T>*>(work), j0, jb, k0, kb, npairs, twx, kf,
-                      tb->fold[0], 0, a.a_pipe > 0 ? 1 : 0, ct_b_variant(a), ct_c_variant(a), (a.a_var == 2 || a.a_var == 3) ? a.a_var : 1, a.nt_hint != 0 ? 1 : 0, ct_zsplit(), a.segs, jsplit};
+                      tb->fold[0], 0, a.a_pipe > 0 ? 1 : 0, ct_b_variant(a), ct_c_variant(a), (a.a_var >= 1 && a.a_var <= 3) ? a.a_var : 0, a.nt_hint != 0 ? 1 : 0, ct_zsplit(), a.segs, jsplit};
         CtAcc<A> ca{acc, ld_acc, first, a.out, a.ld_out, out_c64 ? 1 : 0, jsplit > 1 ? 0 : last, a.pipe, gstride};
         FX_TRY(prof_begin(ctx, st, FX_K_VX_PLANE_FWD, 2.0 * vol, &slot));
         FX_TRY(ct_pass_a<T>(ctx, st, g.nx, cb));

@@ -58,7 +58,7 @@ struct VxArgs {
   int c_var = 0;    // specialised plane-inverse form: 1 default, 2 second thread count, 3/4 those with the
                     // next plane staged in LDS, 0 automatic
   int a_var = 0;    // specialised plane-forward threads: 1 default, 2 second count, 3 that with the
-                    // wave-level x transform (FP32 at 72 and 96), 0 automatic
+                    // wave-level x transform (72 and 96), 0 automatic
   int nt_hint = -1;  // specialised kernels: non-temporal hints on the pair volume (1, 0, -1 automatic = 1)
   int c_split = 0;   // specialised plane-inverse pass: j-sum groups (1, 2, 4 or 8; 0 automatic = 1)
   bool plans_set = false;  // generic kernels: radix schedules in `plans`
@@ -109,9 +109,11 @@ struct CtBatch {
   int a_pipe;       // plane-forward pass: register prefetch of the next plane
   int b_var;        // z pass: 1 default x tile, 2 half tile, 3 whole x rows, 4 persistent (default tile)
   int c_var;        // plane-inverse pass: 1 default threads, 2 the second thread count, 3/4 staged
-  int a_var;        // plane-forward pass: 1 default threads, 2 the second thread count, 3 wave-level x
+  int a_var;        // plane-forward pass: 1 default threads, 2 the second thread count, 3 wave-level x,
+                    // 0 automatic (3 in FP64 where the wave-level form exists, else 1)
   int nts;          // the pair volume is read and written with non-temporal hints
-  int zsplit = 0;   // plane passes split over the XCDs by z (bit 0: forward, bit 1: inverse) or by unit
+  int zsplit = 0;   // plane passes split over the XCDs by z (bit 0: forward, bit 1: inverse) or by unit;
+                    // bit 2: the forward pass walks its pairs in 8 x 8 blocks (FP32)
   TrajSegs segs;    // per-target orbital blocks (multi-trajectory launches; n == 0: psi for all)
   int jsplit = 1;   // plane-inverse pass: terms of orbital j go to sum group j mod jsplit
 };

@@ -108,7 +108,7 @@ struct PassAWaves {
 };
 
 // WX: the product formed in the registers of a wave-level forward x
-// transform (RowStage::fwd_x_wave; FP32 at 72^2 and 96^2 with one row
+// transform (RowStage::fwd_x_wave; at 72^2 and 96^2 with one row
 // butterfly per thread), whose results go to LDS once for the y transform.
 // VEC: FP32 inputs 16-byte aligned with even leading dimensions (checked on
 // the host): each thread loads two consecutive plane values at a time.
@@ -169,7 +169,7 @@ __global__ void __launch_bounds__(NT, (PassAWaves<T, PIPE, NT>::value)) k_pass_a
   int li = im.first;
   if constexpr (WX) {
     using RS = RowStage<T, N, NT>;
-    static_assert(RS::kWave && sizeof(T) == 4 && !PIPE, "wave-level form: FP32, 72^2 or 96^2, one butterfly per thread");
+    static_assert(RS::kWave && !PIPE, "wave-level form: 72^2 or 96^2, one butterfly per thread");
     __syncthreads();  // twiddles
     for (; li < im.total; li += im.step) {
       int p, z;
@@ -722,6 +722,8 @@ static bool pass_a_vec_ok(const CtBatch<T>& b) {
 template <typename T, int N, int NT, bool WX = false>
 static fx_status pass_a_shape(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b) {
   const size_t lds = ((size_t)N * (N + 1) + N) * sizeof(cpx<T>);
+  // the blocked pair order (bit 2 of zsplit) in FP32 only: with one FP64
+  // workgroup per CU it measured slower (2.57 -> 2.67 ms per launch at 96^3)
   // the prefetching form exists for FP32 only (FP64 has no registers to spare)
   constexpr bool F32 = sizeof(T) == 4;
   const bool pipe = F32 && b.a_pipe && !WX;
@@ -735,7 +737,7 @@ static fx_status pass_a_shape(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b) 
   int grid = 0;
   FX_TRY(ct_prepare(ctx, kern, NT, lds, items, true, &grid));
   hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, st, b.psi, b.ld_psi, b.phi, b.ld_phi, b.work, b.j0, b.nj, b.k0,
-                     b.tri, items, b.tw, b.zsplit & 5, b.segs);
+                     b.tri, items, b.tw, b.zsplit & (sizeof(T) == 4 ? 5 : 1), b.segs);
   FX_LAUNCH_CHECK();
   return FX_OK;
 }
@@ -743,10 +745,15 @@ static fx_status pass_a_shape(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b) 
 template <typename T, int N>
 static fx_status pass_a_n(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b) {
   using S = CubeShape<N>;
-  // the wave-level form: FP32 at 72 and 96, with the second thread count
-  if constexpr (sizeof(T) == 4 && RowStage<T, N, S::NT_A2>::kWave)
-    if (b.a_var == 3) return pass_a_shape<T, N, S::NT_A2, true>(ctx, st, b);
-  if (b.a_var == 2 || b.a_var == 3) return pass_a_shape<T, N, S::NT_A2>(ctx, st, b);
+  constexpr bool kWx = RowStage<T, N, S::NT_A2>::kWave;
+  // automatic: the wave-level form in FP64 where it exists (one workgroup per
+  // CU, whose barriers it halves: 3.21 -> 2.57-2.66 ms per launch of 585 pairs
+  // at 96^3, 2.87 -> 2.75 at 72^3); FP32 keeps the default threads
+  const int av = b.a_var ? b.a_var : (sizeof(T) == 8 && kWx ? 3 : 1);
+  // the wave-level form: at 72 and 96, with the second thread count
+  if constexpr (kWx)
+    if (av == 3) return pass_a_shape<T, N, S::NT_A2, true>(ctx, st, b);
+  if (av == 2 || av == 3) return pass_a_shape<T, N, S::NT_A2>(ctx, st, b);
   return pass_a_shape<T, N, S::NT_P>(ctx, st, b);
 }
 
