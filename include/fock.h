@@ -224,7 +224,7 @@ typedef struct fx_vx_config {
                           while the current one is transformed (where two planes fit
                           the LDS: not FP64 at 72 and 96, which run 2 and 1 instead),
                           5: 2 with the inverse x transform across the lanes of a
-                          wave (FP32 at edges 72 and 96; elsewhere 2);
+                          wave (edges 72 and 96; elsewhere 2);
                           0 automatic (5 at edges 96 and 72, else 1) */
   int32_t a_variant;   /* specialised plane-forward pass threads: 1 the edge's default,
                           2 a count that divides the butterflies evenly, 3: 2 with the

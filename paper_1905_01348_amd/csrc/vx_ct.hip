@@ -474,10 +474,12 @@ __global__ void __launch_bounds__(NT) k_pass_c_ct(const cpx<T>* __restrict__ mul
   // the extra accumulators cost more registers than the saved LDS round trip
   // and barrier are worth.
   // WX: the whole inverse x transform in registers and across lanes
-  // (RowStage::inv_x_wave): one LDS pass and one barrier fewer again.
+  // (RowStage::inv_x_wave): one LDS pass and one barrier fewer again.  In
+  // FP64 this is the one register form (the orbital values loaded after the
+  // transform): 2.50 -> 2.38 ms per launch at 96^3, 2.43 -> 2.23 at 72^3.
   using LX = RowStage<T, N, NT>;
-  constexpr bool kRegX = sizeof(T) == 4 && !STG && LX::TOTAL == NT;
-  static_assert(!WX || (kRegX && LX::kWave), "wave-level form: FP32, 72^2 or 96^2, one butterfly per thread");
+  constexpr bool kRegX = (sizeof(T) == 4 || WX) && !STG && LX::TOTAL == NT;
+  static_assert(!WX || (kRegX && LX::kWave), "wave-level form: 72^2 or 96^2, one butterfly per thread");
   // plane position of value m of butterfly it of this thread in the register form
   auto rpos = [&](int it, int m) __attribute__((always_inline)) {
     return WX ? LX::wave_pos(tid, m) : LX::pos(tid, it, m);
@@ -509,11 +511,13 @@ __global__ void __launch_bounds__(NT) k_pass_c_ct(const cpx<T>* __restrict__ mul
         ct_stage_io<R1, false, T, N, R1, N, SX, 1, NT, true, false, N, 1, NTS>(sl, plane_ptr(tt, l, z), nullptr, tw,
                                                                               tid);
         __syncthreads();
+        if constexpr (!kLateOrbital) {
 #pragma unroll
-        for (int it = 0; it < LX::IT; ++it)
+          for (int it = 0; it < LX::IT; ++it)
 #pragma unroll
-          for (int m = 0; m < LX::R; ++m)
-            if (LX::owns(tid, it)) vp[it][m] = pm[rpos(it, m)];
+            for (int m = 0; m < LX::R; ++m)
+              if (LX::owns(tid, it)) vp[it][m] = pm[rpos(it, m)];
+        }
         ct_stage<R0, false, T, N, N, N, SX, 1, NT>(sl, tw, tid);
         __syncthreads();
         cpx<T> x[LX::IT][LX::R];
@@ -523,6 +527,15 @@ __global__ void __launch_bounds__(NT) k_pass_c_ct(const cpx<T>* __restrict__ mul
           ct_stage<R1, false, T, N, R1, N, 1, SX, NT>(sl, tw, tid);
           __syncthreads();
           LX::template inv_from_lds<SX>(sl, tw, tid, x);
+        }
+        // FP64 (wave-level form): the orbital values once the transform's
+        // registers are free
+        if constexpr (kLateOrbital) {
+#pragma unroll
+          for (int it = 0; it < LX::IT; ++it)
+#pragma unroll
+            for (int m = 0; m < LX::R; ++m)
+              if (LX::owns(tid, it)) vp[it][m] = pm[rpos(it, m)];
         }
 #pragma unroll
         for (int it = 0; it < LX::IT; ++it)
@@ -843,8 +856,8 @@ static fx_status pass_c_n(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b, cons
   using S = CubeShape<N>;
   // the staged forms where the second plane fits the LDS (not FP64 at 72 and 96)
   constexpr bool kStg = pass_c_lds<T, N>(true) <= kLdsPerCu;
-  // the wave-level form: FP32 at 72 and 96, with the larger thread count
-  constexpr bool kWx = sizeof(T) == 4 && RowStage<T, N, S::NT_C2>::kWave;
+  // the wave-level form: at 72 and 96, with the larger thread count
+  constexpr bool kWx = RowStage<T, N, S::NT_C2>::kWave;
   if constexpr (kWx)
     if (b.c_var == 5) return pass_c_shape<T, A, N, S::NT_C2, 2>(ctx, st, b, c, role);
   if (b.c_var == 3 && kStg) return pass_c_shape<T, A, N, S::NT_C2, kStg ? 1 : 0>(ctx, st, b, c, role);
