@@ -735,8 +735,9 @@ static bool pass_a_vec_ok(const CtBatch<T>& b) {
 template <typename T, int N, int NT, bool WX = false>
 static fx_status pass_a_shape(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b) {
   const size_t lds = ((size_t)N * (N + 1) + N) * sizeof(cpx<T>);
-  // the blocked pair order (bit 2 of zsplit) in FP32 only: with one FP64
-  // workgroup per CU it measured slower (2.57 -> 2.67 ms per launch at 96^3)
+  // the blocked pair order (bit 2 of zsplit) for the FP32 form with
+  // coalesced loads only: the wave-level forms measured slower with it
+  // (FP32 at 72^3: 0.734 -> 0.789 ms per launch; FP64 at 96^3: 2.57 -> 2.67)
   // the prefetching form exists for FP32 only (FP64 has no registers to spare)
   constexpr bool F32 = sizeof(T) == 4;
   const bool pipe = F32 && b.a_pipe && !WX;
@@ -750,7 +751,7 @@ static fx_status pass_a_shape(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b) 
   int grid = 0;
   FX_TRY(ct_prepare(ctx, kern, NT, lds, items, true, &grid));
   hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), lds, st, b.psi, b.ld_psi, b.phi, b.ld_phi, b.work, b.j0, b.nj, b.k0,
-                     b.tri, items, b.tw, b.zsplit & (sizeof(T) == 4 ? 5 : 1), b.segs);
+                     b.tri, items, b.tw, b.zsplit & (sizeof(T) == 4 && !WX ? 5 : 1), b.segs);
   FX_LAUNCH_CHECK();
   return FX_OK;
 }
