@@ -376,8 +376,8 @@ static int ct_b_variant(const VxArgs& a) {
 // accumulators per thread, more waves per CU) is the automatic choice at
 // 96^3, where it measured faster (3.34 vs 3.39 ms per launch of 1170 pairs),
 // and at 72^3 (15.1 vs 15.6 ms for 432 orbitals x 8 targets, with whole-row
-// z tiles), in its wave-level form (5; FP64 runs the plain form 2 there):
-// 2.75 vs 2.79 ms per launch at 96^3.  Elsewhere the autotuner decides.
+// z tiles), in its wave-level form (5): 2.75 vs 2.79 ms per launch at 96^3
+// in FP32, 2.38 vs 2.50 in FP64.  Elsewhere the autotuner decides.
 static int ct_c_variant(const VxArgs& a) {
   if (a.c_var >= 1 && a.c_var <= 5) return a.c_var;
   return a.cell->n[0] == 96 || a.cell->n[0] == 72 ? 5 : 1;
