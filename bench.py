@@ -30,7 +30,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 KSRC = ["paper_1905_01348_amd/csrc/vx.hip", "paper_1905_01348_amd/csrc/vx_passes.hpp",
         "paper_1905_01348_amd/csrc/fft.hpp", "paper_1905_01348_amd/csrc/vx_ct.hip",
-        "paper_1905_01348_amd/csrc/fft_ct.hpp"]
+        "paper_1905_01348_amd/csrc/fft_ct.hpp", "paper_1905_01348_amd/csrc/pair_order.hpp"]
 
 
 def _code_tokens(text):
