@@ -434,7 +434,7 @@ static fx_status combine_groups(fx_ctx* ctx, hipStream_t st, const cpx<A>* acc, 
 // Work order of the specialised plane passes: bit 0 splits the plane-forward
 // pass over the XCDs by z, bit 1 the plane-inverse pass (slower: 2.76 against
 // 2.71 ms per launch at 96^3), bit 2 walks the plane-forward pass's pairs in
-// blocks of 8 orbitals x 8 targets (unit_plane).  Only the order changes,
+// blocks of 4 orbitals x 16 targets (unit_plane).  Only the order changes,
 // never a result.
 static int ct_zsplit() {
   const char* e = getenv("FX_VX_ZSPLIT");

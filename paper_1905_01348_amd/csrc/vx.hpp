@@ -113,7 +113,7 @@ struct CtBatch {
                     // 0 automatic (3 in FP64 where the wave-level form exists, else 1)
   int nts;          // the pair volume is read and written with non-temporal hints
   int zsplit = 0;   // plane passes split over the XCDs by z (bit 0: forward, bit 1: inverse) or by unit;
-                    // bit 2: the forward pass walks its pairs in 8 x 8 blocks (FP32, not the
+                    // bit 2: the forward pass walks its pairs in 4 x 16 blocks (FP32, not the
                     // wave-level form)
   TrajSegs segs;    // per-target orbital blocks (multi-trajectory launches; n == 0: psi for all)
   int jsplit = 1;   // plane-inverse pass: terms of orbital j go to sum group j mod jsplit

@@ -1,8 +1,8 @@
 // The pair enumeration of the specialised plane passes on the CPU: pair_of
 // inverts plane_of for rectangular and diagonal (packed triangle) batches,
 // and unit_plane is a bijection of [0, units) in the plain and the blocked
-// order, the blocked order keeping each aligned run of 64 units within 8
-// orbitals and 8 targets where the batch is whole blocks.  Prints
+// order, the blocked order keeping each aligned run of 64 units within 4
+// orbitals and 16 targets where the batch is whole blocks.  Prints
 // "ok <cases>" on success.
 #include <cstdio>
 #include <vector>
@@ -41,8 +41,8 @@ int main() {
           if (p >= 0 && p < units) ++seen[p];
         }
         for (int p = 0; p < units; ++p) CHECK(seen[p] == 1, "plane %d of nj %d nk %d seen %d times", p, nj, nk, seen[p]);
-        if (blocked && nj % 8 == 0 && nk % 8 == 0) {
-          // whole blocks: each aligned run of 64 units is one block of 8 x 8
+        if (blocked && nj % 4 == 0 && nk % 16 == 0) {
+          // whole blocks: each aligned run of 64 units is one block of 4 x 16
           for (int u0 = 0; u0 < units; u0 += 64) {
             int jlo = nj, jhi = -1, klo = nk, khi = -1;
             for (int u = u0; u < u0 + 64 && u < units; ++u) {
@@ -53,7 +53,7 @@ int main() {
               klo = kk < klo ? kk : klo;
               khi = kk > khi ? kk : khi;
             }
-            CHECK(jhi - jlo == 7 && khi - klo == 7, "block at %d of nj %d nk %d spans %d x %d", u0, nj, nk,
+            CHECK(jhi - jlo == 3 && khi - klo == 15, "block at %d of nj %d nk %d spans %d x %d", u0, nj, nk,
                   jhi - jlo + 1, khi - klo + 1);
           }
         }

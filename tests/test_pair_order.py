@@ -3,7 +3,7 @@ on the CPU, built with g++ and the address and undefined-behaviour sanitizers: p
 plane_of for rectangular batches and for the packed triangle of a halved apply (up to 3000
 orbitals, where the float square root needs its integer correction), and the plane-forward
 pass's unit order is a bijection of the batch's planes, plain and blocked (in batches of
-whole blocks, each aligned run of 64 units is one block of 8 orbitals x 8 targets).  A wrong order would leave pair volumes unwritten; the GPU
+whole blocks, each aligned run of 64 units is one block of 4 orbitals x 16 targets).  A wrong order would leave pair volumes unwritten; the GPU
 parity tests would catch it only on the shapes they run."""
 import os
 import shutil
