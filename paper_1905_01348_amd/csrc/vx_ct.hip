@@ -702,7 +702,7 @@ static fx_status pass_a_shape(fx_ctx* ctx, hipStream_t st, const CtBatch<T>& b) 
   const size_t lds = ((size_t)N * (N + 1) + N) * sizeof(cpx<T>);
   // the blocked pair order (bit 2 of zsplit) for the FP32 form with
   // coalesced loads only: the wave-level forms measured slower with it
-  // (FP32 at 72^3: 0.734 -> 0.789 ms per launch; FP64 at 96^3: 2.57 -> 2.67)
+  // (FP32 at 72^3: 0.705 -> 0.800 ms per launch; FP64 at 96^3: 2.53 -> 2.66)
   // the prefetching form exists for FP32 only (FP64 has no registers to spare)
   constexpr bool F32 = sizeof(T) == 4;
   const bool pipe = F32 && b.a_pipe && !WX;
